@@ -1,0 +1,270 @@
+"""FP64 CPU oracle for the GRMHD stage (Phoebus paper, Sec. 2.1, Sec. 3.1, App. B).
+
+TEST INFRASTRUCTURE ONLY.  The plain C implementation under this directory is
+what the HIP library is checked against; it shares no code with it.  Only the
+test-suite, the smoke check and the CPU-baseline leg of the benchmark may load
+it.  Nothing in the product path imports this package.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCES = ["metric.c", "physics.c", "recon.c", "c2p.c", "stage.c", "api.c"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-std=c11", "-Wall"]
+
+
+def build(force=True):
+    """Compile liboracle.so with gcc (no fast-math, no FMA contraction)."""
+    if not force and os.path.exists(LIB_PATH):
+        return LIB_PATH
+    cmd = ["gcc"] + CFLAGS + ["-o", LIB_PATH + ".tmp"] + \
+        [os.path.join(_HERE, s) for s in SOURCES] + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("ng", ctypes.c_int),
+                ("xmin", ctypes.c_double * 3), ("dx", ctypes.c_double * 3),
+                ("bc", ctypes.c_int * 6), ("recon", ctypes.c_int),
+                ("riemann", ctypes.c_int), ("weno_fv", ctypes.c_int)]
+
+
+class Metric(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("M", ctypes.c_double), ("a", ctypes.c_double)]
+
+
+class Eos(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("rho_flr0", ctypes.c_double),
+                ("rho_flr_pow", ctypes.c_double), ("u_flr0", ctypes.c_double),
+                ("u_flr_pow", ctypes.c_double), ("W_max", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        _lib = ctypes.CDLL(LIB_PATH)
+        _lib.orc_pt_master.restype = ctypes.c_double
+    return _lib
+
+
+_P = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(a):
+    if not (a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
+        raise TypeError("oracle arrays must be C-contiguous float64")
+    return a.ctypes.data_as(_P)
+
+
+def metric_struct(kind, M=1.0, a=0.0):
+    return Metric(kind, M, a)
+
+
+# ----------------------------------------------------------------- point API
+
+def geom(metric, x):
+    out = np.zeros(56)
+    lib().orc_pt_geom(ctypes.byref(metric), _ptr(np.asarray(x, float)), _ptr(out))
+    return {"g": out[0:16].reshape(4, 4), "gi": out[16:32].reshape(4, 4),
+            "alpha": out[32], "beta": out[33:36], "gam": out[36:45].reshape(3, 3),
+            "gami": out[45:54].reshape(3, 3), "sqrtgam": out[54], "sqrtmg": out[55]}
+
+
+def derivs(metric, x):
+    dg = np.zeros((4, 4, 4)); Gam = np.zeros((4, 4, 4)); dla = np.zeros(4)
+    lib().orc_pt_derivs(ctypes.byref(metric), _ptr(np.asarray(x, float)), _ptr(dg),
+                        _ptr(Gam), _ptr(dla))
+    return dg, Gam, dla
+
+
+def p2c(metric, x, gam, prim):
+    U = np.zeros(8)
+    lib().orc_pt_p2c(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.c_double(gam),
+                     _ptr(np.asarray(prim, float)), _ptr(U))
+    return U
+
+
+def flux(metric, x, gam, prim, d):
+    F = np.zeros(8)
+    lib().orc_pt_flux(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.c_double(gam),
+                      _ptr(np.asarray(prim, float)), ctypes.c_int(d), _ptr(F))
+    return F
+
+
+def speeds(metric, x, gam, prim, d):
+    out = np.zeros(2)
+    lib().orc_pt_speeds(ctypes.byref(metric), _ptr(np.asarray(x, float)),
+                        ctypes.c_double(gam), _ptr(np.asarray(prim, float)), ctypes.c_int(d),
+                        _ptr(out))
+    return out[0], out[1]
+
+
+def riemann(metric, x, gam, solver, pl, pr, d):
+    F = np.zeros(8)
+    lib().orc_pt_riemann(ctypes.byref(metric), _ptr(np.asarray(x, float)),
+                         ctypes.c_double(gam), ctypes.c_int(solver),
+                         _ptr(np.asarray(pl, float)), _ptr(np.asarray(pr, float)),
+                         ctypes.c_int(d), _ptr(F))
+    return F
+
+
+def tmunu(metric, x, gam, prim):
+    T = np.zeros(16)
+    lib().orc_pt_tmunu(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.c_double(gam),
+                       _ptr(np.asarray(prim, float)), _ptr(T))
+    return T.reshape(4, 4)
+
+
+def c2p(metric, x, gam, Ud, B):
+    out = np.zeros(8)
+    mu = ctypes.c_double(0.0)
+    r = lib().orc_pt_c2p(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.c_double(gam),
+                         _ptr(np.asarray(Ud, float)), _ptr(np.asarray(B, float)), _ptr(out),
+                         ctypes.byref(mu))
+    return r, out, mu.value
+
+
+def master(gam, q, r2, b2, rb, mu):
+    return lib().orc_pt_master(ctypes.c_double(gam), ctypes.c_double(q), ctypes.c_double(r2),
+                               ctypes.c_double(b2), ctypes.c_double(rb), ctypes.c_double(mu))
+
+
+def recon(method, f, fv=0):
+    out = np.zeros(2)
+    lib().orc_pt_recon(ctypes.c_int(method), ctypes.c_int(fv), _ptr(np.ascontiguousarray(f, dtype=float)),
+                       _ptr(out))
+    return out[0], out[1]
+
+
+def weno(f, fv=0):
+    w = np.zeros(3)
+    s = ctypes.c_double(0.0)
+    lib().orc_pt_weno(ctypes.c_int(fv), _ptr(np.ascontiguousarray(f, dtype=float)), _ptr(w), ctypes.byref(s))
+    return w, s.value
+
+
+# ----------------------------------------------------------------- block API
+
+class Block:
+    """One meshblock of a problem description, evaluated by the oracle."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        g = Grid()
+        for d in range(3):
+            g.n[d] = prob.n[d]
+            g.xmin[d] = prob.xmin[d]
+            g.dx[d] = prob.dx[d]
+        g.ng = prob.ng
+        for s in range(6):
+            g.bc[s] = prob.bc[s]
+        g.recon = prob.recon
+        g.riemann = prob.riemann
+        g.weno_fv = prob.weno_fv
+        self.grid = g
+        self.metric = Metric(prob.metric_kind, prob.M, prob.a)
+        self.eos = Eos(prob.gamma, prob.rho_flr0, prob.rho_flr_pow, prob.u_flr0,
+                       prob.u_flr_pow, prob.W_max)
+        self.shape = prob.shape
+
+    def coord(self, loc, i, j, k):
+        x = np.zeros(3)
+        lib().orc_pt_coord(ctypes.byref(self.grid), ctypes.byref(self.metric), loc, i, j, k,
+                           _ptr(x))
+        return x
+
+    def fill_ghosts(self, P, Bf):
+        lib().orc_fill_ghosts(ctypes.byref(self.grid), ctypes.byref(self.metric), _ptr(P),
+                              _ptr(Bf))
+
+    def cell_B(self, Bf):
+        Bcc = np.zeros((3,) + self.shape)
+        lib().orc_cell_B(ctypes.byref(self.grid), ctypes.byref(self.metric), _ptr(Bf),
+                         _ptr(Bcc))
+        return Bcc
+
+    def prim_to_cons(self, P, Bf, U=None):
+        if U is None:
+            U = np.zeros((5,) + self.shape)
+        lib().orc_prim_to_cons_grid(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                                    ctypes.byref(self.eos), _ptr(P), _ptr(Bf), _ptr(U))
+        return U
+
+    def stage(self, P, Bf, U0, Bf0, U, dt, rk, nthreads=1, want_flux=False):
+        Uout = np.zeros_like(U)
+        Bfout = np.zeros_like(Bf)
+        F = np.zeros((3, 8) + self.shape) if want_flux else None
+        rkc = (ctypes.c_double * 3)(*rk)
+        r = lib().orc_stage(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                            ctypes.byref(self.eos), _ptr(P), _ptr(Bf), _ptr(U0), _ptr(Bf0),
+                            _ptr(U), ctypes.c_double(dt), rkc, _ptr(Uout), _ptr(Bfout),
+                            _ptr(F) if want_flux else None, ctypes.c_int(nthreads))
+        if r != 0:
+            raise RuntimeError("orc_stage failed")
+        return (Uout, Bfout, F) if want_flux else (Uout, Bfout)
+
+    def con2prim(self, U, Bf, P, nthreads=1):
+        flag = np.zeros(self.shape, dtype=np.int8)
+        nfail = lib().orc_con2prim(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                                   ctypes.byref(self.eos), _ptr(U), _ptr(Bf), _ptr(P),
+                                   flag.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
+                                   ctypes.c_int(nthreads))
+        return flag, nfail
+
+    def reductions(self, P, Bf, U, cfl):
+        out = np.zeros(8)
+        lib().orc_reductions(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                             ctypes.byref(self.eos), _ptr(P), _ptr(Bf), _ptr(U),
+                             ctypes.c_double(cfl), _ptr(out))
+        return {"dt": out[0], "divb_rel": out[1], "divb_max": out[2], "totals": out[3:8].copy()}
+
+
+class Sim:
+    """SSPRK2 driver over the oracle's stage (Shu-Osher form)."""
+
+    def __init__(self, prob, nthreads=1):
+        self.blk = Block(prob)
+        self.nthreads = nthreads
+        self.P = prob.P.copy()
+        self.Bf = prob.Bf.copy()
+        self.blk.fill_ghosts(self.P, self.Bf)
+        self.U = self.blk.prim_to_cons(self.P, self.Bf)
+        self.cfl = prob.cfl
+        self.t = 0.0
+
+    def dt(self):
+        return self.blk.reductions(self.P, self.Bf, self.U, self.cfl)["dt"]
+
+    def stage(self, dt, rk, U0, Bf0):
+        U, Bf = self.blk.stage(self.P, self.Bf, U0, Bf0, self.U, dt, rk, self.nthreads)
+        self.U, self.Bf = U, Bf
+        flag, nfail = self.blk.con2prim(self.U, self.Bf, self.P, self.nthreads)
+        self.blk.fill_ghosts(self.P, self.Bf)
+        return flag, nfail
+
+    def step(self, dt=None):
+        if dt is None:
+            dt = self.dt()
+        U0, Bf0 = self.U.copy(), self.Bf.copy()
+        self.stage(dt, (1.0, 0.0, 1.0), U0, Bf0)
+        self.stage(dt, (0.5, 0.5, 0.5), U0, Bf0)
+        self.t += dt
+        return dt
+
+
+def weno_beta(f):
+    b = np.zeros(3)
+    lib().orc_pt_beta(_ptr(np.ascontiguousarray(f, dtype=float)), _ptr(b))
+    return b

@@ -1,0 +1,135 @@
+/*
+ * Flat point-wise entry points of the oracle, for the pin tests.
+ * TEST INFRASTRUCTURE ONLY (see orc.h).
+ * Primitive vectors are packed as (rho, ut1, ut2, ut3, u, B1, B2, B3).
+ */
+#include <math.h>
+#include <string.h>
+#include "orc.h"
+
+static void unpack(const double p[8], orc_prim *q)
+{
+  q->rho = p[0];
+  for (int i = 0; i < 3; ++i) q->ut[i] = p[1 + i];
+  q->u = p[4];
+  for (int i = 0; i < 3; ++i) q->B[i] = p[5 + i];
+}
+
+/* out: g[16], gi[16], alpha, beta[3], gam[9], gami[9], sqrtgam, sqrtmg (56) */
+void orc_pt_geom(const orc_metric *m, const double x[3], double *out)
+{
+  orc_geom G;
+  orc_geom_at(m, x, &G);
+  int o = 0;
+  for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) out[o++] = G.g[a][b];
+  for (int a = 0; a < 4; ++a) for (int b = 0; b < 4; ++b) out[o++] = G.gi[a][b];
+  out[o++] = G.alpha;
+  for (int i = 0; i < 3; ++i) out[o++] = G.beta[i];
+  for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) out[o++] = G.gam[a][b];
+  for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) out[o++] = G.gami[a][b];
+  out[o++] = G.sqrtgam;
+  out[o++] = G.sqrtmg;
+}
+
+void orc_pt_derivs(const orc_metric *m, const double x[3], double *dg, double *Gam,
+                   double *dla)
+{
+  double a[4][4][4], b[4][4][4], c[4];
+  orc_metric_derivs(m, x, a, b, c);
+  memcpy(dg, a, sizeof a);
+  memcpy(Gam, b, sizeof b);
+  memcpy(dla, c, sizeof c);
+}
+
+void orc_pt_p2c(const orc_metric *m, const double x[3], double gam, const double p[8],
+                double U[8])
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  unpack(p, &q);
+  orc_prim_to_cons(&G, gam, &q, U);
+}
+
+void orc_pt_flux(const orc_metric *m, const double x[3], double gam, const double p[8],
+                 int dir, double F[8])
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  unpack(p, &q);
+  orc_flux(&G, gam, &q, dir, F);
+}
+
+void orc_pt_speeds(const orc_metric *m, const double x[3], double gam, const double p[8],
+                   int dir, double out[2])
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  unpack(p, &q);
+  orc_speeds(&G, gam, &q, dir, &out[0], &out[1]);
+}
+
+void orc_pt_riemann(const orc_metric *m, const double x[3], double gam, int solver,
+                    const double pl[8], const double pr[8], int dir, double flux[8])
+{
+  orc_geom G;
+  orc_prim L, R;
+  orc_geom_at(m, x, &G);
+  unpack(pl, &L);
+  unpack(pr, &R);
+  orc_riemann(&G, gam, solver, &L, &R, dir, flux);
+}
+
+void orc_pt_tmunu(const orc_metric *m, const double x[3], double gam, const double p[8],
+                  double T[16])
+{
+  orc_geom G;
+  orc_prim q;
+  double t[4][4];
+  orc_geom_at(m, x, &G);
+  unpack(p, &q);
+  orc_tmunu(&G, gam, &q, t);
+  memcpy(T, t, sizeof t);
+}
+
+int orc_pt_c2p(const orc_metric *m, const double x[3], double gam, const double Ud[5],
+               const double B[3], double pout[8], double *mu)
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  int r = orc_c2p_point(gam, &G, Ud, B, &q, mu);
+  if (r == 0) {
+    pout[0] = q.rho;
+    for (int i = 0; i < 3; ++i) pout[1 + i] = q.ut[i];
+    pout[4] = q.u;
+    for (int i = 0; i < 3; ++i) pout[5 + i] = q.B[i];
+  }
+  return r;
+}
+
+double orc_pt_master(double gam, double q, double r2, double b2, double rb, double mu)
+{
+  return orc_c2p_master(gam, q, r2, b2, rb, mu);
+}
+
+void orc_pt_recon(int method, int fv, const double f[5], double out[2])
+{
+  orc_recon1(method, fv, f, &out[0], &out[1]);
+}
+
+void orc_pt_weno(int fv, const double f[5], double w[3], double *sigma_side)
+{
+  orc_weno_weights(fv, f, w);
+  *sigma_side = orc_weno_sigma_side(fv, w);
+}
+
+void orc_pt_beta(const double f[5], double b[3]) { orc_weno_beta(f, b); }
+
+void orc_pt_coord(const orc_grid *g, const orc_metric *m, int loc, int i, int j, int k,
+                  double x[3])
+{
+  orc_coord(g, m, loc, i, j, k, x);
+}

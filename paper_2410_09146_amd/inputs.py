@@ -1,0 +1,561 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the benchmark.
+
+This module holds problem descriptions and initial conditions only: grid
+extents, boundary kinds, EOS and floor parameters, and primitive fields built
+from analytic solutions (linear waves, shock tubes, Michel inflow, the
+Fishbone-Moncrief torus) or seeded random draws.  It contains none of the
+finite-volume stage: no reconstruction, Riemann flux, constrained transport,
+source term or conserved-to-primitive inversion.  The torus and Michel
+generators evaluate the Kerr / Schwarzschild metric themselves only to lay
+down the initial fluid (their own short formulas); neither the oracle nor the
+HIP library calls into this module's arithmetic.
+
+Array conventions (both paths): cell-centred primitives ``P[5, s3, s2, s1]`` =
+(rho, W v^1, W v^2, W v^3, u = rho eps) with contravariant velocities, and
+face-centred densitized field ``Bf[3, s3, s2, s1]`` = sqrt(gamma) B^d on the
+lower d-face of each cell; s_d = n_d + 2 ng.
+"""
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# boundary kinds, reconstructions, Riemann solvers, metrics (ABI values)
+BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FIXED = 0, 1, 2, 3
+RECON_CONST, RECON_PLM_MC, RECON_WENO5Z, RECON_PLM_MINMOD = 0, 1, 2, 3
+RIEMANN_HLL, RIEMANN_LLF = 0, 1
+MINKOWSKI, KS_LOGSPH = 0, 1
+
+
+@dataclass
+class Problem:
+    n: tuple
+    xmin: tuple
+    xmax: tuple
+    bc: tuple
+    metric_kind: int = MINKOWSKI
+    M: float = 1.0
+    a: float = 0.0
+    gamma: float = 4.0 / 3.0
+    rho_flr0: float = 1e-20
+    rho_flr_pow: float = 0.0
+    u_flr0: float = 1e-22
+    u_flr_pow: float = 0.0
+    W_max: float = 50.0
+    recon: int = RECON_PLM_MC
+    riemann: int = RIEMANN_HLL
+    weno_fv: int = 0
+    cfl: float = 0.4
+    ng: int = 4
+    P: np.ndarray = None
+    Bf: np.ndarray = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dx(self):
+        return tuple((self.xmax[d] - self.xmin[d]) / self.n[d] for d in range(3))
+
+    @property
+    def shape(self):
+        return tuple(self.n[2 - d] + 2 * self.ng for d in range(3))   # (s3, s2, s1)
+
+    @property
+    def ncell(self):
+        s = self.shape
+        return s[0] * s[1] * s[2]
+
+    def centers(self, d):
+        """Cell-centre coordinate along d for every index (ghosts included)."""
+        idx = np.arange(self.n[d] + 2 * self.ng)
+        return self.xmin[d] + (idx - self.ng + 0.5) * self.dx[d]
+
+    def faces(self, d):
+        idx = np.arange(self.n[d] + 2 * self.ng)
+        return self.xmin[d] + (idx - self.ng) * self.dx[d]
+
+    def interior(self):
+        g = self.ng
+        return (slice(g, g + self.n[2]), slice(g, g + self.n[1]), slice(g, g + self.n[0]))
+
+
+def splitmix64(x):
+    """SplitMix64 output for uint64 array x (Steele, Lea & Flood 2014)."""
+    x = np.asarray(x, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform01(seed, idx):
+    """Uniform [0,1) doubles from SplitMix64(seed xor index), 53-bit mantissa."""
+    z = splitmix64(np.uint64(seed) ^ np.asarray(idx, dtype=np.uint64))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+# ---------------------------------------------------------------------------
+# Uniform state and random perturbations (unit tests)
+# ---------------------------------------------------------------------------
+
+def uniform_box(n, rho=1.0, ut=(0.0, 0.0, 0.0), u=1.0, B=(0.0, 0.0, 0.0), **kw):
+    prob = Problem(n=tuple(n), xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0),
+                   bc=(BC_PERIODIC,) * 6, **kw)
+    P = np.zeros((5,) + prob.shape)
+    P[0] = rho
+    for d in range(3):
+        P[1 + d] = ut[d]
+    P[4] = u
+    Bf = np.zeros((3,) + prob.shape)
+    for d in range(3):
+        Bf[d] = B[d]
+    prob.P, prob.Bf = P, Bf
+    return prob
+
+
+def random_smooth_box(n, seed=0, amp=0.05, B0=(0.3, 0.2, 0.1), **kw):
+    """Periodic box with a few seeded Fourier modes in every primitive and a
+    divergence-free face field from a periodic vector potential."""
+    prob = uniform_box(n, rho=1.0, u=1.0, **kw)
+    rng = np.random.default_rng(seed)
+    x = [prob.centers(d) for d in range(3)]
+    xf = [prob.faces(d) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    P = prob.P
+    for q, base in enumerate([1.0, 0.0, 0.0, 0.0, 1.0]):
+        f = np.full(X.shape, base)
+        for _ in range(3):
+            kv = rng.integers(-2, 3, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            f = f + amp * rng.uniform(0.5, 1.0) * np.cos(
+                2 * np.pi * (kv[0] * X + kv[1] * Y + kv[2] * Z) + ph)
+        P[q] = f
+    # A_d at d-edges; B = curl A
+    modes = [(rng.integers(-2, 3, size=3), rng.uniform(0, 2 * np.pi), rng.uniform(-1, 1, 3))
+             for _ in range(3)]
+
+    def A(comp, Xe, Ye, Ze):
+        out = np.zeros(Xe.shape)
+        for kv, ph, c in modes:
+            out += amp * c[comp] * np.sin(2 * np.pi * (kv[0] * Xe + kv[1] * Ye + kv[2] * Ze) + ph)
+        return out
+    prob.Bf = _curl_faces(prob, A, B0)
+    return prob
+
+
+def _curl_faces(prob, A, B0, sqrtg_face=None):
+    """Face field B^d = B0_d + (curl A)_d with A_c sampled at c-edges (Stokes
+    on each face, so the discrete divergence vanishes to rounding)."""
+    xc = [prob.centers(d) for d in range(3)]
+    xf = [prob.faces(d) for d in range(3)]
+    dx = prob.dx
+    Bf = np.zeros((3,) + prob.shape)
+
+    def grid(a, b, c):
+        Z, Y, X = np.meshgrid(c, b, a, indexing="ij")
+        return X, Y, Z
+
+    def up(a, d):
+        return a + dx[d]
+    # B1 on x1-faces (x1 face, x2 centre, x3 centre)
+    X, Y, Z = grid(xf[0], xc[1], xc[2])
+    Bf[0] = B0[0] + (A(2, X, Y + 0.5 * dx[1], Z) - A(2, X, Y - 0.5 * dx[1], Z)) / dx[1] \
+        - (A(1, X, Y, Z + 0.5 * dx[2]) - A(1, X, Y, Z - 0.5 * dx[2])) / dx[2]
+    X, Y, Z = grid(xc[0], xf[1], xc[2])
+    Bf[1] = B0[1] + (A(0, X, Y, Z + 0.5 * dx[2]) - A(0, X, Y, Z - 0.5 * dx[2])) / dx[2] \
+        - (A(2, X + 0.5 * dx[0], Y, Z) - A(2, X - 0.5 * dx[0], Y, Z)) / dx[0]
+    X, Y, Z = grid(xc[0], xc[1], xf[2])
+    Bf[2] = B0[2] + (A(1, X + 0.5 * dx[0], Y, Z) - A(1, X - 0.5 * dx[0], Y, Z)) / dx[0] \
+        - (A(0, X, Y + 0.5 * dx[1], Z) - A(0, X, Y - 0.5 * dx[1], Z)) / dx[1]
+    return Bf
+
+
+# ---------------------------------------------------------------------------
+# Linear magnetosonic wave in a periodic box (Minkowski)
+# ---------------------------------------------------------------------------
+
+def sr_wave_eigen(rho, p, gamma, B, nhat, mode="fast"):
+    """Right-going plane-wave eigenmode of linearised special-relativistic
+    ideal MHD about a static uniform state.
+
+    With enthalpy density w = rho + p gamma/(gamma-1), the velocity amplitude
+    solves  K dv = V^2 M dv  with
+        M = (w + B^2) I - B B^T
+        K = (gamma p + B^2) n n^T - (n.B)(n B^T + B n^T) + (n.B)^2 I,
+    obtained from linearising the conserved momentum (w + B^2) v - (B.v) B and
+    its flux with dp = gamma p (n.dv)/V, drho = rho (n.dv)/V and
+    dB = -[(n.B) dv - (n.dv) B]/V.  Returns (V, R) with R the primitive
+    eigenvector (rho, ut1, ut2, ut3, u, B1, B2, B3) scaled to unit 2-norm.
+    """
+    import scipy.linalg
+    n = np.asarray(nhat, float) / np.linalg.norm(nhat)
+    B = np.asarray(B, float)
+    w = rho + gamma * p / (gamma - 1.0)
+    nB = n @ B
+    M = (w + B @ B) * np.eye(3) - np.outer(B, B)
+    K = (gamma * p + B @ B) * np.outer(n, n) - nB * (np.outer(n, B) + np.outer(B, n)) \
+        + nB * nB * np.eye(3)
+    vals, vecs = scipy.linalg.eigh(K, M)
+    idx = {"slow": 0, "alfven": 1, "fast": 2}[mode]
+    V = np.sqrt(vals[idx])
+    dv = vecs[:, idx]
+    if n @ dv < 0 and mode != "alfven":
+        dv = -dv
+    drho = rho * (n @ dv) / V
+    dp = gamma * p * (n @ dv) / V
+    dB = -(nB * dv - (n @ dv) * B) / V
+    R = np.concatenate([[drho], dv, [dp / (gamma - 1.0)], dB])
+    return V, R / np.linalg.norm(R)
+
+
+def linear_wave(n=(32, 32, 32), k=(1, 1, 1), amp=1e-6, rho=1.0, p=1.0, gamma=4.0 / 3.0,
+                B=(1.0, np.sqrt(2.0), 0.5), mode="fast", recon=RECON_PLM_MC,
+                riemann=RIEMANN_HLL, cfl=0.4):
+    """Periodic unit box carrying one right-going eigenmode along integer k."""
+    box_len = [1.0, 1.0, 1.0]
+    for d in range(3):
+        if k[d] == 0 and n[d] == 1:
+            box_len[d] = 1.0
+    prob = Problem(n=tuple(n), xmin=(0.0, 0.0, 0.0), xmax=tuple(box_len),
+                   bc=(BC_PERIODIC,) * 6, gamma=gamma, recon=recon, riemann=riemann, cfl=cfl)
+    kvec = 2.0 * np.pi * np.asarray(k, float)
+    nhat = kvec / np.linalg.norm(kvec)
+    V, R = sr_wave_eigen(rho, p, gamma, B, nhat, mode)
+    x = [prob.centers(d) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    phase = np.cos(kvec[0] * X + kvec[1] * Y + kvec[2] * Z)
+    P = np.zeros((5,) + prob.shape)
+    base = [rho, 0.0, 0.0, 0.0, p / (gamma - 1.0)]
+    for q in range(5):
+        P[q] = base[q] + amp * R[q] * phase
+    dB = amp * R[5:8]
+    kk = kvec @ kvec
+    avec = np.cross(dB, kvec) / kk    # A = (dB x k)/|k|^2 sin(k.x)  ->  curl A = dB cos(k.x)
+
+    def A(comp, Xe, Ye, Ze):
+        return avec[comp] * np.sin(kvec[0] * Xe + kvec[1] * Ye + kvec[2] * Ze)
+    prob.Bf = _curl_faces(prob, A, B)
+    prob.P = P
+    prob.meta = {"speed": V, "eigvec": R, "k": kvec, "amp": amp,
+                 "period": (2.0 * np.pi / np.sqrt(kk)) / V}
+    return prob
+
+
+# ---------------------------------------------------------------------------
+# Shock tube (Minkowski, B = 0, along x1)
+# ---------------------------------------------------------------------------
+
+def shock_tube(n1=400, left=(10.0, 0.0, 13.33), right=(1.0, 0.0, 1e-6), gamma=5.0 / 3.0,
+               x0=0.5, recon=RECON_PLM_MC, riemann=RIEMANN_HLL, cfl=0.4):
+    """States (rho, v^x, p).  Outflow along x1, one cell in x2 and x3."""
+    prob = Problem(n=(n1, 1, 1), xmin=(0.0, 0.0, 0.0), xmax=(1.0, 1.0, 1.0),
+                   bc=(BC_OUTFLOW, BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC,
+                       BC_PERIODIC), gamma=gamma, recon=recon, riemann=riemann, cfl=cfl)
+    x = prob.centers(0)
+    P = np.zeros((5,) + prob.shape)
+    for st, mask in ((left, x < x0), (right, x >= x0)):
+        rho, v, p = st
+        W = 1.0 / np.sqrt(1.0 - v * v)
+        P[0][..., mask] = rho
+        P[1][..., mask] = W * v
+        P[4][..., mask] = p / (gamma - 1.0)
+    prob.P = P
+    prob.Bf = np.zeros((3,) + prob.shape)
+    prob.meta = {"left": left, "right": right, "x0": x0}
+    return prob
+
+
+# ---------------------------------------------------------------------------
+# Michel (Bondi) inflow on Schwarzschild in Kerr-Schild coordinates
+# ---------------------------------------------------------------------------
+
+def michel_solution(r, rc=8.0, gamma=4.0 / 3.0, M=1.0):
+    """Transonic polytropic radial inflow (Michel 1972) with sonic radius rc.
+
+    T = p/rho, n = 1/(gamma-1), rho = T^n (K = 1).  Conserved along the flow:
+    C1 = T^n u^r r^2 and C2 = (1 + (n+1)T)^2 (1 - 2M/r + (u^r)^2).  At the sonic
+    point (u^r)^2 = M/(2 rc) and the sound speed^2 V^2 = u^2/(1 - 3u^2) fixes T.
+    Returns (rho, u^r, T) arrays.
+    """
+    nn = 1.0 / (gamma - 1.0)
+    uc2 = M / (2.0 * rc)
+    Vc2 = uc2 / (1.0 - 3.0 * uc2)
+    Tc = nn * Vc2 / ((nn + 1.0) * (1.0 - nn * Vc2))
+    C1 = Tc ** nn * np.sqrt(uc2) * rc * rc
+    C2 = (1.0 + (nn + 1.0) * Tc) ** 2 * (1.0 - 2.0 * M / rc + uc2)
+    import scipy.optimize as so
+
+    def f(T, rr):
+        ur = C1 / (rr * rr * T ** nn)
+        return (1.0 + (nn + 1.0) * T) ** 2 * (1.0 - 2.0 * M / rr + ur * ur) - C2
+
+    rr = np.atleast_1d(np.asarray(r, float))
+    T = np.zeros_like(rr)
+    for i, x in enumerate(rr):
+        if abs(x - rc) < 1e-12:
+            T[i] = Tc
+            continue
+        # f has one minimum in T; the two roots straddle it.
+        tm = so.minimize_scalar(lambda t: f(t, x), bounds=(1e-12, 10.0), method="bounded",
+                                options={"xatol": 1e-14}).x
+        if x > rc:       # subsonic branch: the larger-T root
+            lo, hi = tm, tm
+            while f(hi, x) < 0:
+                hi *= 2.0
+            T[i] = so.brentq(lambda t: f(t, x), tm, hi, xtol=1e-15, rtol=1e-15)
+        else:            # supersonic branch: the smaller-T root
+            lo = tm
+            while f(lo, x) < 0:
+                lo *= 0.5
+            T[i] = so.brentq(lambda t: f(t, x), lo, tm, xtol=1e-15, rtol=1e-15)
+    rho = T ** nn
+    ur = -C1 / (rr * rr * T ** nn)
+    return rho, ur, T
+
+
+def _ks_lapse_shift_r(r, th, a=0.0, M=1.0):
+    sig = r * r + a * a * np.cos(th) ** 2
+    z = 2.0 * M * r / sig
+    return 1.0 / np.sqrt(1.0 + z), z / (1.0 + z), z
+
+
+def bondi(n1=64, rin=2.5, rout=20.0, rc=8.0, gamma=4.0 / 3.0, dtheta=0.1,
+          recon=RECON_PLM_MC, riemann=RIEMANN_HLL, cfl=0.4):
+    """Radial Michel inflow, a = 0, one cell in theta (equator) and phi; the
+    x1 ghosts hold the exact solution (fixed boundary)."""
+    prob = Problem(n=(n1, 1, 1), xmin=(np.log(rin), 0.5 * np.pi - 0.5 * dtheta, 0.0),
+                   xmax=(np.log(rout), 0.5 * np.pi + 0.5 * dtheta, 2.0 * np.pi),
+                   bc=(BC_FIXED, BC_FIXED, BC_OUTFLOW, BC_OUTFLOW, BC_PERIODIC, BC_PERIODIC),
+                   metric_kind=KS_LOGSPH, M=1.0, a=0.0, gamma=gamma, recon=recon,
+                   riemann=riemann, cfl=cfl)
+    r = np.exp(prob.centers(0))
+    rho, ur, T = michel_solution(r, rc, gamma)
+    alpha, betar, z = _ks_lapse_shift_r(r, 0.5 * np.pi)
+    # KS: g_tt = -(1-z), g_tr = z, g_rr = 1+z ; solve for u^t (future root)
+    A = -(1.0 - z)
+    Bq = 2.0 * z * ur
+    C = (1.0 + z) * ur * ur + 1.0
+    ut = (-Bq - np.sqrt(Bq * Bq - 4.0 * A * C)) / (2.0 * A)
+    # u-tilde^r = u^r + u^t beta^r ; x1 = ln r  ->  divide by r
+    utr = (ur + ut * betar) / r
+    P = np.zeros((5,) + prob.shape)
+    P[0] = rho[None, None, :]
+    P[1] = utr[None, None, :]
+    P[4] = (rho * T / (gamma - 1.0))[None, None, :]
+    prob.P = P
+    prob.Bf = np.zeros((3,) + prob.shape)
+    prob.meta = {"rc": rc}
+    return prob
+
+
+# ---------------------------------------------------------------------------
+# Fishbone-Moncrief torus around a Kerr black hole (Kerr-Schild, x1 = ln r)
+# ---------------------------------------------------------------------------
+
+def _bl_tphi(r, th, a, M=1.0):
+    """Boyer-Lindquist (t, phi) block of g_{mu nu} and its determinant."""
+    s2 = np.sin(th) ** 2
+    sig = r * r + a * a * np.cos(th) ** 2
+    delta = r * r - 2.0 * M * r + a * a
+    Acal = (r * r + a * a) ** 2 - delta * a * a * s2
+    gtt = -(1.0 - 2.0 * M * r / sig)
+    gtp = -2.0 * M * a * r * s2 / sig
+    gpp = Acal * s2 / sig
+    return gtt, gtp, gpp
+
+
+def fm_ell(rmax, a, M=1.0):
+    """ell = u^t u_phi of the prograde equatorial circular geodesic at rmax
+    (Bardeen, Press & Teukolsky 1972), the Fishbone-Moncrief constant that puts
+    the pressure maximum at rmax."""
+    sM = np.sqrt(M)
+    den = rmax ** 0.75 * np.sqrt(rmax ** 1.5 - 3.0 * M * np.sqrt(rmax) + 2.0 * a * sM)
+    ut = (rmax ** 1.5 + a * sM) / den
+    uphi = sM * (rmax * rmax - 2.0 * a * sM * np.sqrt(rmax) + a * a) / den
+    return ut * uphi
+
+
+def fm_lnh(r, th, a, ell, M=1.0):
+    """ln h + const for the constant-(u^t u_phi) torus.
+
+    Circular flow u = u^t (1, 0, 0, Omega) with u^t u_phi = ell and u.u = -1
+    gives u_phi^2 = Z, Z^2 + g_phiphi Z + D ell^2 = 0 (D = det of the (t,phi)
+    block), and the Euler equation reduces to d ln h = ell d(u_t/u_phi) - d ln u_phi.
+    Returns (ln h + const, u_t, u_phi)."""
+    gtt, gtp, gpp = _bl_tphi(r, th, a, M)
+    D = gtt * gpp - gtp * gtp
+    Z = 0.5 * (-gpp + np.sqrt(gpp * gpp - 4.0 * D * ell * ell))
+    uphi = np.sqrt(Z)
+    gitt, gitp = gpp / D, -gtp / D
+    ut_low = (ell - gitp * Z) / (gitt * uphi)
+    return ell * ut_low / uphi - np.log(uphi), ut_low, uphi
+
+
+def torus(n=(128, 128, 128), a=0.9375, rin=6.0, rmax=12.0, gamma=13.0 / 9.0, rmin=1.2,
+          rout=40.0, seed=1, noise=4e-2, beta=100.0, rho_flr0=1e-6, rho_flr_pow=1.5,
+          u_flr0=1e-8, u_flr_pow=2.5, recon=RECON_WENO5Z, riemann=RIEMANN_LLF, cfl=0.4,
+          W_max=50.0):
+    """Fishbone-Moncrief torus (rho_max = 1) with a seeded pressure noise and a
+    poloidal loop field A_phi = max(rho/rho_max - 0.2, 0) scaled so that
+    max p / max(b^2/2) = beta, on Kerr-Schild coordinates x1 = ln r, x2 = theta,
+    x3 = phi.  Outside the torus the gas sits at the floor values with zero
+    Eulerian velocity."""
+    M = 1.0
+    prob = Problem(n=tuple(n), xmin=(np.log(rmin), 0.0, 0.0),
+                   xmax=(np.log(rout), np.pi, 2.0 * np.pi),
+                   bc=(BC_OUTFLOW, BC_OUTFLOW, BC_POLAR, BC_POLAR, BC_PERIODIC, BC_PERIODIC),
+                   metric_kind=KS_LOGSPH, M=M, a=a, gamma=gamma, rho_flr0=rho_flr0,
+                   rho_flr_pow=rho_flr_pow, u_flr0=u_flr0, u_flr_pow=u_flr_pow, W_max=W_max,
+                   recon=recon, riemann=riemann, cfl=cfl)
+    ell = fm_ell(rmax, a, M)
+    lnh_in = fm_lnh(rin, 0.5 * np.pi, a, ell, M)[0]
+    lnh_max = fm_lnh(rmax, 0.5 * np.pi, a, ell, M)[0] - lnh_in
+    hmax = np.exp(lnh_max)
+    K = (hmax - 1.0) * (gamma - 1.0) / gamma     # rho(rmax) = 1
+
+    def rho_of(r, th):
+        with np.errstate(invalid="ignore", divide="ignore"):
+            lnh, ut_low, uphi = fm_lnh(r, th, a, ell, M)
+            lnh = lnh - lnh_in
+            inside = (lnh > 0.0) & (r >= rin) & np.isfinite(lnh)
+            h = np.where(inside, np.exp(np.where(inside, lnh, 0.0)), 1.0)
+            rho = np.where(inside,
+                           ((h - 1.0) * (gamma - 1.0) / (K * gamma)) ** (1.0 / (gamma - 1.0)),
+                           0.0)
+        return rho, inside, ut_low, uphi
+
+    s1, s2 = prob.n[0] + 2 * prob.ng, prob.n[1] + 2 * prob.ng
+    r1 = np.exp(prob.centers(0))
+    th1 = prob.centers(1)
+    # ghost rows beyond the poles take their mirror theta (the field there is
+    # overwritten by the boundary fill anyway; this keeps the numbers finite)
+    thc = np.clip(th1, 1e-12, np.pi - 1e-12)
+    R2, TH2 = np.meshgrid(r1, thc, indexing="xy")        # shape (s2, s1)
+    rho, inside, ut_low, uphi = rho_of(R2, TH2)
+    p = np.where(inside, K * rho ** gamma, 0.0)
+
+    # four-velocity of the torus (BL and KS share u^t, u^phi when u^r = 0)
+    gtt, gtp, gpp = _bl_tphi(R2, TH2, a, M)
+    D = gtt * gpp - gtp * gtp
+    gitt, gitp, gipp = gpp / D, -gtp / D, gtt / D
+    with np.errstate(invalid="ignore"):
+        ucon_t = gitt * ut_low + gitp * uphi
+        ucon_p = gitp * ut_low + gipp * uphi
+    alpha, betar, z = _ks_lapse_shift_r(R2, TH2, a, M)
+    # u-tilde^i = u^i + u^t beta^i ; beta^1 = beta^r / r in x1 = ln r ; beta^phi = 0
+    ut1 = np.where(inside, ucon_t * betar / R2, 0.0)
+    ut3 = np.where(inside, ucon_p, 0.0)
+
+    rflr = rho_flr0 * R2 ** (-rho_flr_pow)
+    uflr = u_flr0 * R2 ** (-u_flr_pow)
+    rho_f = np.maximum(rho, rflr)
+    u_f = np.maximum(p / (gamma - 1.0), uflr)
+
+    shp = prob.shape
+    P = np.zeros((5,) + shp)
+    P[0] = rho_f[None]
+    P[1] = ut1[None]
+    P[3] = ut3[None]
+    # seeded pressure noise inside the torus, keyed by the global cell index
+    cell = np.arange(prob.ncell, dtype=np.uint64).reshape(shp)
+    xi = uniform01(seed, cell)
+    pert = 1.0 + noise * (xi - 0.5)
+    P[4] = np.where(inside[None], u_f[None] * pert, u_f[None])
+
+    # vector potential at (x1-face, x2-face) edges, axisymmetric
+    rf = np.exp(prob.faces(0))
+    thf = np.clip(prob.faces(1), 0.0, np.pi)
+    RF, THF = np.meshgrid(rf, thf, indexing="xy")
+    rhoe, _, _, _ = rho_of(RF, np.clip(THF, 1e-12, np.pi - 1e-12))
+    Aphi = np.maximum(rhoe - 0.2, 0.0)
+    Aphi[np.abs(THF) < 1e-14] = 0.0
+    Aphi[np.abs(THF - np.pi) < 1e-14] = 0.0
+    dx1, dx2 = prob.dx[0], prob.dx[1]
+    Bf = np.zeros((3,) + shp)
+    # B1 (x1 faces) = d_2 A_3 ; B2 (x2 faces) = -d_1 A_3   (densitized)
+    b1 = np.zeros((s2, s1))
+    b1[:-1, :] = (Aphi[1:, :] - Aphi[:-1, :]) / dx2
+    b2 = np.zeros((s2, s1))
+    b2[:, :-1] = -(Aphi[:, 1:] - Aphi[:, :-1]) / dx1
+    Bf[0] = b1[None]
+    Bf[1] = b2[None]
+
+    # normalise: max p / max(b^2/2) = beta, with b^2 from the cell-centre field
+    sqrtgam = _ks_sqrtgam(R2, TH2, a, M)
+    Bc1 = 0.5 * (b1[:, :] + np.roll(b1, -1, axis=1)) / sqrtgam
+    Bc2 = 0.5 * (b2[:, :] + np.roll(b2, -1, axis=0)) / sqrtgam
+    b2fluid = _ks_b2(R2, TH2, a, M, ut1, np.zeros_like(ut1), ut3, Bc1, Bc2)
+    g = prob.ng
+    sl = (slice(g, g + prob.n[1]), slice(g, g + prob.n[0]))
+    pmax = np.max(p[sl])
+    bmax = np.max(b2fluid[sl])
+    scale = np.sqrt(2.0 * pmax / (beta * bmax)) if bmax > 0 else 0.0
+    Bf *= scale
+    prob.P, prob.Bf = P, Bf
+    prob.meta = {"ell": ell, "K": K, "pmax": pmax, "field_scale": scale, "seed": seed}
+    return prob
+
+
+def _ks_gamma_ij(r, th, a, M):
+    """Spatial KS metric in (x1 = ln r, theta, phi): nonzero g11, g13, g22, g33."""
+    s2 = np.sin(th) ** 2
+    sig = r * r + a * a * np.cos(th) ** 2
+    z = 2.0 * M * r / sig
+    g11 = r * r * (1.0 + z)
+    g13 = -a * (1.0 + z) * s2 * r
+    g22 = sig
+    g33 = s2 * (sig + a * a * (1.0 + z) * s2)
+    return g11, g13, g22, g33
+
+
+def _ks_sqrtgam(r, th, a, M):
+    g11, g13, g22, g33 = _ks_gamma_ij(r, th, a, M)
+    return np.sqrt(g22 * (g11 * g33 - g13 * g13))
+
+
+def _ks_b2(r, th, a, M, u1, u2, u3, B1, B2):
+    """Fluid-frame b^2 for the IC normalisation (B^3 = 0)."""
+    g11, g13, g22, g33 = _ks_gamma_ij(r, th, a, M)
+    alpha, betar, z = _ks_lapse_shift_r(r, th, a, M)
+    W = np.sqrt(1.0 + g11 * u1 * u1 + 2.0 * g13 * u1 * u3 + g22 * u2 * u2 + g33 * u3 * u3)
+    v1, v2, v3 = u1 / W, u2 / W, u3 / W
+    vl1 = g11 * v1 + g13 * v3
+    vl2 = g22 * v2
+    Bv = B1 * vl1 + B2 * vl2
+    BB = g11 * B1 * B1 + g22 * B2 * B2
+    b0 = W * Bv / alpha
+    return (BB + alpha * alpha * b0 * b0) / (W * W)
+
+
+# ---------------------------------------------------------------------------
+# Random primitive states for inversion tests and the learned-guess data set
+# ---------------------------------------------------------------------------
+
+def random_prims(count, seed=3, rho=(1e-8, 1.0), p_over_rho=(1e-6, 10.0), W=(1.0, 50.0),
+                 sigma=(1e-4, 100.0), gamma=13.0 / 9.0):
+    """Minkowski primitive samples: log-uniform rho, p/rho, W, sigma = b^2/rho;
+    isotropic directions of v and B; |B| chosen so that b^2 = sigma rho.
+    Returns dict of arrays rho, ut[3], u, B[3] (contravariant, flat metric)."""
+    rng = np.random.default_rng(seed)
+
+    def logu(lo, hi, size):
+        return np.exp(rng.uniform(np.log(lo), np.log(hi), size))
+
+    def iso(size):
+        v = rng.normal(size=(size, 3))
+        return v / np.linalg.norm(v, axis=1, keepdims=True)
+    r = logu(*rho, count)
+    pr = logu(*p_over_rho, count)
+    Wl = logu(max(W[0], 1.0 + 1e-12), W[1], count) if W[0] > 1.0 else \
+        1.0 + logu(1e-6, W[1] - 1.0, count)
+    sg = logu(*sigma, count)
+    vhat = iso(count)
+    bhat = iso(count)
+    vmag = np.sqrt(1.0 - 1.0 / (Wl * Wl))
+    v = vhat * vmag[:, None]
+    b2 = sg * r
+    Bmag = np.sqrt(b2 / (1.0 / (Wl * Wl) + (np.sum(bhat * v, axis=1)) ** 2))
+    B = bhat * Bmag[:, None]
+    ut = v * Wl[:, None]
+    u = pr * r / (gamma - 1.0)
+    return {"rho": r, "ut": ut, "u": u, "B": B, "W": Wl, "gamma": gamma}
