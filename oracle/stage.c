@@ -56,7 +56,9 @@ static int map_axis(const orc_grid *g, int d, int idx, int normal, int *src, int
   *side = low ? -1 : 1;
   switch (bc) {
   case ORC_BC_PERIODIC:
-    *src = low ? idx + n : idx - n;
+    /* wrap modulo n: a direction thinner than the ghost depth still maps
+       every ghost to an interior cell (face n is face 0) */
+    *src = ng + (((idx - ng) % n) + n) % n;
     return 1;
   case ORC_BC_OUTFLOW:
     *src = low ? lo : hi;
