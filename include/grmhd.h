@@ -1,0 +1,184 @@
+/*
+ * grmhd.h - C ABI of the MI355X (gfx950) GRMHD stage library, libgrmhd.so.
+ *
+ * One Runge-Kutta stage of the Valencia-formulation ideal GRMHD finite-volume
+ * update (Phoebus paper, Sec. 2.1 conservation law with the conserved vector,
+ * flux vector and source vector given there; Sec. 3.1 second-order finite
+ * volumes, constrained transport, LLF/HLL Riemann solvers, the reconstruction
+ * list and the master-function inversion; Sec. 3.2 floors; App. B
+ * WENO5-Z-AOAH) over a pack of meshblocks on one GPU.
+ *
+ * Memory and ownership
+ *   - All state arrays are device memory owned by the caller.  The library
+ *     never allocates device memory: scratch lives in a caller-provided
+ *     workspace of grmhd_pack_workspace_bytes() bytes (256-byte aligned).
+ *   - A pack owns host metadata only and is bound to one HIP stream; every
+ *     call below is asynchronous on that stream unless stated otherwise.
+ *   - Arrays are structure-of-arrays, FP64: variable v of cell c of block b is
+ *     at  base[v * ncell_total + offset[b] + c],  c = i + s1 (j + s2 k),
+ *     s_d = n_d + 2 ng, offsets from grmhd_layout().
+ *       P  [5]: rho, W v^1, W v^2, W v^3 (contravariant), u = rho eps
+ *       Bf [3]: sqrt(gamma) B^d on the lower d-face of each cell
+ *       U  [5]: sqrt(gamma) (D, S_1, S_2, S_3, tau), S_j covariant
+ *       U0 [5], Bf0 [3]: Runge-Kutta base copies of U and Bf.
+ *   - Coordinates: Minkowski-Cartesian, or Kerr-Schild with x1 = ln r,
+ *     x2 = theta, x3 = phi (units G = c = M = 1, Heaviside-Lorentz B).
+ *
+ * Errors: every int-returning call gives 0 on success or a negative code;
+ * grmhd_last_error() returns the message.  No exception or abort crosses the
+ * ABI.  Con2prim failures are not errors: they are flagged per cell.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRMHD_ABI_VERSION 1
+
+enum { GRMHD_OK = 0, GRMHD_E_INVALID = -1, GRMHD_E_SHAPE = -2, GRMHD_E_HIP = -3,
+       GRMHD_E_UNSUPPORTED = -4 };
+enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KS_LOGSPH = 1 };
+enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2, GRMHD_BC_FIXED = 3 };
+enum { GRMHD_RECON_CONST = 0, GRMHD_RECON_PLM_MC = 1, GRMHD_RECON_WENO5Z_AOAH = 2,
+       GRMHD_RECON_PLM_MINMOD = 3 };
+enum { GRMHD_RIEMANN_HLL = 0, GRMHD_RIEMANN_LLF = 1 };
+enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
+enum { GRMHD_GUESS_COLD = 0, GRMHD_GUESS_PREV = 1, GRMHD_GUESS_MLP = 2 };
+/* per-cell con2prim flag bits */
+enum { GRMHD_FLAG_RHO_FLOOR = 1, GRMHD_FLAG_U_FLOOR = 2, GRMHD_FLAG_W_CAP = 4,
+       GRMHD_FLAG_C2P_FAIL = 8 };
+
+typedef struct grmhd_pack grmhd_pack;
+
+/* Analytic metric (Sec. 2.3): kind, black-hole mass M and spin a (KS only). */
+typedef struct { int kind; double M, a; } grmhd_metric;
+
+/*
+ * Ideal-gas EOS (Sec. 2.2) and floors (Sec. 3.2):
+ *   p = (gamma - 1) u;  rho >= rho_flr0 r^-rho_flr_pow;  u >= u_flr0 r^-u_flr_pow
+ *   (r = 1 in Minkowski);  W <= W_max.
+ * c2p_tol: relative Newton tolerance on mu = 1/(hW); c2p_max_iter: cap.
+ */
+typedef struct {
+  double gamma, rho_flr0, rho_flr_pow, u_flr0, u_flr_pow, W_max, c2p_tol;
+  int c2p_max_iter;
+} grmhd_eos;
+
+/*
+ * Pack descriptor.  nblocks blocks, block b has nx[3b..3b+2] interior cells,
+ * refinement level level[b] and logical location lloc[3b..3b+2] = global index
+ * (in cells of its level) of its first interior cell.  The whole domain spans
+ * [xmin, xmax] with root_nx cells at level 0.  bc[6] = boundary kind at
+ * (x1 lo, x1 hi, x2 lo, x2 hi, x3 lo, x3 hi).  ng must be 4.
+ * weno_fv: 0 = WENO candidates interpolate point values (App. B wording),
+ *          1 = cell-average candidates.
+ */
+typedef struct {
+  int nblocks, ng;
+  int recon, riemann, precision, weno_fv;
+  const int *nx, *level, *lloc;
+  int root_nx[3];
+  double xmin[3], xmax[3];
+  int bc[6];
+} grmhd_pack_desc;
+
+/* Device pointers bound to a pack (caller-owned, see layout above). */
+typedef struct { void *P, *Bf, *U, *U0, *Bf0; } grmhd_state_ptrs;
+
+/*
+ * Reduction results (O(1) scalars).
+ *   dt: cfl / max over interior cells of sum_d max|lambda_d| / dx_d
+ *       (directions with a single cell are skipped);
+ *   divb_rel: max |sum_d delta_d Bf_d / dx_d| / (max |Bf| / min dx);
+ *   totals[5]: sum over interior of U_v dx1 dx2 dx3;
+ *   c2p_fail, floor_hits: flagged cells of the last con2prim;
+ *   c2p_iter_mean / c2p_iter_wavemax_mean: Newton iterations per cell and the
+ *   mean over 64-cell wavefronts of the per-wavefront maximum.
+ */
+typedef struct {
+  double dt, divb_rel, divb_max, totals[5];
+  long long c2p_fail, floor_hits;
+  double c2p_iter_mean, c2p_iter_wavemax_mean;
+} grmhd_reduction_out;
+
+int grmhd_abi_version(void);
+
+/* Layout: fills offsets[nblocks] (cells) and *ncell_total (cells per variable
+ * plane, every block offset a multiple of 32 cells = 256 bytes). */
+int grmhd_layout(const grmhd_pack_desc *desc, long long *offsets, long long *ncell_total);
+
+/* Workspace bytes a pack with this descriptor needs (0 on invalid desc). */
+size_t grmhd_pack_workspace_bytes(const grmhd_pack_desc *desc);
+
+/*
+ * Validate desc, build block tables, ghost maps and tile lists, upload them
+ * into the workspace (async on hip_stream).  ws must stay valid and unused by
+ * anything else until grmhd_pack_destroy.  Errors: E_INVALID / E_SHAPE /
+ * E_UNSUPPORTED for a bad descriptor, E_HIP for a failed HIP call.
+ */
+int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state,
+                      void *workspace, size_t ws_bytes, void *hip_stream, grmhd_pack **out);
+
+/* Frees host metadata only (after synchronising the stream). */
+int grmhd_pack_destroy(grmhd_pack *pack);
+
+/* Replace the bound state pointers (same shapes). */
+int grmhd_bind_state(grmhd_pack *pack, const grmhd_state_ptrs *state);
+
+/*
+ * Fill the ghost zones of P and Bf (boundary kinds and same-level block
+ * copies), then the cell-centred field used by the next stage.
+ */
+int grmhd_fill_ghosts(grmhd_pack *pack, const grmhd_metric *metric);
+
+/*
+ * One Runge-Kutta stage (Sec. 2.1, Sec. 3.1):  with L = -div F + sqrt(-g) S
+ * evaluated on the current P and Bf,
+ *     U  <- c0 U0  + c1 U  + c_dt dt L
+ *     Bf <- c0 Bf0 + c1 Bf + c_dt dt (CT update from edge-averaged EMFs).
+ * rk_coeffs = {c0, c1, c_dt}.  When c1 == 0 the current U and Bf are the
+ * base: they are first saved into U0 and Bf0 (so SSPRK2 is {1,0,1} then
+ * {1/2,1/2,1/2}).  dt <= 0 means: use the device-resident dt written by the
+ * last grmhd_reductions (no host round trip).  Requires grmhd_fill_ghosts
+ * since the last change of P or Bf.
+ */
+int grmhd_stage(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
+                double dt, const double rk_coeffs[3]);
+
+/*
+ * Con2prim + floors on interior cells: P <- P(U, Bf) by safeguarded Newton on
+ * the master function f(mu) = mu - 1/(h/W + mu rbar^2) (the unknown mu =
+ * 1/(hW)), starting from guess (COLD: mu = 1/W_cold; PREV: from the current
+ * P; MLP: learned initial guess bound by grmhd_mlp_bind, falling back to PREV).
+ * A failed inversion keeps the previous P.  Where a floor or the fallback
+ * acts, the hydro part of U is rewritten from the final P.
+ */
+int grmhd_con2prim(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
+                   int guess);
+
+/* Initialise U from P and Bf on interior cells (same map as the inversion's inverse). */
+int grmhd_prim_to_cons(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos);
+
+/*
+ * Reductions (see grmhd_reduction_out).  The dt is always stored device-side
+ * for the next grmhd_stage(dt <= 0).  out == NULL: asynchronous; otherwise the
+ * call synchronises the stream and fills *out.
+ */
+int grmhd_reductions(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
+                     double cfl, grmhd_reduction_out *out);
+
+/* Device pointers to the per-cell int8 flags and uint8 Newton iteration
+ * counts of the last con2prim (inside the workspace; same cell layout as P). */
+int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
+
+const char *grmhd_last_error(const grmhd_pack *pack);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,342 @@
+// Device math for the gfx950 GRMHD stage: analytic metric, Valencia
+// conserved/flux/speed evaluation, reconstruction, inversion.  Every function
+// is inlined into the kernels of grmhd.hip.
+//
+// The metric family covered has gamma_12 = gamma_23 = 0 and shift only along
+// x1: Minkowski-Cartesian and Kerr-Schild in (ln r, theta, phi).  The code is
+// written for exactly that structure (11 scalars per point) to keep FP64
+// register pressure down.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grmhd {
+
+enum { MK_MINK = 0, MK_KS = 1 };
+enum { RC_CONST = 0, RC_PLM_MC = 1, RC_WENO = 2, RC_PLM_MINMOD = 3 };
+enum { RS_HLL = 0, RS_LLF = 1 };
+
+// ------------------------------------------------------------------ layout
+
+struct BlockInfo {
+  int n[3];          // interior cells
+  int s[3];          // padded extent n + 2 ng
+  long long off;     // cell offset of the block in every variable plane
+  double dx[3];
+  int tab1, tab2;    // offsets of the block's rows in the 1-D coordinate tables
+  int pole_lo, pole_hi;  // local x2 face index of a polar face, or -1
+  int pad[2];
+};
+
+struct Tables {      // Kerr-Schild 1-D coordinate tables (ghost rows mirrored)
+  const double *rc, *rf;          // r at x1 centres / lower faces
+  const double *sc, *cc, *sf, *cf;  // sin, cos theta at x2 centres / lower faces
+};
+
+struct MetricP { double M, a; };
+
+struct EosP {
+  double gam, rho_flr0, rho_flr_pow, u_flr0, u_flr_pow, W_max, tol;
+  int max_iter;
+};
+
+// ------------------------------------------------------------------ metric
+
+struct Geo {
+  double alpha, beta1;               // lapse, shift (x1 component only)
+  double g11, g13, g22, g33;         // gamma_ij
+  double gi11, gi13, gi22, gi33;     // gamma^ij
+  double sqrtg;                      // sqrt(gamma)
+};
+
+__device__ __forceinline__ Geo geo_mink()
+{
+  Geo G;
+  G.alpha = 1.0; G.beta1 = 0.0;
+  G.g11 = 1.0; G.g13 = 0.0; G.g22 = 1.0; G.g33 = 1.0;
+  G.gi11 = 1.0; G.gi13 = 0.0; G.gi22 = 1.0; G.gi33 = 1.0;
+  G.sqrtg = 1.0;
+  return G;
+}
+
+// Kerr-Schild at (r, sin theta, cos theta), x1 = ln r.  With Sigma = r^2 +
+// a^2 cos^2, z = 2 M r / Sigma:  alpha = (1+z)^-1/2, beta^1 = z/((1+z) r),
+// gamma_11 = r^2 (1+z), gamma_13 = -a (1+z) sin^2 r, gamma_22 = Sigma,
+// gamma_33 = sin^2 (Sigma + a^2 (1+z) sin^2); the (1,3) block has
+// determinant r^2 (1+z) sin^2 Sigma, so sqrt(gamma) = r Sigma sin sqrt(1+z).
+__device__ __forceinline__ Geo geo_ks(double r, double s, double c, const MetricP &m)
+{
+  const double a2 = m.a * m.a, s2 = s * s;
+  const double Sig = fma(a2 * c, c, r * r);
+  const double iSig = 1.0 / Sig;
+  const double z = 2.0 * m.M * r * iSig;
+  const double opz = 1.0 + z;
+  const double sq = sqrt(opz);
+  Geo G;
+  G.alpha = 1.0 / sq;
+  const double ir = 1.0 / r;
+  G.beta1 = z * G.alpha * G.alpha * ir;
+  G.g11 = r * r * opz;
+  G.g13 = -m.a * opz * s2 * r;
+  G.g22 = Sig;
+  G.g33 = s2 * fma(a2 * opz, s2, Sig);
+  const double idet = iSig * ir * ir / (opz * s2);
+  G.gi11 = G.g33 * idet;
+  G.gi13 = -G.g13 * idet;
+  G.gi33 = G.g11 * idet;
+  G.gi22 = iSig;
+  G.sqrtg = r * Sig * s * sq;
+  return G;
+}
+
+template <int MK>
+__device__ __forceinline__ Geo geo_at(const Tables &T, const MetricP &m, int ir, bool rface,
+                                      int it, bool tface)
+{
+  if constexpr (MK == MK_MINK) {
+    return geo_mink();
+  } else {
+    const double r = rface ? T.rf[ir] : T.rc[ir];
+    const double s = tface ? T.sf[it] : T.sc[it];
+    const double c = tface ? T.cf[it] : T.cc[it];
+    return geo_ks(r, s, c, m);
+  }
+}
+
+// ------------------------------------------------------------------ physics
+
+struct Prim { double rho, u1, u2, u3, ie, B1, B2, B3; };
+
+// Auxiliary 4-vector quantities of a primitive state (Sec. 2.1 kinematics and
+// the b^mu / B^i relation).
+struct Aux {
+  double W, ut2, v1, v2, v3, vl1, vl2, vl3, Bv;
+  double uc1, uc2, uc3;        // u^i (contravariant four-velocity)
+  double b0, bc1, bc2, bc3;    // b^mu
+  double bl1, bl2, bl3;        // b_i
+  double b2, p, w;             // b^2, pressure, rho h
+};
+
+__device__ __forceinline__ Aux aux_of(const Geo &G, double gam, const Prim &q)
+{
+  Aux A;
+  A.ut2 = G.g11 * q.u1 * q.u1 + 2.0 * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
+          G.g33 * q.u3 * q.u3;
+  A.W = sqrt(1.0 + A.ut2);
+  const double iW = 1.0 / A.W;
+  A.v1 = q.u1 * iW; A.v2 = q.u2 * iW; A.v3 = q.u3 * iW;
+  A.vl1 = G.g11 * A.v1 + G.g13 * A.v3;
+  A.vl2 = G.g22 * A.v2;
+  A.vl3 = G.g13 * A.v1 + G.g33 * A.v3;
+  A.Bv = q.B1 * A.vl1 + q.B2 * A.vl2 + q.B3 * A.vl3;
+  const double Bl1 = G.g11 * q.B1 + G.g13 * q.B3;
+  const double Bl2 = G.g22 * q.B2;
+  const double Bl3 = G.g13 * q.B1 + G.g33 * q.B3;
+  const double BB = q.B1 * Bl1 + q.B2 * Bl2 + q.B3 * Bl3;
+  const double ia = 1.0 / G.alpha;
+  // u^i = W v^i - W beta^i / alpha;  b^i = B^i / W + (alpha b^0 / W) u^i,
+  // alpha b^0 = W (B . v)
+  A.uc1 = q.u1 - A.W * G.beta1 * ia;
+  A.uc2 = q.u2;
+  A.uc3 = q.u3;
+  A.b0 = A.W * A.Bv * ia;
+  A.bc1 = q.B1 * iW + A.Bv * A.uc1;
+  A.bc2 = q.B2 * iW + A.Bv * A.uc2;
+  A.bc3 = q.B3 * iW + A.Bv * A.uc3;
+  // b_i = beta_i b^0 + gamma_ij b^j  (beta_1 = g11 beta^1, beta_3 = g13 beta^1)
+  A.bl1 = G.g11 * (G.beta1 * A.b0 + A.bc1) + G.g13 * A.bc3;
+  A.bl2 = G.g22 * A.bc2;
+  A.bl3 = G.g13 * (G.beta1 * A.b0 + A.bc1) + G.g33 * A.bc3;
+  A.b2 = BB * iW * iW + A.Bv * A.Bv;
+  A.p = (gam - 1.0) * q.ie;
+  A.w = q.rho + q.ie + A.p;
+  return A;
+}
+
+// Undensitized conserved vector (D, S_j, tau, B^k).
+__device__ __forceinline__ void cons_of(const Geo &G, const Prim &q, const Aux &A, double U[8])
+{
+  const double W2 = A.W * A.W;
+  const double D = q.rho * A.W;
+  const double wt = A.w + A.b2;
+  const double ab0 = A.W * A.Bv;     // alpha b^0
+  U[0] = D;
+  U[1] = wt * W2 * A.vl1 - ab0 * A.bl1;
+  U[2] = wt * W2 * A.vl2 - ab0 * A.bl2;
+  U[3] = wt * W2 * A.vl3 - ab0 * A.bl3;
+  // tau with the rest-mass part rho (W^2 - W) = D ut2 / (W + 1)
+  U[4] = D * A.ut2 / (A.W + 1.0) + (q.ie + A.p + A.b2) * W2 - (A.p + 0.5 * A.b2) - ab0 * ab0;
+  U[5] = q.B1; U[6] = q.B2; U[7] = q.B3;
+}
+
+// Undensitized flux along direction DIR (0,1,2) given U.
+template <int DIR>
+__device__ __forceinline__ void flux_of(const Geo &G, const Prim &q, const Aux &A,
+                                        const double U[8], double F[8])
+{
+  const double ia = 1.0 / G.alpha;
+  const double vt1 = G.alpha * A.v1 - G.beta1, vt2 = G.alpha * A.v2, vt3 = G.alpha * A.v3;
+  const double vtd = DIR == 0 ? vt1 : (DIR == 1 ? vt2 : vt3);
+  const double vd = DIR == 0 ? A.v1 : (DIR == 1 ? A.v2 : A.v3);
+  const double Bd = DIR == 0 ? q.B1 : (DIR == 1 ? q.B2 : q.B3);
+  const double pt = A.p + 0.5 * A.b2;
+  const double iW = 1.0 / A.W;
+  const double adv = vtd * ia;
+  F[0] = U[0] * adv;
+  F[1] = U[1] * adv - A.bl1 * Bd * iW + (DIR == 0 ? pt : 0.0);
+  F[2] = U[2] * adv - A.bl2 * Bd * iW + (DIR == 1 ? pt : 0.0);
+  F[3] = U[3] * adv - A.bl3 * Bd * iW + (DIR == 2 ? pt : 0.0);
+  F[4] = U[4] * adv + pt * vd - A.Bv * Bd;
+  F[5] = (q.B1 * vtd - Bd * vt1) * ia;
+  F[6] = (q.B2 * vtd - Bd * vt2) * ia;
+  F[7] = (q.B3 * vtd - Bd * vt3) * ia;
+}
+
+// Fast-wave coordinate speeds along DIR from (k.u)^2 (1 - c^2) = c^2 k.k,
+// k_mu = (-lambda, e_DIR), c^2 = cs^2 + ca^2 - cs^2 ca^2.
+template <int DIR>
+__device__ __forceinline__ void speeds_of(const Geo &G, double gam, const Aux &A, double &lm,
+                                          double &lp)
+{
+  const double cs2 = gam * A.p / A.w;
+  const double ca2 = A.b2 / (A.w + A.b2);
+  const double c2 = cs2 + ca2 - cs2 * ca2;
+  const double ia2 = 1.0 / (G.alpha * G.alpha);
+  const double u0 = A.W / G.alpha;
+  const double ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
+  const double g00 = -ia2;
+  const double g0d = DIR == 0 ? G.beta1 * ia2 : 0.0;
+  const double gdd = DIR == 0 ? G.gi11 - G.beta1 * G.beta1 * ia2 : (DIR == 1 ? G.gi22 : G.gi33);
+  const double omc = 1.0 - c2;
+  const double qa = omc * u0 * u0 - c2 * g00;
+  const double qb = -2.0 * (omc * u0 * ud - c2 * g0d);
+  const double qc = omc * ud * ud - c2 * gdd;
+  double disc = qb * qb - 4.0 * qa * qc;
+  disc = disc > 0.0 ? disc : 0.0;
+  const double sq = sqrt(disc);
+  const double i2a = 0.5 / qa;
+  const double l1 = (-qb + sq) * i2a, l2 = (-qb - sq) * i2a;
+  lp = fmax(l1, l2);
+  lm = fmin(l1, l2);
+}
+
+// Densitized face flux (sqrt(-g) F) from left/right states; dissipation on
+// sqrt(gamma) U (speeds are eigenvalues of d(sqrt(-g)F)/d(sqrt(gamma)U)).
+template <int DIR, int RS>
+__device__ __forceinline__ void riemann(const Geo &G, double gam, const Prim &L, const Prim &R,
+                                        double out[8])
+{
+  double UL[8], UR[8], FL[8], FR[8], lmL, lpL, lmR, lpR;
+  {
+    const Aux A = aux_of(G, gam, L);
+    cons_of(G, L, A, UL);
+    flux_of<DIR>(G, L, A, UL, FL);
+    speeds_of<DIR>(G, gam, A, lmL, lpL);
+  }
+  {
+    const Aux A = aux_of(G, gam, R);
+    cons_of(G, R, A, UR);
+    flux_of<DIR>(G, R, A, UR, FR);
+    speeds_of<DIR>(G, gam, A, lmR, lpR);
+  }
+  const double sg = G.sqrtg, smg = G.alpha * G.sqrtg;
+  if constexpr (RS == RS_HLL) {
+    const double cm = fmin(0.0, fmin(lmL, lmR));
+    const double cp = fmax(0.0, fmax(lpL, lpR));
+    const double den = cp - cm;
+    if (den > 0.0) {
+      const double id = 1.0 / den;
+      const double a = cp * smg * id, b = cm * smg * id, c = cp * cm * sg * id;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) out[v] = a * FL[v] - b * FR[v] + c * (UR[v] - UL[v]);
+    } else {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) out[v] = 0.5 * smg * (FL[v] + FR[v]);
+    }
+  } else {
+    const double c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+    const double hs = 0.5 * smg, hc = 0.5 * c * sg;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) out[v] = hs * (FL[v] + FR[v]) - hc * (UR[v] - UL[v]);
+  }
+}
+
+// ---------------------------------------------------------- reconstruction
+
+__device__ __forceinline__ double mc_slope(double dm, double dp)
+{
+  if (dm * dp <= 0.0) return 0.0;
+  const double a = fmin(fmin(2.0 * fabs(dm), 2.0 * fabs(dp)), 0.5 * fabs(dm + dp));
+  return dm > 0.0 ? a : -a;
+}
+
+__device__ __forceinline__ double minmod_slope(double dm, double dp)
+{
+  if (dm * dp <= 0.0) return 0.0;
+  const double a = fmin(fabs(dm), fabs(dp));
+  return dm > 0.0 ? a : -a;
+}
+
+// One WENO5-Z face value at x_{j+1/2} from f0..f4 = f_{j-2..j+2}; also the
+// per-face measure 3 w0 w1 w2 / (g2 w0 w1 + g1 w0 w2 + g0 w1 w2).
+template <int FV>
+__device__ __forceinline__ double weno_z_face(double f0, double f1, double f2, double f3,
+                                              double f4, double &sig)
+{
+  constexpr double g0 = FV ? 0.1 : 1.0 / 16.0;
+  constexpr double g1 = FV ? 0.6 : 10.0 / 16.0;
+  constexpr double g2 = FV ? 0.3 : 5.0 / 16.0;
+  const double t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const double t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const double t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  constexpr double c13 = 13.0 / 12.0;
+  const double b0 = c13 * t0 * t0 + 0.25 * s0 * s0;
+  const double b1 = c13 * t1 * t1 + 0.25 * s1 * s1;
+  const double b2 = c13 * t2 * t2 + 0.25 * s2 * s2;
+  const double tau = fabs(b0 - b2);
+  const double r0 = tau / (b0 + 1e-40), r1 = tau / (b1 + 1e-40), r2 = tau / (b2 + 1e-40);
+  const double a0 = g0 * (1.0 + r0 * r0), a1 = g1 * (1.0 + r1 * r1), a2 = g2 * (1.0 + r2 * r2);
+  const double is = 1.0 / (a0 + a1 + a2);
+  const double w0 = a0 * is, w1 = a1 * is, w2 = a2 * is;
+  double p0, p1, p2;
+  if constexpr (FV) {
+    p0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * (1.0 / 6.0);
+    p1 = (-f1 + 5.0 * f2 + 2.0 * f3) * (1.0 / 6.0);
+    p2 = (2.0 * f2 + 5.0 * f3 - f4) * (1.0 / 6.0);
+  } else {
+    p0 = (3.0 * f0 - 10.0 * f1 + 15.0 * f2) * 0.125;
+    p1 = (-f1 + 6.0 * f2 + 3.0 * f3) * 0.125;
+    p2 = (3.0 * f2 + 6.0 * f3 - f4) * 0.125;
+  }
+  const double w01 = w0 * w1;
+  sig = 3.0 * w01 * w2 / (g2 * w01 + g1 * w0 * w2 + g0 * w1 * w2);
+  return w0 * p0 + w1 * p1 + w2 * p2;
+}
+
+// Left (j-1/2) and right (j+1/2) face values of cell j.
+template <int RECON, int FV>
+__device__ __forceinline__ void recon5(double f0, double f1, double f2, double f3, double f4,
+                                       double &fl, double &fr)
+{
+  if constexpr (RECON == RC_CONST) {
+    fl = f2; fr = f2;
+  } else if constexpr (RECON == RC_PLM_MINMOD) {
+    const double s = minmod_slope(f2 - f1, f3 - f2);
+    fl = f2 - 0.5 * s; fr = f2 + 0.5 * s;
+  } else if constexpr (RECON == RC_PLM_MC) {
+    const double s = mc_slope(f2 - f1, f3 - f2);
+    fl = f2 - 0.5 * s; fr = f2 + 0.5 * s;
+  } else {
+    const double s = mc_slope(f2 - f1, f3 - f2);
+    double sp, sm;
+    const double pr = weno_z_face<FV>(f0, f1, f2, f3, f4, sp);
+    const double pl = weno_z_face<FV>(f4, f3, f2, f1, f0, sm);   // mirror x -> -x
+    double sigma = 2.0 * sp * sm / (sp + sm);
+    sigma = sigma > 0.0 ? sigma : 0.0;                            // also maps NaN to 0
+    sigma = sigma < 1.0 ? sigma : 1.0;
+    fr = sigma * pr + (1.0 - sigma) * (f2 + 0.5 * s);
+    fl = sigma * pl + (1.0 - sigma) * (f2 - 0.5 * s);
+  }
+}
+
+}  // namespace grmhd

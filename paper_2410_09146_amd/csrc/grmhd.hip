@@ -1,0 +1,711 @@
+// libgrmhd.so: host side of the C ABI declared in include/grmhd.h, plus the
+// gfx950 kernels (kernels.h).  The host builds, once per pack, everything the
+// kernels need as flat device tables: block descriptors, 1-D coordinate
+// tables, ghost-zone gather maps and tile / chunk work lists, all placed in
+// the caller's workspace.  Each public call then only enqueues kernels on
+// the pack's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/grmhd.h"
+#include "kernels.h"
+
+using namespace grmhd;
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Everything derived from a descriptor on the host.
+struct Plan {
+  int nb = 0, ng = 4;
+  long long nct = 0;
+  std::vector<long long> off;
+  std::vector<BlockInfo> blocks;
+  std::vector<double> rc, rf, sc, cc, sf, cf;
+  std::vector<int4> tiles[3];
+  std::vector<int2> planes[3];
+  std::vector<int2> ch_int, ch_ext, ch_bcc;
+  std::vector<GhostP> gP;
+  std::vector<GhostB> gB;
+  int active[3] = {1, 1, 1};
+  double dxmin = 0.0;
+  // workspace carve-up (byte offsets)
+  size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_tiles[3], o_planes[3], o_chi, o_che,
+      o_chb, o_gP, o_gB, o_part, o_res, o_mlp, total;
+};
+
+int fail(const std::string &m, int code)
+{
+  g_err = m;
+  return code;
+}
+
+int validate(const grmhd_pack_desc *d)
+{
+  if (!d) return fail("null descriptor", GRMHD_E_INVALID);
+  if (d->nblocks < 1 || d->nblocks > (1 << 20)) return fail("nblocks out of range", GRMHD_E_INVALID);
+  if (d->ng != 4) return fail("ng must be 4", GRMHD_E_UNSUPPORTED);
+  if (d->recon < 0 || d->recon > 3) return fail("bad recon", GRMHD_E_INVALID);
+  if (d->riemann < 0 || d->riemann > 1) return fail("bad riemann", GRMHD_E_INVALID);
+  if (d->precision != GRMHD_PREC_FP64) return fail("only FP64 precision", GRMHD_E_UNSUPPORTED);
+  if (!d->nx || !d->lloc) return fail("null nx/lloc", GRMHD_E_INVALID);
+  for (int s = 0; s < 6; ++s)
+    if (d->bc[s] < 0 || d->bc[s] > 3) return fail("bad boundary kind", GRMHD_E_INVALID);
+  for (int dd = 0; dd < 3; ++dd) {
+    if (d->root_nx[dd] < 1) return fail("root_nx < 1", GRMHD_E_SHAPE);
+    if (!(d->xmax[dd] > d->xmin[dd])) return fail("xmax <= xmin", GRMHD_E_SHAPE);
+    if ((d->bc[2 * dd] == GRMHD_BC_PERIODIC) != (d->bc[2 * dd + 1] == GRMHD_BC_PERIODIC))
+      return fail("periodic must pair", GRMHD_E_INVALID);
+  }
+  if ((d->bc[0] == GRMHD_BC_POLAR) || (d->bc[1] == GRMHD_BC_POLAR) ||
+      (d->bc[4] == GRMHD_BC_POLAR) || (d->bc[5] == GRMHD_BC_POLAR))
+    return fail("polar boundaries only along x2", GRMHD_E_UNSUPPORTED);
+  for (int b = 0; b < d->nblocks; ++b) {
+    const int lev = d->level ? d->level[b] : 0;
+    if (lev != 0) return fail("refined blocks not supported by this build", GRMHD_E_UNSUPPORTED);
+    for (int dd = 0; dd < 3; ++dd) {
+      const int n = d->nx[3 * b + dd], l = d->lloc[3 * b + dd];
+      if (n < 1 || n > 4096) return fail("block size out of range", GRMHD_E_SHAPE);
+      if (l < 0 || l + n > d->root_nx[dd]) return fail("block outside the domain", GRMHD_E_SHAPE);
+      if (n < d->ng && d->root_nx[dd] != n) return fail("split blocks need n >= ng", GRMHD_E_SHAPE);
+    }
+  }
+  // blocks must tile the domain exactly once
+  long long vol = 0;
+  for (int b = 0; b < d->nblocks; ++b)
+    vol += (long long)d->nx[3 * b] * d->nx[3 * b + 1] * d->nx[3 * b + 2];
+  if (vol != (long long)d->root_nx[0] * d->root_nx[1] * d->root_nx[2])
+    return fail("blocks do not cover the domain", GRMHD_E_SHAPE);
+  return GRMHD_OK;
+}
+
+void layout(const grmhd_pack_desc *d, std::vector<long long> &off, long long &nct)
+{
+  off.resize(d->nblocks);
+  long long o = 0;
+  for (int b = 0; b < d->nblocks; ++b) {
+    off[b] = o;
+    long long c = 1;
+    for (int dd = 0; dd < 3; ++dd) c *= d->nx[3 * b + dd] + 2 * d->ng;
+    o += (c + 31) / 32 * 32;
+  }
+  nct = o;
+}
+
+// owner lookup of level-0 cells: granularity g cells
+struct Owner {
+  int g[3], dims[3];
+  std::vector<int> id;
+  int at(const int c[3]) const
+  {
+    return id[(c[0] / g[0]) + (size_t)dims[0] * ((c[1] / g[1]) + (size_t)dims[1] * (c[2] / g[2]))];
+  }
+};
+
+int gcd(int a, int b) { return b ? gcd(b, a % b) : a; }
+
+int build_plan(const grmhd_pack_desc *d, Plan &p)
+{
+  int rc = validate(d);
+  if (rc) return rc;
+  p.nb = d->nblocks;
+  p.ng = d->ng;
+  const int ng = d->ng;
+  layout(d, p.off, p.nct);
+  double dx[3];
+  for (int dd = 0; dd < 3; ++dd) dx[dd] = (d->xmax[dd] - d->xmin[dd]) / d->root_nx[dd];
+  p.dxmin = 1e300;
+  for (int dd = 0; dd < 3; ++dd) {
+    p.active[dd] = d->root_nx[dd] > 1;
+    if (p.active[dd]) p.dxmin = std::min(p.dxmin, dx[dd]);
+  }
+  if (p.dxmin == 1e300) p.dxmin = dx[0];
+
+  // owner grid
+  Owner own;
+  for (int dd = 0; dd < 3; ++dd) {
+    int g = d->root_nx[dd];
+    for (int b = 0; b < p.nb; ++b) g = gcd(g, gcd(d->nx[3 * b + dd], d->lloc[3 * b + dd]));
+    own.g[dd] = g;
+    own.dims[dd] = d->root_nx[dd] / g;
+  }
+  own.id.assign((size_t)own.dims[0] * own.dims[1] * own.dims[2], -1);
+  for (int b = 0; b < p.nb; ++b) {
+    int lo[3], hi[3];
+    for (int dd = 0; dd < 3; ++dd) {
+      lo[dd] = d->lloc[3 * b + dd] / own.g[dd];
+      hi[dd] = (d->lloc[3 * b + dd] + d->nx[3 * b + dd]) / own.g[dd];
+    }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) {
+          int &o = own.id[x + (size_t)own.dims[0] * (y + (size_t)own.dims[1] * z)];
+          if (o >= 0) return fail("blocks overlap", GRMHD_E_SHAPE);
+          o = b;
+        }
+  }
+
+  // blocks and coordinate tables
+  p.blocks.resize(p.nb);
+  const bool plo = d->bc[2] == GRMHD_BC_POLAR, phi = d->bc[3] == GRMHD_BC_POLAR;
+  const int N2 = d->root_nx[1];
+  for (int b = 0; b < p.nb; ++b) {
+    BlockInfo &bi = p.blocks[b];
+    std::memset(&bi, 0, sizeof bi);
+    for (int dd = 0; dd < 3; ++dd) {
+      bi.n[dd] = d->nx[3 * b + dd];
+      bi.s[dd] = bi.n[dd] + 2 * ng;
+      bi.dx[dd] = dx[dd];
+    }
+    bi.off = p.off[b];
+    bi.tab1 = (int)p.rc.size();
+    bi.tab2 = (int)p.sc.size();
+    for (int i = 0; i < bi.s[0]; ++i) {
+      const int g = d->lloc[3 * b] + i - ng;
+      p.rc.push_back(std::exp(d->xmin[0] + ((double)g + 0.5) * dx[0]));
+      p.rf.push_back(std::exp(d->xmin[0] + ((double)g) * dx[0]));
+    }
+    bi.pole_lo = bi.pole_hi = -1;
+    for (int j = 0; j < bi.s[1]; ++j) {
+      int g = d->lloc[3 * b + 1] + j - ng;
+      if (plo && g < 0) g = -1 - g;
+      if (phi && g >= N2) g = 2 * N2 - 1 - g;
+      const double th = d->xmin[1] + ((double)g + 0.5) * dx[1];
+      p.sc.push_back(std::sin(th));
+      p.cc.push_back(std::cos(th));
+      int gf = d->lloc[3 * b + 1] + j - ng;
+      if (plo && gf < 0) gf = -gf;
+      if (phi && gf > N2) gf = 2 * N2 - gf;
+      const double tf = d->xmin[1] + ((double)gf) * dx[1];
+      const bool pole = (plo && gf == 0) || (phi && gf == N2);
+      p.sf.push_back(pole ? 0.0 : std::sin(tf));
+      p.cf.push_back(std::cos(tf));
+      if (plo && d->lloc[3 * b + 1] + j - ng == 0) bi.pole_lo = j;
+      if (phi && d->lloc[3 * b + 1] + j - ng == N2) bi.pole_hi = j;
+    }
+  }
+
+  // work lists
+  for (int b = 0; b < p.nb; ++b) {
+    const BlockInfo &bi = p.blocks[b];
+    for (int D = 0; D < 3; ++D) {
+      const int AX = D == 0 ? 1 : 0, BX = D == 2 ? 1 : 2;
+      for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
+        for (int a0 = ng - 1; a0 <= ng + bi.n[AX]; a0 += TA)
+          for (int f0 = ng; f0 < ng + bi.n[D]; f0 += TD) {
+            int o[3];
+            o[D] = f0; o[AX] = a0; o[BX] = kb;
+            p.tiles[D].push_back(make_int4(b, o[0], o[1], o[2]));
+          }
+      const int np = (bi.n[AX] + 2) * (bi.n[BX] + 2);
+      for (int s = 0; s < np; s += 256) p.planes[D].push_back(make_int2(b, s));
+    }
+    const long long ni = (long long)bi.n[0] * bi.n[1] * bi.n[2];
+    for (long long s = 0; s < ni; s += 256) p.ch_int.push_back(make_int2(b, (int)s));
+    const long long ne = (long long)(bi.n[0] + 1) * (bi.n[1] + 1) * (bi.n[2] + 1);
+    for (long long s = 0; s < ne; s += 256) p.ch_ext.push_back(make_int2(b, (int)s));
+    const long long nbc = (long long)(bi.s[0] - 1) * (bi.s[1] - 1) * (bi.s[2] - 1);
+    for (long long s = 0; s < nbc; s += 256) p.ch_bcc.push_back(make_int2(b, (int)s));
+  }
+
+  // ghost maps.  Per axis: global index -> (source global index, flags);
+  // returns 0 interior, 1 mapped, -1 fixed (leave).
+  auto map_axis = [&](int dd, int g, bool normal, int &src, int &flip, int &ofl) -> int {
+    const int N = d->root_nx[dd];
+    const int hiN = normal ? N : N - 1;
+    flip = 0; ofl = 0;
+    if (g >= 0 && g <= hiN) { src = g; return 0; }
+    const bool low = g < 0;
+    const int bc = d->bc[2 * dd + (low ? 0 : 1)];
+    switch (bc) {
+      case GRMHD_BC_PERIODIC: src = ((g % N) + N) % N; return 1;   // face N is face 0
+      case GRMHD_BC_OUTFLOW: src = low ? 0 : hiN; ofl = low ? 1 : 2; return 1;
+      case GRMHD_BC_POLAR:
+        src = normal ? (low ? -g : 2 * N - g) : (low ? -1 - g : 2 * N - 1 - g);
+        flip = 1;
+        return 1;
+      default: return -1;
+    }
+  };
+  for (int b = 0; b < p.nb; ++b) {
+    const BlockInfo &bi = p.blocks[b];
+    const int *ll = &d->lloc[3 * b];
+    for (int comp = -1; comp < 3; ++comp) {   // -1: cell-centred P
+      for (int k = 0; k < bi.s[2]; ++k)
+        for (int j = 0; j < bi.s[1]; ++j)
+          for (int i = 0; i < bi.s[0]; ++i) {
+            const int idx[3] = {i, j, k};
+            bool ghost = false;
+            for (int dd = 0; dd < 3; ++dd) {
+              const int hi = (comp == dd) ? ng + bi.n[dd] : ng + bi.n[dd] - 1;
+              if (idx[dd] < ng || idx[dd] > hi) ghost = true;
+            }
+            if (!ghost) continue;
+            int src[3], flags = 0, flipn = 0;
+            bool fixed = false;
+            for (int dd = 0; dd < 3; ++dd) {
+              int fl, ofl;
+              const int g = ll[dd] + idx[dd] - ng;
+              const int r = map_axis(dd, g, comp == dd, src[dd], fl, ofl);
+              if (r < 0) fixed = true;
+              if (fl) { flags |= 1 << dd; if (comp == dd) flipn = 1; }
+              if (ofl & 1) flags |= 8 << (2 * dd);
+              if (ofl & 2) flags |= 16 << (2 * dd);
+            }
+            if (fixed) continue;
+            // owning block of the source (faces on the upper domain edge
+            // belong to the cell below)
+            int cell[3];
+            for (int dd = 0; dd < 3; ++dd)
+              cell[dd] = std::min(src[dd], d->root_nx[dd] - 1);
+            const int ob = own.at(cell);
+            if (ob < 0) return fail("ghost source not covered", GRMHD_E_SHAPE);
+            const BlockInfo &sb = p.blocks[ob];
+            long long lin = 0, mul = 1;
+            for (int dd = 0; dd < 3; ++dd) {
+              lin += mul * (src[dd] - d->lloc[3 * ob + dd] + ng);
+              mul *= sb.s[dd];
+            }
+            const long long dst = bi.off + i + (long long)bi.s[0] * (j + (long long)bi.s[1] * k);
+            if (comp < 0) {
+              GhostP gp{dst, sb.off + lin, flags, 0};
+              p.gP.push_back(gp);
+            } else {
+              GhostB gb{dst, sb.off + lin, comp, flipn};
+              p.gB.push_back(gb);
+            }
+          }
+    }
+  }
+
+  // every gather index must stay inside the pack's planes
+  for (const GhostP &g : p.gP)
+    if (g.dst < 0 || g.dst >= p.nct || g.src < 0 || g.src >= p.nct)
+      return fail("internal: ghost map out of range", GRMHD_E_SHAPE);
+  for (const GhostB &g : p.gB)
+    if (g.dst < 0 || g.dst >= p.nct || g.src < 0 || g.src >= p.nct || g.comp < 0 || g.comp > 2)
+      return fail("internal: face ghost map out of range", GRMHD_E_SHAPE);
+
+  // workspace carve-up
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o += align_up(bytes); return r; };
+  p.o_F = take(sizeof(double) * 24 * (size_t)p.nct);
+  p.o_Bcc = take(sizeof(double) * 3 * (size_t)p.nct);
+  p.o_flags = take((size_t)p.nct);
+  p.o_iters = take((size_t)p.nct);
+  p.o_blocks = take(sizeof(BlockInfo) * p.nb);
+  p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
+  for (int D = 0; D < 3; ++D) p.o_tiles[D] = take(sizeof(int4) * p.tiles[D].size());
+  for (int D = 0; D < 3; ++D) p.o_planes[D] = take(sizeof(int2) * p.planes[D].size());
+  p.o_chi = take(sizeof(int2) * p.ch_int.size());
+  p.o_che = take(sizeof(int2) * p.ch_ext.size());
+  p.o_chb = take(sizeof(int2) * p.ch_bcc.size());
+  p.o_gP = take(sizeof(GhostP) * std::max<size_t>(p.gP.size(), 1));
+  p.o_gB = take(sizeof(GhostB) * std::max<size_t>(p.gB.size(), 1));
+  p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
+  p.o_res = take(sizeof(double) * 32);
+  p.o_mlp = take(sizeof(float) * (size_t)p.nct);
+  p.total = o;
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+struct grmhd_pack {
+  Plan plan;
+  grmhd_pack_desc desc;
+  grmhd_state_ptrs st;
+  hipStream_t stream;
+  char *ws;
+  std::string err;
+  bool mlp_bound = false;
+  KArgs args() const
+  {
+    KArgs a;
+    a.P = (double *)st.P; a.Bf = (double *)st.Bf; a.U = (double *)st.U;
+    a.U0 = (double *)st.U0; a.Bf0 = (double *)st.Bf0;
+    a.F = (double *)(ws + plan.o_F);
+    a.Bcc = (double *)(ws + plan.o_Bcc);
+    a.flags = (int8_t *)(ws + plan.o_flags);
+    a.iters = (uint8_t *)(ws + plan.o_iters);
+    a.blocks = (const BlockInfo *)(ws + plan.o_blocks);
+    const double *t = (const double *)(ws + plan.o_tab);
+    const size_t n1 = plan.rc.size(), n2 = plan.sc.size();
+    a.tab.rc = t; a.tab.rf = t + n1;
+    a.tab.sc = t + 2 * n1; a.tab.cc = t + 2 * n1 + n2;
+    a.tab.sf = t + 2 * n1 + 2 * n2; a.tab.cf = t + 2 * n1 + 3 * n2;
+    a.met.M = 1.0; a.met.a = 0.0;
+    std::memset(&a.eos, 0, sizeof a.eos);
+    a.nct = plan.nct;
+    a.ng = plan.ng;
+    for (int d = 0; d < 3; ++d) a.active[d] = plan.active[d];
+    return a;
+  }
+};
+
+namespace {
+
+int perr(grmhd_pack *p, const std::string &m, int code)
+{
+  if (p) p->err = m;
+  g_err = m;
+  return code;
+}
+
+#define HIPCHK(p, x)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return perr(p, std::string(#x ": ") + hipGetErrorString(e_), GRMHD_E_HIP);      \
+  } while (0)
+
+#define LAUNCHCHK(p)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = hipGetLastError();                                                \
+    if (e_ != hipSuccess)                                                             \
+      return perr(p, std::string("launch: ") + hipGetErrorString(e_), GRMHD_E_HIP);   \
+  } while (0)
+
+int check_metric(grmhd_pack *p, const grmhd_metric *m)
+{
+  if (!m) return perr(p, "null metric", GRMHD_E_INVALID);
+  if (m->kind != GRMHD_METRIC_MINKOWSKI && m->kind != GRMHD_METRIC_KS_LOGSPH)
+    return perr(p, "bad metric kind", GRMHD_E_INVALID);
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH && !(std::fabs(m->a) < m->M))
+    return perr(p, "need |a| < M", GRMHD_E_INVALID);
+  return 0;
+}
+
+void fill_eos(KArgs &a, const grmhd_eos *e)
+{
+  a.eos.gam = e->gamma;
+  a.eos.rho_flr0 = e->rho_flr0; a.eos.rho_flr_pow = e->rho_flr_pow;
+  a.eos.u_flr0 = e->u_flr0; a.eos.u_flr_pow = e->u_flr_pow;
+  a.eos.W_max = e->W_max;
+  a.eos.tol = e->c2p_tol > 0 ? e->c2p_tol : 1e-14;
+  a.eos.max_iter = e->c2p_max_iter > 0 ? e->c2p_max_iter : 40;
+}
+
+int check_eos(grmhd_pack *p, const grmhd_eos *e)
+{
+  if (!e) return perr(p, "null eos", GRMHD_E_INVALID);
+  if (!(e->gamma > 1.0)) return perr(p, "gamma must exceed 1", GRMHD_E_INVALID);
+  if (!(e->W_max > 1.0)) return perr(p, "W_max must exceed 1", GRMHD_E_INVALID);
+  return 0;
+}
+
+template <typename T>
+const T *dptr(const grmhd_pack *p, size_t off) { return (const T *)(p->ws + off); }
+
+// ---- templated launch helpers (host dispatch over compile-time options)
+
+template <int MK, int D, int RC, int FV, int RS>
+void launch_flux(grmhd_pack *p, const KArgs &a)
+{
+  const Plan &pl = p->plan;
+  if (!pl.tiles[D].empty())
+    hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS>), dim3(pl.tiles[D].size()), dim3(256), 0,
+                       p->stream, a, dptr<int4>(p, pl.o_tiles[D]));
+  if (!pl.planes[D].empty())
+    hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS>), dim3(pl.planes[D].size()), dim3(256),
+                       0, p->stream, a, dptr<int2>(p, pl.o_planes[D]));
+}
+
+template <int MK, int RC, int FV, int RS>
+void launch_flux3(grmhd_pack *p, const KArgs &a)
+{
+  launch_flux<MK, 0, RC, FV, RS>(p, a);
+  launch_flux<MK, 1, RC, FV, RS>(p, a);
+  launch_flux<MK, 2, RC, FV, RS>(p, a);
+}
+
+template <int MK, int RC, int FV>
+void launch_flux_rs(grmhd_pack *p, const KArgs &a, int rs)
+{
+  if (rs == RS_HLL) launch_flux3<MK, RC, FV, RS_HLL>(p, a);
+  else launch_flux3<MK, RC, FV, RS_LLF>(p, a);
+}
+
+template <int MK>
+void launch_flux_all(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs)
+{
+  switch (rc) {
+    case RC_CONST: launch_flux_rs<MK, RC_CONST, 0>(p, a, rs); break;
+    case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0>(p, a, rs); break;
+    case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0>(p, a, rs); break;
+    default:
+      if (fv) launch_flux_rs<MK, RC_WENO, 1>(p, a, rs);
+      else launch_flux_rs<MK, RC_WENO, 0>(p, a, rs);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_abi_version(void) { return GRMHD_ABI_VERSION; }
+
+int grmhd_layout(const grmhd_pack_desc *desc, long long *offsets, long long *ncell_total)
+{
+  int rc = validate(desc);
+  if (rc) return rc;
+  std::vector<long long> off;
+  long long n;
+  layout(desc, off, n);
+  if (offsets)
+    for (int b = 0; b < desc->nblocks; ++b) offsets[b] = off[b];
+  if (ncell_total) *ncell_total = n;
+  return GRMHD_OK;
+}
+
+size_t grmhd_pack_workspace_bytes(const grmhd_pack_desc *desc)
+{
+  Plan p;
+  if (build_plan(desc, p)) return 0;
+  return p.total;
+}
+
+int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state,
+                      void *workspace, size_t ws_bytes, void *hip_stream, grmhd_pack **out)
+{
+  if (!out) return fail("null out", GRMHD_E_INVALID);
+  *out = nullptr;
+  if (!state || !state->P || !state->Bf || !state->U || !state->U0 || !state->Bf0)
+    return fail("null state pointer", GRMHD_E_INVALID);
+  if (!workspace || ((uintptr_t)workspace % ALIGN)) return fail("workspace null or unaligned", GRMHD_E_INVALID);
+  grmhd_pack *p = new grmhd_pack();
+  int rc = build_plan(desc, p->plan);
+  if (rc) { delete p; return rc; }
+  if (ws_bytes < p->plan.total) { delete p; return fail("workspace too small", GRMHD_E_SHAPE); }
+  p->desc = *desc;
+  p->desc.nx = p->desc.level = p->desc.lloc = nullptr;
+  p->st = *state;
+  p->stream = (hipStream_t)hip_stream;
+  p->ws = (char *)workspace;
+  const Plan &pl = p->plan;
+  auto up = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(p->ws + off, src, bytes, hipMemcpyHostToDevice, p->stream);
+  };
+  std::vector<double> tab;
+  tab.insert(tab.end(), pl.rc.begin(), pl.rc.end());
+  tab.insert(tab.end(), pl.rf.begin(), pl.rf.end());
+  tab.insert(tab.end(), pl.sc.begin(), pl.sc.end());
+  tab.insert(tab.end(), pl.cc.begin(), pl.cc.end());
+  tab.insert(tab.end(), pl.sf.begin(), pl.sf.end());
+  tab.insert(tab.end(), pl.cf.begin(), pl.cf.end());
+  hipError_t e = hipSuccess;
+  if (!e) e = up(pl.o_blocks, pl.blocks.data(), sizeof(BlockInfo) * pl.blocks.size());
+  if (!e) e = up(pl.o_tab, tab.data(), sizeof(double) * tab.size());
+  for (int D = 0; D < 3; ++D) {
+    if (!e) e = up(pl.o_tiles[D], pl.tiles[D].data(), sizeof(int4) * pl.tiles[D].size());
+    if (!e) e = up(pl.o_planes[D], pl.planes[D].data(), sizeof(int2) * pl.planes[D].size());
+  }
+  if (!e) e = up(pl.o_chi, pl.ch_int.data(), sizeof(int2) * pl.ch_int.size());
+  if (!e) e = up(pl.o_che, pl.ch_ext.data(), sizeof(int2) * pl.ch_ext.size());
+  if (!e) e = up(pl.o_chb, pl.ch_bcc.data(), sizeof(int2) * pl.ch_bcc.size());
+  if (!e) e = up(pl.o_gP, pl.gP.data(), sizeof(GhostP) * pl.gP.size());
+  if (!e) e = up(pl.o_gB, pl.gB.data(), sizeof(GhostB) * pl.gB.size());
+  // flags / iteration counters / flux scratch start defined
+  if (!e) e = hipMemsetAsync(p->ws + pl.o_flags, 0, 2 * align_up(pl.nct), p->stream);
+  if (!e) e = hipMemsetAsync(p->ws + pl.o_F, 0, sizeof(double) * 24 * (size_t)pl.nct, p->stream);
+  // host vectors must outlive the async copies
+  if (!e) e = hipStreamSynchronize(p->stream);
+  if (e) {
+    std::string m = std::string("upload: ") + hipGetErrorString(e);
+    delete p;
+    return fail(m, GRMHD_E_HIP);
+  }
+  *out = p;
+  return GRMHD_OK;
+}
+
+int grmhd_pack_destroy(grmhd_pack *p)
+{
+  if (!p) return GRMHD_E_INVALID;
+  (void)hipStreamSynchronize(p->stream);
+  delete p;
+  return GRMHD_OK;
+}
+
+int grmhd_bind_state(grmhd_pack *p, const grmhd_state_ptrs *state)
+{
+  if (!p || !state || !state->P || !state->Bf || !state->U || !state->U0 || !state->Bf0)
+    return perr(p, "null pointer", GRMHD_E_INVALID);
+  p->st = *state;
+  return GRMHD_OK;
+}
+
+int grmhd_fill_ghosts(grmhd_pack *p, const grmhd_metric *m)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  const Plan &pl = p->plan;
+  if (!pl.gP.empty())
+    hipLaunchKernelGGL(k_ghost_P, dim3((pl.gP.size() + 255) / 256), dim3(256), 0, p->stream, a,
+                       dptr<GhostP>(p, pl.o_gP), (int)pl.gP.size());
+  if (!pl.gB.empty())
+    hipLaunchKernelGGL(k_ghost_B, dim3((pl.gB.size() + 255) / 256), dim3(256), 0, p->stream, a,
+                       dptr<GhostB>(p, pl.o_gB), (int)pl.gB.size());
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
+    hipLaunchKernelGGL(k_bcc<MK_KS>, dim3(pl.ch_bcc.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chb));
+  else
+    hipLaunchKernelGGL(k_bcc<MK_MINK>, dim3(pl.ch_bcc.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chb));
+  LAUNCHCHK(p);
+  return GRMHD_OK;
+}
+
+int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, double dt,
+                const double rk[3])
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  if (!rk) return perr(p, "null rk_coeffs", GRMHD_E_INVALID);
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  fill_eos(a, eos);
+  const Plan &pl = p->plan;
+  const int rc = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rc, fv, rs);
+  else launch_flux_all<MK_MINK>(p, a, rc, fv, rs);
+  LAUNCHCHK(p);
+  const double *dtd = dptr<double>(p, pl.o_res);
+  const int save = rk[1] == 0.0;
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
+    hipLaunchKernelGGL(k_update<MK_KS>, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  else
+    hipLaunchKernelGGL(k_update<MK_MINK>, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  LAUNCHCHK(p);
+  return GRMHD_OK;
+}
+
+int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  if (guess < 0 || guess > 2) return perr(p, "bad guess kind", GRMHD_E_INVALID);
+  if (guess == GRMHD_GUESS_MLP && !p->mlp_bound)
+    return perr(p, "no learned guess bound", GRMHD_E_INVALID);
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  fill_eos(a, eos);
+  const Plan &pl = p->plan;
+  const dim3 g(pl.ch_int.size());
+  const int2 *ch = dptr<int2>(p, pl.o_chi);
+  const float *mlp = dptr<float>(p, pl.o_mlp);
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH) {
+    if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
+    else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK_KS, 1>), g, dim3(256), 0, p->stream, a, ch, mlp);
+    else hipLaunchKernelGGL((k_c2p<MK_KS, 2>), g, dim3(256), 0, p->stream, a, ch, mlp);
+  } else {
+    if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_MINK, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
+    else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK_MINK, 1>), g, dim3(256), 0, p->stream, a, ch, mlp);
+    else hipLaunchKernelGGL((k_c2p<MK_MINK, 2>), g, dim3(256), 0, p->stream, a, ch, mlp);
+  }
+  LAUNCHCHK(p);
+  return GRMHD_OK;
+}
+
+int grmhd_prim_to_cons(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  fill_eos(a, eos);
+  const Plan &pl = p->plan;
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
+    hipLaunchKernelGGL(k_p2c<MK_KS>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chi));
+  else
+    hipLaunchKernelGGL(k_p2c<MK_MINK>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chi));
+  LAUNCHCHK(p);
+  return GRMHD_OK;
+}
+
+int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, double cfl,
+                     grmhd_reduction_out *out)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  fill_eos(a, eos);
+  const Plan &pl = p->plan;
+  double *part = (double *)(p->ws + pl.o_part);
+  double *res = (double *)(p->ws + pl.o_res);
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
+    hipLaunchKernelGGL(k_reduce<MK_KS>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chi), part);
+  else
+    hipLaunchKernelGGL(k_reduce<MK_MINK>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_chi), part);
+  hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(256), 0, p->stream, (const double *)part,
+                     (int)pl.ch_int.size(), cfl, pl.dxmin, res);
+  LAUNCHCHK(p);
+  if (out) {
+    double h[16];
+    HIPCHK(p, hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(p, hipStreamSynchronize(p->stream));
+    out->dt = h[0];
+    out->divb_rel = h[1];
+    out->divb_max = h[2];
+    for (int v = 0; v < 5; ++v) out->totals[v] = h[3 + v];
+    out->c2p_fail = (long long)h[8];
+    out->floor_hits = (long long)h[9];
+    long long ncell = 0, nwave = 0;
+    for (int b = 0; b < pl.nb; ++b) {
+      const long long nb = (long long)pl.blocks[b].n[0] * pl.blocks[b].n[1] * pl.blocks[b].n[2];
+      ncell += nb;
+    }
+    for (const int2 &c : pl.ch_int) {
+      const BlockInfo &b = pl.blocks[c.x];
+      const long long nb = (long long)b.n[0] * b.n[1] * b.n[2];
+      const long long live = std::min<long long>(256, nb - c.y);
+      nwave += (live + 63) / 64;
+    }
+    out->c2p_iter_mean = ncell ? h[10] / ncell : 0.0;
+    out->c2p_iter_wavemax_mean = nwave ? h[11] / nwave : 0.0;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_debug_ptrs(grmhd_pack *p, void **flags, void **iters, void **flux)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (flags) *flags = p->ws + p->plan.o_flags;
+  if (iters) *iters = p->ws + p->plan.o_iters;
+  if (flux) *flux = p->ws + p->plan.o_F;
+  return GRMHD_OK;
+}
+
+const char *grmhd_last_error(const grmhd_pack *p)
+{
+  if (p && !p->err.empty()) return p->err.c_str();
+  return g_err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,702 @@
+// gfx950 kernels of the GRMHD stage.  Included once, by grmhd.hip.
+//
+//   k_ghost_P / k_ghost_B   gather ghost zones through precomputed maps
+//   k_bcc                   cell-centred B from the face field
+//   k_flux<D>               LDS-staged 16x16 face tiles: reconstruct -> Riemann
+//   k_flux_plane<D>         the last face plane along D (one thread per face)
+//   k_update                flux divergence + sources + CT (edge-averaged EMF)
+//                           + Runge-Kutta combination, one thread per cell
+//   k_c2p                   safeguarded Newton inversion + floors
+//   k_p2c                   U from P (initialisation)
+//   k_reduce / k_reduce_fin CFL dt, div B, conserved totals, inversion stats
+#pragma once
+#include "dev.h"
+
+namespace grmhd {
+
+struct KArgs {
+  double *P, *Bf, *U, *U0, *Bf0;
+  double *F;            // [3][8][nct] densitized face fluxes
+  double *Bcc;          // [3][nct] cell-centred undensitized B
+  int8_t *flags;
+  uint8_t *iters;
+  const BlockInfo *blocks;
+  Tables tab;
+  MetricP met;
+  EosP eos;
+  long long nct;
+  int ng;
+  int active[3];        // directions with more than one cell (CFL sum)
+};
+
+struct GhostP { long long dst, src; int flags, pad; };
+struct GhostB { long long dst, src; int comp, flip; };
+
+// ------------------------------------------------------------------ ghosts
+
+__global__ __launch_bounds__(256) void k_ghost_P(KArgs a, const GhostP *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostP g = map[e];
+  double v[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = a.P[q * a.nct + g.src];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (g.flags & (8 << (2 * d))) v[1 + d] = v[1 + d] > 0.0 ? 0.0 : v[1 + d];   // lo outflow
+    if (g.flags & (16 << (2 * d))) v[1 + d] = v[1 + d] < 0.0 ? 0.0 : v[1 + d];  // hi outflow
+    if (g.flags & (1 << d)) v[1 + d] = -v[1 + d];                                // mirror
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.P[q * a.nct + g.dst] = v[q];
+}
+
+__global__ __launch_bounds__(256) void k_ghost_B(KArgs a, const GhostB *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostB g = map[e];
+  const double v = a.Bf[g.comp * a.nct + g.src];
+  a.Bf[g.comp * a.nct + g.dst] = g.flip ? -v : v;
+}
+
+// ------------------------------------------------------------ cell-centred B
+
+template <int MK>
+__device__ __forceinline__ Geo geo_center(const KArgs &a, const BlockInfo &b, int i, int j)
+{
+  return geo_at<MK>(a.tab, a.met, b.tab1 + i, false, b.tab2 + j, false);
+}
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_bcc(KArgs a, const int2 *__restrict__ chunks)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  const int m1 = b.s[0] - 1, m2 = b.s[1] - 1;
+  if (e >= m1 * m2 * (b.s[2] - 1)) return;
+  const int i = e % m1, j = (e / m1) % m2, k = e / (m1 * m2);
+  const long long c = b.off + i + (long long)b.s[0] * (j + (long long)b.s[1] * k);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const Geo G = geo_center<MK>(a, b, i, j);
+  const double h = 0.5 / G.sqrtg;
+  a.Bcc[c] = h * (a.Bf[c] + a.Bf[c + 1]);
+  a.Bcc[a.nct + c] = h * (a.Bf[a.nct + c] + a.Bf[a.nct + c + sj]);
+  a.Bcc[2 * a.nct + c] = h * (a.Bf[2 * a.nct + c] + a.Bf[2 * a.nct + c + sk]);
+}
+
+// ------------------------------------------------------------------- fluxes
+
+constexpr int TD = 16, TA = 16, NS = TD + 5, NR = TD + 1, NV = 7;
+
+// transverse field components reconstructed along D
+template <int D> __device__ constexpr int tcomp(int w) { return D == 0 ? 1 + w : (D == 1 ? 2 * w : w); }
+
+template <int MK, int D>
+__device__ __forceinline__ Geo geo_face(const KArgs &a, const BlockInfo &b, int i, int j)
+{
+  return geo_at<MK>(a.tab, a.met, b.tab1 + i, D == 0, b.tab2 + j, D == 1);
+}
+
+template <int D>
+__device__ __forceinline__ Prim make_prim(const double q[7], double bn)
+{
+  Prim p;
+  p.rho = q[0]; p.u1 = q[1]; p.u2 = q[2]; p.u3 = q[3]; p.ie = q[4];
+  if constexpr (D == 0) { p.B1 = bn; p.B2 = q[5]; p.B3 = q[6]; }
+  if constexpr (D == 1) { p.B1 = q[5]; p.B2 = bn; p.B3 = q[6]; }
+  if constexpr (D == 2) { p.B1 = q[5]; p.B2 = q[6]; p.B3 = bn; }
+  return p;
+}
+
+template <int MK, int D, int RS>
+__device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo &b, int i, int j,
+                                                long long c, const double qL[7],
+                                                const double qR[7])
+{
+  if (D == 1 && (j == b.pole_lo || j == b.pole_hi)) {   // sqrt(-g) = 0 on the axis
+#pragma unroll
+    for (int v = 0; v < 8; ++v) a.F[(D * 8 + v) * a.nct + c] = 0.0;
+    return;
+  }
+  const Geo G = geo_face<MK, D>(a, b, i, j);
+  const double bn = a.Bf[D * a.nct + c] / G.sqrtg;
+  const Prim L = make_prim<D>(qL, bn), R = make_prim<D>(qR, bn);
+  double out[8];
+  riemann<D, RS>(G, a.eos.gam, L, R, out);
+#pragma unroll
+  for (int v = 0; v < 8; ++v) a.F[(D * 8 + v) * a.nct + c] = out[v];
+}
+
+__device__ __forceinline__ void positivity(int v, double f2, double &l, double &r)
+{
+  if (v == 0 || v == 4) {
+    if (!(l > 0.0) || !isfinite(l)) l = f2;
+    if (!(r > 0.0) || !isfinite(r)) r = f2;
+  }
+}
+
+// Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
+// else x1), one row along the third axis.  Tile origin = lower face of the
+// tile in block-local (i, j, k).
+template <int MK, int D, int RECON, int FV, int RS>
+__global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ tiles)
+{
+  __shared__ double stg[NV * TA * NS];
+  __shared__ double sfl[NV * TA * NR];
+  __shared__ double sfr[NV * TA * NR];
+  constexpr int AX = (D == 0) ? 1 : 0;
+  const int4 t = tiles[blockIdx.x];
+  const BlockInfo b = a.blocks[t.x];
+  const int org[3] = {t.y, t.z, t.w};
+  const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
+  const int tid = threadIdx.x;
+
+  // stage P and the transverse cell-centred field: cells org[D]-3 .. org[D]+TD+1
+  for (int it = tid; it < NV * TA * NS; it += 256) {
+    int s, aa, v;
+    if constexpr (D == 0) { s = it % NS; aa = (it / NS) % TA; v = it / (NS * TA); }
+    else                  { aa = it % TA; s = (it / TA) % NS; v = it / (TA * NS); }
+    int idx[3] = {org[0], org[1], org[2]};
+    idx[D] = min(max(org[D] - 3 + s, 0), b.s[D] - 1);
+    idx[AX] = min(org[AX] + aa, b.s[AX] - 1);
+    const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+    double val;
+    if (v < 5) val = a.P[v * a.nct + c];
+    else val = a.Bcc[tcomp<D>(v - 5) * a.nct + c];
+    stg[(v * TA + aa) * NS + s] = val;
+  }
+  __syncthreads();
+
+  // reconstruct every (variable, column, cell) of cells org[D]-1 .. org[D]+TD-1
+  for (int it = tid; it < NV * TA * NR; it += 256) {
+    const int cc = it % NR, aa = (it / NR) % TA, v = it / (NR * TA);
+    const double *f = &stg[(v * TA + aa) * NS + cc];
+    double l, r;
+    recon5<RECON, FV>(f[0], f[1], f[2], f[3], f[4], l, r);
+    positivity(v, f[2], l, r);
+    sfl[it] = l;
+    sfr[it] = r;
+  }
+  __syncthreads();
+
+  int fd, aa;
+  if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
+  else                  { aa = tid % TA; fd = tid / TA; }
+  int idx[3] = {org[0], org[1], org[2]};
+  idx[D] = org[D] + fd;
+  idx[AX] = org[AX] + aa;
+  if (idx[D] >= a.ng + b.n[D]) return;
+  if (idx[AX] > a.ng + b.n[AX] || idx[AX] >= b.s[AX]) return;
+  const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+  double qL[7], qR[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    qL[v] = sfr[(v * TA + aa) * NR + fd];        // right face of cell idx[D]-1
+    qR[v] = sfl[(v * TA + aa) * NR + fd + 1];    // left face of cell idx[D]
+  }
+  face_flux_store<MK, D, RS>(a, b, idx[0], idx[1], c, qL, qR);
+}
+
+// Faces on the upper boundary plane along D (index ng + n_D), one per thread.
+template <int MK, int D, int RECON, int FV, int RS>
+__global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restrict__ chunks)
+{
+  constexpr int AX = (D == 0) ? 1 : 0;
+  constexpr int BX = (D == 2) ? 1 : 2;
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  const int na = b.n[AX] + 2, nb = b.n[BX] + 2;
+  if (e >= na * nb) return;
+  int idx[3];
+  idx[D] = a.ng + b.n[D];
+  idx[AX] = a.ng - 1 + e % na;
+  idx[BX] = a.ng - 1 + e / na;
+  const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
+  const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+  const long long sd = str[D];
+  double qL[7], qR[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    const double *arr = v < 5 ? a.P + v * a.nct : a.Bcc + tcomp<D>(v - 5) * a.nct;
+    double f[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) f[m] = arr[c + (m - 3) * sd];
+    double l, r;
+    recon5<RECON, FV>(f[0], f[1], f[2], f[3], f[4], l, r);   // cell idx-1
+    positivity(v, f[2], l, r);
+    qL[v] = r;
+    recon5<RECON, FV>(f[1], f[2], f[3], f[4], f[5], l, r);   // cell idx
+    positivity(v, f[3], l, r);
+    qR[v] = l;
+  }
+  face_flux_store<MK, D, RS>(a, b, idx[0], idx[1], c, qL, qR);
+}
+
+// --------------------------------------------------------- sources (KS)
+
+struct Sym4 { double t00, t01, t02, t03, t11, t12, t13, t22, t23, t33; };
+
+// sqrt(-g) (S_1, S_2, S_tau) at a cell centre of Kerr-Schild (x1 = ln r).
+// S_j = T^{mu nu} d_j g_{mu nu} / 2;
+// S_tau = alpha (T^{mu 0} d_mu ln alpha - T^{mu nu} Gamma^0_{mu nu}),
+// Gamma^0_{mu nu} = (g^00 (d_mu g_0nu + d_nu g_0mu) + g^01 (d_mu g_1nu + d_nu g_1mu - d_1 g_mu nu))/2
+// (KS: g^02 = g^03 = 0; stationary and axisymmetric, so only d_1, d_2 act).
+__device__ __forceinline__ void ks_sources(double r, double s, double cth, const MetricP &m,
+                                           const Geo &G, const Sym4 &T, double &S1, double &S2,
+                                           double &St)
+{
+  const double a = m.a, a2 = a * a, s2 = s * s, ds2 = 2.0 * s * cth;
+  const double Sig = r * r + a2 * cth * cth;
+  const double iSig = 1.0 / Sig;
+  const double z = 2.0 * m.M * r * iSig;
+  const double opz = 1.0 + z;
+  const double r2 = r * r;
+  const double dz1 = z * (1.0 - 2.0 * r2 * iSig);
+  const double dz2 = z * 2.0 * a2 * cth * s * iSig;
+  // d_1 g
+  const double a00 = dz1, a01 = r * dz1 + z * r, a03 = -a * s2 * dz1;
+  const double a11 = r2 * dz1 + 2.0 * opz * r2, a13 = -a * s2 * (r * dz1 + opz * r);
+  const double a22 = 2.0 * r2, a33 = s2 * (2.0 * r2 + a2 * s2 * dz1);
+  // d_2 g
+  const double dSig2 = -2.0 * a2 * cth * s;
+  const double c00 = dz2, c01 = r * dz2, c03 = -a * (dz2 * s2 + z * ds2);
+  const double c11 = r2 * dz2, c13 = -a * r * (dz2 * s2 + opz * ds2);
+  const double c22 = dSig2;
+  const double c33 = ds2 * (Sig + a2 * opz * s2) + s2 * (dSig2 + a2 * (dz2 * s2 + opz * ds2));
+  S1 = 0.5 * (T.t00 * a00 + 2.0 * T.t01 * a01 + 2.0 * T.t03 * a03 + T.t11 * a11 +
+              2.0 * T.t13 * a13 + T.t22 * a22 + T.t33 * a33);
+  S2 = 0.5 * (T.t00 * c00 + 2.0 * T.t01 * c01 + 2.0 * T.t03 * c03 + T.t11 * c11 +
+              2.0 * T.t13 * c13 + T.t22 * c22 + T.t33 * c33);
+  // Gamma^0 components (symmetric), X = g^00, Y = g^01
+  const double X = -opz, Y = z / r;
+  // Gamma^0_{mu nu} = X/2 (d_mu g_0nu + d_nu g_0mu) + Y/2 (d_mu g_1nu + d_nu g_1mu - d_1 g_mu nu)
+  const double G00 = 0.5 * Y * (-a00);
+  const double G01 = 0.5 * X * (a00) + 0.5 * Y * (a01 - a01);
+  const double G02 = 0.5 * X * (c00) + 0.5 * Y * (c01);
+  const double G03 = 0.5 * Y * (-a03);
+  const double G11 = 0.5 * X * (2.0 * a01) + 0.5 * Y * (2.0 * a11 - a11);
+  const double G12 = 0.5 * X * (c01) + 0.5 * Y * (c11);
+  const double G13 = 0.5 * X * (a03) + 0.5 * Y * (a13 - a13);
+  const double G22 = 0.5 * Y * (-a22);
+  const double G23 = 0.5 * X * (c03) + 0.5 * Y * (c13);
+  const double G33 = 0.5 * Y * (-a33);
+  const double TG = T.t00 * G00 + 2.0 * (T.t01 * G01 + T.t02 * G02 + T.t03 * G03 +
+                                         T.t12 * G12 + T.t13 * G13 + T.t23 * G23) +
+                    T.t11 * G11 + T.t22 * G22 + T.t33 * G33;
+  const double dla1 = -0.5 * dz1 / opz, dla2 = -0.5 * dz2 / opz;
+  St = G.alpha * (T.t01 * dla1 + T.t02 * dla2 - TG);
+  const double smg = G.alpha * G.sqrtg;
+  S1 *= smg; S2 *= smg; St *= smg;
+}
+
+__device__ __forceinline__ Sym4 tmunu(const Geo &G, const Aux &A)
+{
+  const double wt = A.w + A.b2, pt = A.p + 0.5 * A.b2;
+  const double ia2 = 1.0 / (G.alpha * G.alpha);
+  const double u0 = A.W / G.alpha;
+  const double gi00 = -ia2, gi01 = G.beta1 * ia2, gi11 = G.gi11 - G.beta1 * G.beta1 * ia2;
+  Sym4 T;
+  T.t00 = wt * u0 * u0 + pt * gi00 - A.b0 * A.b0;
+  T.t01 = wt * u0 * A.uc1 + pt * gi01 - A.b0 * A.bc1;
+  T.t02 = wt * u0 * A.uc2 - A.b0 * A.bc2;
+  T.t03 = wt * u0 * A.uc3 - A.b0 * A.bc3;
+  T.t11 = wt * A.uc1 * A.uc1 + pt * gi11 - A.bc1 * A.bc1;
+  T.t12 = wt * A.uc1 * A.uc2 - A.bc1 * A.bc2;
+  T.t13 = wt * A.uc1 * A.uc3 + pt * G.gi13 - A.bc1 * A.bc3;
+  T.t22 = wt * A.uc2 * A.uc2 + pt * G.gi22 - A.bc2 * A.bc2;
+  T.t23 = wt * A.uc2 * A.uc3 - A.bc2 * A.bc3;
+  T.t33 = wt * A.uc3 * A.uc3 + pt * G.gi33 - A.bc3 * A.bc3;
+  return T;
+}
+
+// ------------------------------------------------------------------ update
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict__ chunks,
+                                                double dt_in, const double *__restrict__ dt_dev,
+                                                double c0, double c1, double cdt, int save_base)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  const int m1 = b.n[0] + 1, m2 = b.n[1] + 1;
+  if (e >= m1 * m2 * (b.n[2] + 1)) return;
+  const int ng = a.ng;
+  const int i = ng + e % m1, j = ng + (e / m1) % m2, k = ng + e / (m1 * m2);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const long long c = b.off + i + sj * j + sk * k;
+  const long long n = a.nct;
+  const double dt = dt_in > 0.0 ? dt_in : *dt_dev;
+  const double h = cdt * dt;
+  const double i1 = 1.0 / b.dx[0], i2 = 1.0 / b.dx[1], i3 = 1.0 / b.dx[2];
+  const double *F0 = a.F, *F1 = a.F + 8 * n, *F2 = a.F + 16 * n;
+  const bool in1 = i < ng + b.n[0], in2 = j < ng + b.n[1], in3 = k < ng + b.n[2];
+
+  if (in1 && in2 && in3) {
+    double rhs[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      rhs[v] = -(F0[v * n + c + 1] - F0[v * n + c]) * i1 - (F1[v * n + c + sj] - F1[v * n + c]) * i2 -
+               (F2[v * n + c + sk] - F2[v * n + c]) * i3;
+    if constexpr (MK == MK_KS) {
+      const double r = a.tab.rc[b.tab1 + i], s = a.tab.sc[b.tab2 + j], ct = a.tab.cc[b.tab2 + j];
+      const Geo G = geo_ks(r, s, ct, a.met);
+      Prim q;
+      q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+      q.ie = a.P[4 * n + c];
+      q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
+      const Aux A = aux_of(G, a.eos.gam, q);
+      const Sym4 T = tmunu(G, A);
+      double S1, S2, St;
+      ks_sources(r, s, ct, a.met, G, T, S1, S2, St);
+      rhs[1] += S1;
+      rhs[2] += S2;
+      rhs[4] += St;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const double u = a.U[v * n + c];
+      if (save_base) {
+        a.U0[v * n + c] = u;
+        a.U[v * n + c] = c0 * u + h * rhs[v];
+      } else {
+        a.U[v * n + c] = c0 * a.U0[v * n + c] + c1 * u + h * rhs[v];
+      }
+    }
+  }
+
+  // edge EMFs: E1 = Omega_23 at (i, j-1/2, k-1/2), E2 = Omega_31 at
+  // (i-1/2, j, k-1/2), E3 = Omega_12 at (i-1/2, j-1/2, k); four-point averages
+  auto E1 = [&](long long q) {
+    return 0.25 * (F1[7 * n + q] + F1[7 * n + q - sk] - F2[6 * n + q] - F2[6 * n + q - sj]);
+  };
+  auto E2 = [&](long long q) {
+    return 0.25 * (F2[5 * n + q] + F2[5 * n + q - 1] - F0[7 * n + q] - F0[7 * n + q - sk]);
+  };
+  auto E3 = [&](long long q) {
+    return 0.25 * (F0[6 * n + q] + F0[6 * n + q - sj] - F1[5 * n + q] - F1[5 * n + q - 1]);
+  };
+  double rb[3];
+  bool upd[3] = {in2 && in3, in1 && in3, in1 && in2};
+  rb[0] = upd[0] ? (E3(c + sj) - E3(c)) * i2 - (E2(c + sk) - E2(c)) * i3 : 0.0;
+  rb[1] = upd[1] ? -(E3(c + 1) - E3(c)) * i1 + (E1(c + sk) - E1(c)) * i3 : 0.0;
+  rb[2] = upd[2] ? (E2(c + 1) - E2(c)) * i1 - (E1(c + sj) - E1(c)) * i2 : 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (!upd[d]) continue;
+    const double bf = a.Bf[d * n + c];
+    if (save_base) {
+      a.Bf0[d * n + c] = bf;
+      a.Bf[d * n + c] = c0 * bf + h * rb[d];
+    } else {
+      a.Bf[d * n + c] = c0 * a.Bf0[d * n + c] + c1 * bf + h * rb[d];
+    }
+  }
+}
+
+// --------------------------------------------------------------- inversion
+
+struct C2P { double q, r2, b2, rb, gam, v2max; };
+
+// Master function f(mu) = mu - 1/(h/W + mu rbar^2) and its derivative.
+__device__ __forceinline__ double master(const C2P &m, double mu, double &df)
+{
+  const double x = 1.0 / (1.0 + mu * m.b2);
+  const double dx = -m.b2 * x * x;
+  const double rb2 = m.rb * m.rb;
+  const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * rb2;
+  const double drbar2 = 2.0 * m.r2 * x * dx + rb2 * (x * (1.0 + x) + mu * (1.0 + 2.0 * x) * dx);
+  const double K = m.b2 * m.r2 - rb2;
+  const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * K;
+  const double dqbar = -K * (mu * x * x + mu * mu * x * dx);
+  double v2 = mu * mu * rbar2, dv2 = 2.0 * mu * rbar2 + mu * mu * drbar2;
+  if (v2 > m.v2max) { v2 = m.v2max; dv2 = 0.0; }
+  const double W = 1.0 / sqrt(1.0 - v2);
+  const double dW = 0.5 * W * W * W * dv2;
+  double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
+  double deps = dW * (1.0 + qbar - mu * rbar2) + W * (dqbar - rbar2 - mu * drbar2);
+  if (eps < 0.0) { eps = 0.0; deps = 0.0; }
+  const double hh = 1.0 + m.gam * eps, dh = m.gam * deps;
+  const double iW = 1.0 / W;
+  const double nu = hh * iW, dnu = dh * iW - hh * dW * iW * iW;
+  const double den = nu + mu * rbar2;
+  const double iden = 1.0 / den;
+  df = 1.0 + (dnu + rbar2 + mu * drbar2) * iden * iden;
+  return mu - iden;
+}
+
+__device__ __forceinline__ double master_f(const C2P &m, double mu)
+{
+  double d;
+  return master(m, mu, d);
+}
+
+template <int MK>
+__device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Geo &G,
+                                           const Prim &q)
+{
+  const Aux A = aux_of(G, a.eos.gam, q);
+  double U[8];
+  cons_of(G, q, A, U);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) a.U[v * a.nct + c] = G.sqrtg * U[v];
+}
+
+template <int MK, int GUESS>
+__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks,
+                                             const float *__restrict__ mlp_mu)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  if (e >= b.n[0] * b.n[1] * b.n[2]) return;
+  const int ng = a.ng;
+  const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const long long c = b.off + i + sj * j + sk * k;
+  const long long n = a.nct;
+  const Geo G = geo_center<MK>(a, b, i, j);
+  const double isg = 1.0 / G.sqrtg;
+  double Ud[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Ud[v] = a.U[v * n + c] * isg;
+  const double B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
+  const double B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
+  const double B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
+  Prim prev;
+  prev.rho = a.P[c]; prev.u1 = a.P[n + c]; prev.u2 = a.P[2 * n + c]; prev.u3 = a.P[3 * n + c];
+  prev.ie = a.P[4 * n + c];
+  prev.B1 = B1; prev.B2 = B2; prev.B3 = B3;
+
+  const double gam = a.eos.gam;
+  int flag = 0, iters = 0;
+  Prim q = prev;
+  bool ok = Ud[0] > 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ok = ok && isfinite(Ud[v]);
+  if (ok) {
+    const double D = Ud[0], iD = 1.0 / D;
+    // S^i = gamma^ij S_j ; B_i = gamma_ij B^j
+    const double Su1 = G.gi11 * Ud[1] + G.gi13 * Ud[3];
+    const double Su2 = G.gi22 * Ud[2];
+    const double Su3 = G.gi13 * Ud[1] + G.gi33 * Ud[3];
+    const double Bl1 = G.g11 * B1 + G.g13 * B3, Bl2 = G.g22 * B2, Bl3 = G.g13 * B1 + G.g33 * B3;
+    C2P m;
+    m.gam = gam;
+    m.q = Ud[4] * iD;
+    m.r2 = (Ud[1] * Su1 + Ud[2] * Su2 + Ud[3] * Su3) * iD * iD;
+    m.b2 = (Bl1 * B1 + Bl2 * B2 + Bl3 * B3) * iD;
+    const double isD = 1.0 / sqrt(D);
+    m.rb = (Ud[1] * B1 + Ud[2] * B2 + Ud[3] * B3) * iD * isD;
+    m.v2max = m.r2 / (1.0 + m.r2);
+    if (master_f(m, 1.0) < 0.0) {
+      ok = false;
+    } else {
+      double mu;
+      if constexpr (GUESS == 0) {
+        mu = 1.0 / sqrt(1.0 + m.r2);
+      } else {
+        const Aux Ap = aux_of(G, gam, prev);
+        mu = 1.0 / ((1.0 + gam * prev.ie / prev.rho) * Ap.W);
+        if constexpr (GUESS == 2) {
+          const float g = mlp_mu[c];
+          if (g > 0.0f && g <= 1.0f) mu = (double)g;
+        }
+      }
+      if (!(mu > 0.0 && mu <= 1.0)) mu = 0.5;
+      double lo = 0.0, hi = 1.0;
+      const double tol = a.eos.tol;
+      for (iters = 1; iters <= a.eos.max_iter; ++iters) {
+        double df;
+        const double f = master(m, mu, df);
+        if (f == 0.0) break;
+        if (f < 0.0) lo = mu; else hi = mu;
+        double mn = mu - f / df;
+        if (!(mn > lo && mn < hi)) mn = 0.5 * (lo + hi);
+        const double dmu = fabs(mn - mu);
+        mu = mn;
+        if (dmu <= tol * mu) break;
+      }
+      const double x = 1.0 / (1.0 + mu * m.b2);
+      const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * m.rb * m.rb;
+      const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * (m.b2 * m.r2 - m.rb * m.rb);
+      double v2 = mu * mu * rbar2;
+      v2 = v2 > m.v2max ? m.v2max : v2;
+      const double W = 1.0 / sqrt(1.0 - v2);
+      double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
+      eps = eps < 0.0 ? 0.0 : eps;
+      q.rho = D / W;
+      q.ie = q.rho * eps;
+      const double f1 = mu * x * W, f2 = mu * m.rb * isD;
+      q.u1 = f1 * (Su1 * iD + f2 * B1);
+      q.u2 = f1 * (Su2 * iD + f2 * B2);
+      q.u3 = f1 * (Su3 * iD + f2 * B3);
+    }
+  }
+  if (!ok) {
+    q = prev;
+    flag |= 8;
+  }
+  // floors (Sec. 3.2)
+  double r = 1.0;
+  if constexpr (MK == MK_KS) r = a.tab.rc[b.tab1 + i];
+  const double rflr = a.eos.rho_flr0 * pow(r, -a.eos.rho_flr_pow);
+  const double uflr = a.eos.u_flr0 * pow(r, -a.eos.u_flr_pow);
+  if (q.rho < rflr) { q.rho = rflr; flag |= 1; }
+  if (q.ie < uflr) { q.ie = uflr; flag |= 2; }
+  const double ut2 = G.g11 * q.u1 * q.u1 + 2.0 * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
+                     G.g33 * q.u3 * q.u3;
+  if (sqrt(1.0 + ut2) > a.eos.W_max) {
+    const double sc = sqrt((a.eos.W_max * a.eos.W_max - 1.0) / ut2);
+    q.u1 *= sc; q.u2 *= sc; q.u3 *= sc;
+    flag |= 4;
+  }
+  a.P[c] = q.rho; a.P[n + c] = q.u1; a.P[2 * n + c] = q.u2; a.P[3 * n + c] = q.u3;
+  a.P[4 * n + c] = q.ie;
+  if (flag) cons_store<MK>(a, c, G, q);
+  a.flags[c] = (int8_t)flag;
+  a.iters[c] = (uint8_t)min(iters, 255);
+}
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_p2c(KArgs a, const int2 *__restrict__ chunks)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  if (e >= b.n[0] * b.n[1] * b.n[2]) return;
+  const int ng = a.ng;
+  const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const long long c = b.off + i + sj * j + sk * k;
+  const long long n = a.nct;
+  const Geo G = geo_center<MK>(a, b, i, j);
+  const double isg = 1.0 / G.sqrtg;
+  Prim q;
+  q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+  q.ie = a.P[4 * n + c];
+  q.B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
+  q.B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
+  q.B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
+  cons_store<MK>(a, c, G, q);
+}
+
+// -------------------------------------------------------------- reductions
+
+constexpr int NPART = 12;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict__ chunks,
+                                                double *__restrict__ part)
+{
+  __shared__ double sh[4][NPART];
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  double val[NPART];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) val[q] = 0.0;
+  const bool live = e < b.n[0] * b.n[1] * b.n[2];
+  if (live) {
+    const int ng = a.ng;
+    const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+    const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+    const long long c = b.off + i + sj * j + sk * k;
+    const long long n = a.nct;
+    const Geo G = geo_center<MK>(a, b, i, j);
+    const double isg = 1.0 / G.sqrtg;
+    Prim q;
+    q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+    q.ie = a.P[4 * n + c];
+    const double b1l = a.Bf[c], b1h = a.Bf[c + 1];
+    const double b2l = a.Bf[n + c], b2h = a.Bf[n + c + sj];
+    const double b3l = a.Bf[2 * n + c], b3h = a.Bf[2 * n + c + sk];
+    q.B1 = 0.5 * (b1l + b1h) * isg; q.B2 = 0.5 * (b2l + b2h) * isg; q.B3 = 0.5 * (b3l + b3h) * isg;
+    const Aux A = aux_of(G, a.eos.gam, q);
+    double s = 0.0, lm, lp;
+    if (a.active[0]) { speeds_of<0>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[0]; }
+    if (a.active[1]) { speeds_of<1>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[1]; }
+    if (a.active[2]) { speeds_of<2>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[2]; }
+    val[0] = s;
+    val[1] = fabs((b1h - b1l) / b.dx[0] + (b2h - b2l) / b.dx[1] + (b3h - b3l) / b.dx[2]);
+    val[2] = fmax(fmax(fmax(fabs(b1l), fabs(b1h)), fmax(fabs(b2l), fabs(b2h))),
+                  fmax(fabs(b3l), fabs(b3h)));
+    const double dV = b.dx[0] * b.dx[1] * b.dx[2];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) val[3 + v] = a.U[v * n + c] * dV;
+    const int fl = a.flags[c];
+    val[8] = (fl & 8) ? 1.0 : 0.0;
+    val[9] = (fl & 7) ? 1.0 : 0.0;
+    val[10] = (double)a.iters[c];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double itmax = wave_max(val[10]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) val[q] = wave_max(val[q]);
+#pragma unroll
+  for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
+  val[11] = itmax;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o[NPART];
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) o[q] = sh[0][q];
+    for (int w = 1; w < 4; ++w) {
+      for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], sh[w][q]);
+      for (int q = 3; q < NPART; ++q) o[q] += sh[w][q];
+    }
+    for (int q = 0; q < NPART; ++q) part[(long long)blockIdx.x * NPART + q] = o[q];
+  }
+}
+
+// One workgroup folds the per-workgroup partials in a fixed order.
+// res: dt, divb_rel, divb_max, tot[5], nfail, nfloor, itsum, wavemax_sum, bmax, smax
+__global__ __launch_bounds__(256) void k_reduce_fin(const double *__restrict__ part, int np,
+                                                    double cfl, double dxmin, double *res)
+{
+  __shared__ double sh[256][NPART];
+  double o[NPART];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) o[q] = 0.0;
+  for (int p = threadIdx.x; p < np; p += 256) {
+    for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], part[(long long)p * NPART + q]);
+    for (int q = 3; q < NPART; ++q) o[q] += part[(long long)p * NPART + q];
+  }
+  for (int q = 0; q < NPART; ++q) sh[threadIdx.x][q] = o[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int t = 1; t < 256; ++t) {
+      for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], sh[t][q]);
+      for (int q = 3; q < NPART; ++q) o[q] += sh[t][q];
+    }
+    res[0] = o[0] > 0.0 ? cfl / o[0] : 0.0;
+    res[1] = o[2] > 0.0 ? o[1] / (o[2] / dxmin) : o[1];
+    res[2] = o[1];
+    for (int v = 0; v < 5; ++v) res[3 + v] = o[3 + v];
+    res[8] = o[8]; res[9] = o[9]; res[10] = o[10]; res[11] = o[11];
+    res[12] = o[2]; res[13] = o[0];
+  }
+}
+
+}  // namespace grmhd

@@ -1,0 +1,316 @@
+"""Python binding of libgrmhd.so (include/grmhd.h): argument marshalling only.
+
+Device memory comes from PyTorch (state tensors and the workspace); every step
+of the method runs in the library's HIP kernels.  The binding fails loudly if
+the library is missing or no GPU is present: there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrmhd.so")
+
+OK = 0
+METRIC_MINKOWSKI, METRIC_KS = 0, 1
+GUESS_COLD, GUESS_PREV, GUESS_MLP = 0, 1, 2
+PREC_FP64, PREC_MIXED = 0, 1
+
+_cint_p = ctypes.POINTER(ctypes.c_int)
+
+
+class PackDesc(ctypes.Structure):
+    _fields_ = [("nblocks", ctypes.c_int), ("ng", ctypes.c_int), ("recon", ctypes.c_int),
+                ("riemann", ctypes.c_int), ("precision", ctypes.c_int), ("weno_fv", ctypes.c_int),
+                ("nx", _cint_p), ("level", _cint_p), ("lloc", _cint_p),
+                ("root_nx", ctypes.c_int * 3), ("xmin", ctypes.c_double * 3),
+                ("xmax", ctypes.c_double * 3), ("bc", ctypes.c_int * 6)]
+
+
+class StatePtrs(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_void_p), ("Bf", ctypes.c_void_p), ("U", ctypes.c_void_p),
+                ("U0", ctypes.c_void_p), ("Bf0", ctypes.c_void_p)]
+
+
+class Metric(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("M", ctypes.c_double), ("a", ctypes.c_double)]
+
+
+class Eos(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("rho_flr0", ctypes.c_double),
+                ("rho_flr_pow", ctypes.c_double), ("u_flr0", ctypes.c_double),
+                ("u_flr_pow", ctypes.c_double), ("W_max", ctypes.c_double),
+                ("c2p_tol", ctypes.c_double), ("c2p_max_iter", ctypes.c_int)]
+
+
+class ReductionOut(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("divb_rel", ctypes.c_double),
+                ("divb_max", ctypes.c_double), ("totals", ctypes.c_double * 5),
+                ("c2p_fail", ctypes.c_longlong), ("floor_hits", ctypes.c_longlong),
+                ("c2p_iter_mean", ctypes.c_double), ("c2p_iter_wavemax_mean", ctypes.c_double)]
+
+
+EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
+           "grmhd_pack_create", "grmhd_pack_destroy", "grmhd_bind_state", "grmhd_fill_ghosts",
+           "grmhd_stage", "grmhd_con2prim", "grmhd_prim_to_cons", "grmhd_reductions",
+           "grmhd_debug_ptrs", "grmhd_last_error"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built; run paper_2410_09146_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        L.grmhd_pack_workspace_bytes.restype = ctypes.c_size_t
+        L.grmhd_last_error.restype = ctypes.c_char_p
+        L.grmhd_last_error.argtypes = [ctypes.c_void_p]
+        L.grmhd_pack_create.argtypes = [ctypes.POINTER(PackDesc), ctypes.POINTER(StatePtrs),
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        for f in ("grmhd_pack_destroy",):
+            getattr(L, f).argtypes = [ctypes.c_void_p]
+        L.grmhd_fill_ghosts.argtypes = [ctypes.c_void_p, ctypes.POINTER(Metric)]
+        L.grmhd_stage.argtypes = [ctypes.c_void_p, ctypes.POINTER(Metric), ctypes.POINTER(Eos),
+                                  ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.grmhd_con2prim.argtypes = [ctypes.c_void_p, ctypes.POINTER(Metric), ctypes.POINTER(Eos),
+                                     ctypes.c_int]
+        L.grmhd_prim_to_cons.argtypes = [ctypes.c_void_p, ctypes.POINTER(Metric),
+                                         ctypes.POINTER(Eos)]
+        L.grmhd_reductions.argtypes = [ctypes.c_void_p, ctypes.POINTER(Metric),
+                                       ctypes.POINTER(Eos), ctypes.c_double,
+                                       ctypes.POINTER(ReductionOut)]
+        L.grmhd_bind_state.argtypes = [ctypes.c_void_p, ctypes.POINTER(StatePtrs)]
+        L.grmhd_debug_ptrs.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 3
+        _lib = L
+    return _lib
+
+
+class GrmhdError(RuntimeError):
+    pass
+
+
+def _check(rc, pack=None):
+    if rc != OK:
+        msg = lib().grmhd_last_error(pack).decode()
+        raise GrmhdError(f"grmhd error {rc}: {msg}")
+
+
+def block_split(n, nblk):
+    """Uniform split of a root grid n[3] into nblk[3] equal blocks."""
+    nx, lloc = [], []
+    for bk in range(nblk[2]):
+        for bj in range(nblk[1]):
+            for bi in range(nblk[0]):
+                sz = [n[d] // nblk[d] for d in range(3)]
+                nx += sz
+                lloc += [bi * sz[0], bj * sz[1], bk * sz[2]]
+    return nx, lloc
+
+
+class Pack:
+    """A pack of same-level meshblocks covering a problem's domain.
+
+    prob: a problem description (paper_2410_09146_amd.inputs.Problem).
+    nblk: blocks per direction (uniform split).
+    """
+
+    def __init__(self, prob, nblk=(1, 1, 1), device="cuda:0", precision=PREC_FP64,
+                 c2p_tol=1e-14, c2p_max_iter=40):
+        import torch
+        if not torch.cuda.is_available():
+            raise GrmhdError("no GPU available: the HIP path has no CPU fallback")
+        self.torch = torch
+        self.prob = prob
+        self.device = torch.device(device)
+        self.ng = prob.ng
+        for d in range(3):
+            if prob.n[d] % nblk[d]:
+                raise GrmhdError("block split must divide the grid")
+        self.nblk = tuple(nblk)
+        nx, lloc = block_split(prob.n, nblk)
+        self.nb = nblk[0] * nblk[1] * nblk[2]
+        self._nx = (ctypes.c_int * len(nx))(*nx)
+        self._lloc = (ctypes.c_int * len(lloc))(*lloc)
+        self._level = (ctypes.c_int * self.nb)(*([0] * self.nb))
+        self.nx = np.array(nx).reshape(-1, 3)
+        self.lloc = np.array(lloc).reshape(-1, 3)
+        d = PackDesc()
+        d.nblocks = self.nb
+        d.ng = prob.ng
+        d.recon, d.riemann, d.precision, d.weno_fv = prob.recon, prob.riemann, precision, prob.weno_fv
+        d.nx, d.level, d.lloc = self._nx, self._level, self._lloc
+        for k in range(3):
+            d.root_nx[k] = prob.n[k]
+            d.xmin[k] = prob.xmin[k]
+            d.xmax[k] = prob.xmax[k]
+        for s in range(6):
+            d.bc[s] = prob.bc[s]
+        self.desc = d
+        L = lib()
+        offs = (ctypes.c_longlong * self.nb)()
+        nct = ctypes.c_longlong()
+        _check(L.grmhd_layout(ctypes.byref(d), offs, ctypes.byref(nct)))
+        self.offsets = np.array(offs[:], dtype=np.int64)
+        self.nct = nct.value
+        wsb = L.grmhd_pack_workspace_bytes(ctypes.byref(d))
+        if wsb == 0:
+            _check(-1)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self.P = torch.zeros((5, self.nct), **f64)
+        self.Bf = torch.zeros((3, self.nct), **f64)
+        self.U = torch.zeros((5, self.nct), **f64)
+        self.U0 = torch.zeros((5, self.nct), **f64)
+        self.Bf0 = torch.zeros((3, self.nct), **f64)
+        self.ws = torch.zeros(wsb + 256, dtype=torch.uint8, device=self.device)
+        ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.ws_bytes = wsb
+        st = StatePtrs(self.P.data_ptr(), self.Bf.data_ptr(), self.U.data_ptr(),
+                       self.U0.data_ptr(), self.Bf0.data_ptr())
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(L.grmhd_pack_create(ctypes.byref(d), ctypes.byref(st), ctypes.c_void_p(ws_ptr),
+                                   ctypes.c_size_t(wsb), ctypes.c_void_p(self.stream.cuda_stream),
+                                   ctypes.byref(h)))
+        self.h = h
+        self.metric = Metric(prob.metric_kind, prob.M, prob.a)
+        self.eos = Eos(prob.gamma, prob.rho_flr0, prob.rho_flr_pow, prob.u_flr0, prob.u_flr_pow,
+                       prob.W_max, c2p_tol, c2p_max_iter)
+        self.cfl = prob.cfl
+        self.t = 0.0
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            try:
+                lib().grmhd_pack_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    # ---------------------------------------------------------- data movement
+    def _block_views(self, arr, b):
+        n = self.nx[b]
+        s = n + 2 * self.ng
+        o = self.offsets[b]
+        cnt = int(s[0] * s[1] * s[2])
+        return arr[:, o:o + cnt].reshape(arr.shape[0], s[2], s[1], s[0])
+
+    def upload(self, P, Bf):
+        """Copy global padded numpy arrays (nvar, s3, s2, s1) into the blocks."""
+        torch = self.torch
+        for b in range(self.nb):
+            lo = self.lloc[b]
+            n = self.nx[b]
+            sl = tuple(slice(lo[2 - d], lo[2 - d] + n[2 - d] + 2 * self.ng) for d in range(3))
+            self._block_views(self.P, b).copy_(torch.from_numpy(np.ascontiguousarray(P[(slice(None),) + sl])))
+            self._block_views(self.Bf, b).copy_(torch.from_numpy(np.ascontiguousarray(Bf[(slice(None),) + sl])))
+
+    def download(self, which="P"):
+        """Assemble a global padded numpy array from the blocks' interiors
+        (and, for face arrays, the upper boundary faces)."""
+        arr = {"P": self.P, "Bf": self.Bf, "U": self.U, "U0": self.U0, "Bf0": self.Bf0}[which]
+        self.torch.cuda.synchronize(self.device)
+        host = arr.cpu().numpy()
+        nv = host.shape[0]
+        g = self.ng
+        shape = tuple(self.prob.n[2 - d] + 2 * g for d in range(3))
+        out = np.zeros((nv,) + shape)
+        face = which in ("Bf", "Bf0")
+        for b in range(self.nb):
+            n = self.nx[b]
+            lo = self.lloc[b]
+            s = n + 2 * g
+            o = self.offsets[b]
+            blk = host[:, o:o + s[0] * s[1] * s[2]].reshape(nv, s[2], s[1], s[0])
+            for v in range(nv):
+                ext = [n[d] + (1 if face and d == v else 0) for d in range(3)]
+                src = blk[v, g:g + ext[2], g:g + ext[1], g:g + ext[0]]
+                out[v, lo[2] + g:lo[2] + g + ext[2], lo[1] + g:lo[1] + g + ext[1],
+                    lo[0] + g:lo[0] + g + ext[0]] = src
+        return out
+
+    def debug_arrays(self):
+        """(flags, iters) of the last inversion as global padded numpy arrays."""
+        f, it, fl = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib().grmhd_debug_ptrs(self.h, ctypes.byref(f), ctypes.byref(it), ctypes.byref(fl)))
+        base = self.ws.data_ptr()
+        off_f = f.value - base
+        off_i = it.value - base
+        self.torch.cuda.synchronize(self.device)
+        flags = self.ws[off_f:off_f + self.nct].cpu().numpy().view(np.int8)
+        iters = self.ws[off_i:off_i + self.nct].cpu().numpy()
+        out = []
+        for arr in (flags, iters):
+            g = self.ng
+            shape = tuple(self.prob.n[2 - d] + 2 * g for d in range(3))
+            glob = np.zeros(shape, dtype=arr.dtype)
+            for b in range(self.nb):
+                n, lo, o = self.nx[b], self.lloc[b], self.offsets[b]
+                s = n + 2 * g
+                blk = arr[o:o + s[0] * s[1] * s[2]].reshape(s[2], s[1], s[0])
+                glob[lo[2] + g:lo[2] + g + n[2], lo[1] + g:lo[1] + g + n[1],
+                     lo[0] + g:lo[0] + g + n[0]] = blk[g:g + n[2], g:g + n[1], g:g + n[0]]
+            out.append(glob)
+        return out
+
+    def flux_array(self):
+        """Face fluxes [3, 8, s3, s2, s1] of a single-block pack (debug)."""
+        assert self.nb == 1
+        fl = ctypes.c_void_p()
+        _check(lib().grmhd_debug_ptrs(self.h, None, None, ctypes.byref(fl)))
+        off = fl.value - self.ws.data_ptr()
+        self.torch.cuda.synchronize(self.device)
+        raw = self.ws[off:off + 24 * self.nct * 8].cpu().numpy().view(np.float64)
+        s = self.nx[0] + 2 * self.ng
+        cnt = s[0] * s[1] * s[2]
+        return raw.reshape(3, 8, self.nct)[:, :, :cnt].reshape(3, 8, s[2], s[1], s[0])
+
+    # ------------------------------------------------------------------ calls
+    def fill_ghosts(self):
+        _check(lib().grmhd_fill_ghosts(self.h, ctypes.byref(self.metric)), self.h)
+
+    def prim_to_cons(self):
+        _check(lib().grmhd_prim_to_cons(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos)),
+               self.h)
+
+    def stage(self, dt, rk):
+        rkc = (ctypes.c_double * 3)(*rk)
+        _check(lib().grmhd_stage(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                 ctypes.c_double(dt), rkc), self.h)
+
+    def con2prim(self, guess=GUESS_PREV):
+        _check(lib().grmhd_con2prim(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                    ctypes.c_int(guess)), self.h)
+
+    def reductions(self, cfl=None, sync=True):
+        out = ReductionOut()
+        _check(lib().grmhd_reductions(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                      ctypes.c_double(self.cfl if cfl is None else cfl),
+                                      ctypes.byref(out) if sync else None), self.h)
+        if not sync:
+            return None
+        return {"dt": out.dt, "divb_rel": out.divb_rel, "divb_max": out.divb_max,
+                "totals": np.array(out.totals[:]), "c2p_fail": out.c2p_fail,
+                "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
+                "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean}
+
+    def init(self, P=None, Bf=None):
+        """Upload the problem's initial state, fill ghosts, build U."""
+        self.upload(self.prob.P if P is None else P, self.prob.Bf if Bf is None else Bf)
+        self.fill_ghosts()
+        self.prim_to_cons()
+
+    def step(self, dt=None, guess=GUESS_PREV):
+        """One SSPRK2 step (Shu-Osher): ghosts, stage {1,0,1}, con2prim, ghosts,
+        stage {1/2,1/2,1/2}, con2prim, ghosts.  dt = None: device-resident dt
+        from reductions(sync=False) (no host round trip)."""
+        h = dt if dt is not None else -1.0
+        self.stage(h, (1.0, 0.0, 1.0))
+        self.con2prim(guess)
+        self.fill_ghosts()
+        self.stage(h, (0.5, 0.5, 0.5))
+        self.con2prim(guess)
+        self.fill_ghosts()
