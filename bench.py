@@ -1,0 +1,141 @@
+#!/usr/bin/env python3
+"""Throughput of the GRMHD RK2 step on one MI355X: zone-cycles/s on the 128^3
+Kerr-Schild torus (WENO5-Z-AOAH + LLF, FP64), with the roofline of the
+dominant kernel and the oracle timed on the host cores.
+
+A step = ghost fill, stage {1,0,1}, con2prim, ghost fill, stage {1/2,1/2,1/2},
+con2prim, ghost fill, reductions (the CFL dt of the next step stays on the
+device).  Inputs are resident in HBM before the timed region starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-cycles/s per GPU, GRMHD RK2 step at 128^3 Kerr-Schild torus; % HBM roofline"
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=128, help="cells per direction of the torus")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def flux_faces(n):
+    """Faces the main flux tiles of one direction compute on an n^3 block:
+    n faces along the direction x (n + 2) x (n + 2) transverse rows."""
+    return n * (n + 2) * (n + 2)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "nothing here spans a second GPU", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: one GPU only; refusing a multi-rank launch", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_09146_amd import grmhd as G
+    from paper_2410_09146_amd import inputs as I
+
+    n = args.n
+    prob = I.torus(n=(n, n, n))
+    pack = G.Pack(prob, device="cuda:0")
+    pack.init()
+    pack.reductions(sync=False)        # device-resident dt for the first step
+    for _ in range(args.warmup):
+        pack.step(None)
+        pack.reductions(sync=False)
+    torch.cuda.synchronize()
+
+    stream = pack.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    pack.profile(True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        pack.step(None)
+        pack.reductions(sync=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = pack.profile_read()
+    pack.profile(False)
+    red = pack.reductions()
+
+    ncell = n ** 3
+    value = ncell * args.steps / (ms * 1e-3)
+
+    # dominant kernel family and its roofline (algorithmic FP64 flops per face)
+    fam = max(prof, key=lambda k: prof[k][0])
+    opc = json.load(open(os.path.join(ROOT, "paper_2410_09146_amd", "opcount", "opcount.json")))
+    per_face = opc["per_face_flux_ks_weno_llf"]
+    roof = None
+    if fam.startswith("flux_x"):
+        t_ms, cnt = prof[fam]
+        avg_ms = t_ms / cnt
+        flops = per_face * flux_faces(n)
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None, "kernel": f"k_flux ({fam})",
+                "avg_launch_ms": round(avg_ms, 4), "flops_per_face": per_face,
+                "faces_per_launch": flux_faces(n)}
+    # HBM view of the whole step: 480 algorithmic bytes per zone-cycle
+    hbm = {"algorithmic_bytes_per_zone_cycle": 480,
+           "achieved_GBs": round(480 * value / 1e9, 1),
+           "frac_of_8TBs": round(480 * value / 1e9 / HBM_PEAK_GBS, 4)}
+
+    kernels = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
+               for k, v in prof.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+        sim = oracle.Sim(prob, nthreads=threads)
+        dt0 = sim.dt()
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_steps):
+            sim.step(dt0)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(ncell * args.cpu_steps / t_cpu, 1), "unit": "zone-cycles/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_steps} SSPRK2 step(s) of the same {n}^3 torus, "
+                         f"{t_cpu:.1f} s wall, {threads} OpenMP threads"}
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "zone-cycles/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Kerr-Schild torus {n}^3 (a=0.9375, FM r_in=6 r_max=12, "
+                               "gamma=13/9, beta=100 loop field, noise 4e-2 seed 1), "
+                               "WENO5-Z-AOAH + LLF, CT, SSPRK2, FP64, one meshblock",
+                   "cells": ncell, "parallelism": "single GPU"},
+        "roofline": roof, "hbm_view": hbm, "kernels": kernels,
+        "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"],
+                  "floor_hits": red["floor_hits"], "c2p_iter_mean": red["c2p_iter_mean"],
+                  "c2p_iter_wavemax_mean": red["c2p_iter_wavemax_mean"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,21 @@ int grmhd_reductions(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_e
  * counts of the last con2prim (inside the workspace; same cell layout as P). */
 int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
 
+/*
+ * Kernel timing.  grmhd_profile(pack, 1) starts recording a HIP event pair on
+ * the pack's stream around every launch of a kernel family; grmhd_profile_read
+ * synchronises the stream and returns, per family, the summed milliseconds and
+ * the number of launches since the last read (arrays of GRMHD_PROF_NFAM).
+ * Families: flux tiles along x1 / x2 / x3, boundary face planes, update,
+ * con2prim, ghost gather, cell-centred field, reductions.
+ */
+enum { GRMHD_PROF_FLUX_X1 = 0, GRMHD_PROF_FLUX_X2 = 1, GRMHD_PROF_FLUX_X3 = 2,
+       GRMHD_PROF_FLUX_PLANE = 3, GRMHD_PROF_UPDATE = 4, GRMHD_PROF_C2P = 5,
+       GRMHD_PROF_GHOST = 6, GRMHD_PROF_BCC = 7, GRMHD_PROF_REDUCE = 8,
+       GRMHD_PROF_NFAM = 9 };
+int grmhd_profile(grmhd_pack *pack, int enable);
+int grmhd_profile_read(grmhd_pack *pack, double *ms, long long *count);
+
 const char *grmhd_last_error(const grmhd_pack *pack);
 
 #ifdef __cplusplus

@@ -331,6 +331,10 @@ struct grmhd_pack {
   char *ws;
   std::string err;
   bool mlp_bound = false;
+  // optional per-kernel-family timing with events on the pack's stream
+  bool prof = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_rec;
   KArgs args() const
   {
     KArgs a;
@@ -363,6 +367,32 @@ int perr(grmhd_pack *p, const std::string &m, int code)
   g_err = m;
   return code;
 }
+
+// RAII event pair around the launches of one kernel family
+struct Prof {
+  grmhd_pack *p;
+  int fam;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t take()
+  {
+    hipEvent_t e = nullptr;
+    if (!p->ev_free.empty()) { e = p->ev_free.back(); p->ev_free.pop_back(); }
+    else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+    return e;
+  }
+  Prof(grmhd_pack *pp, int f) : p(pp), fam(f)
+  {
+    if (!p->prof) return;
+    a = take(); b = take();
+    if (a) (void)hipEventRecord(a, p->stream);
+  }
+  ~Prof()
+  {
+    if (!p->prof || !a || !b) return;
+    (void)hipEventRecord(b, p->stream);
+    p->ev_rec.emplace_back(fam, a, b);
+  }
+};
 
 #define HIPCHK(p, x)                                                                  \
   do {                                                                                \
@@ -415,12 +445,16 @@ template <int MK, int D, int RC, int FV, int RS>
 void launch_flux(grmhd_pack *p, const KArgs &a)
 {
   const Plan &pl = p->plan;
-  if (!pl.tiles[D].empty())
+  if (!pl.tiles[D].empty()) {
+    Prof t(p, GRMHD_PROF_FLUX_X1 + D);
     hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS>), dim3(pl.tiles[D].size()), dim3(256), 0,
                        p->stream, a, dptr<int4>(p, pl.o_tiles[D]));
-  if (!pl.planes[D].empty())
+  }
+  if (!pl.planes[D].empty()) {
+    Prof t(p, GRMHD_PROF_FLUX_PLANE);
     hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS>), dim3(pl.planes[D].size()), dim3(256),
                        0, p->stream, a, dptr<int2>(p, pl.o_planes[D]));
+  }
 }
 
 template <int MK, int RC, int FV, int RS>
@@ -536,6 +570,11 @@ int grmhd_pack_destroy(grmhd_pack *p)
 {
   if (!p) return GRMHD_E_INVALID;
   (void)hipStreamSynchronize(p->stream);
+  for (auto &r : p->ev_rec) {
+    (void)hipEventDestroy(std::get<1>(r));
+    (void)hipEventDestroy(std::get<2>(r));
+  }
+  for (hipEvent_t e : p->ev_free) (void)hipEventDestroy(e);
   delete p;
   return GRMHD_OK;
 }
@@ -555,18 +594,24 @@ int grmhd_fill_ghosts(grmhd_pack *p, const grmhd_metric *m)
   KArgs a = p->args();
   a.met.M = m->M; a.met.a = m->a;
   const Plan &pl = p->plan;
+  {
+  Prof t(p, GRMHD_PROF_GHOST);
   if (!pl.gP.empty())
     hipLaunchKernelGGL(k_ghost_P, dim3((pl.gP.size() + 255) / 256), dim3(256), 0, p->stream, a,
                        dptr<GhostP>(p, pl.o_gP), (int)pl.gP.size());
   if (!pl.gB.empty())
     hipLaunchKernelGGL(k_ghost_B, dim3((pl.gB.size() + 255) / 256), dim3(256), 0, p->stream, a,
                        dptr<GhostB>(p, pl.o_gB), (int)pl.gB.size());
+  }
+  {
+  Prof tb(p, GRMHD_PROF_BCC);
   if (m->kind == GRMHD_METRIC_KS_LOGSPH)
     hipLaunchKernelGGL(k_bcc<MK_KS>, dim3(pl.ch_bcc.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_chb));
   else
     hipLaunchKernelGGL(k_bcc<MK_MINK>, dim3(pl.ch_bcc.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_chb));
+  }
   LAUNCHCHK(p);
   return GRMHD_OK;
 }
@@ -588,6 +633,7 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   LAUNCHCHK(p);
   const double *dtd = dptr<double>(p, pl.o_res);
   const int save = rk[1] == 0.0;
+  Prof t(p, GRMHD_PROF_UPDATE);
   if (m->kind == GRMHD_METRIC_KS_LOGSPH)
     hipLaunchKernelGGL(k_update<MK_KS>, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
@@ -613,6 +659,7 @@ int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
   const dim3 g(pl.ch_int.size());
   const int2 *ch = dptr<int2>(p, pl.o_chi);
   const float *mlp = dptr<float>(p, pl.o_mlp);
+  Prof t(p, GRMHD_PROF_C2P);
   if (m->kind == GRMHD_METRIC_KS_LOGSPH) {
     if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
     else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK_KS, 1>), g, dim3(256), 0, p->stream, a, ch, mlp);
@@ -657,6 +704,8 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
   const Plan &pl = p->plan;
   double *part = (double *)(p->ws + pl.o_part);
   double *res = (double *)(p->ws + pl.o_res);
+  {
+  Prof t(p, GRMHD_PROF_REDUCE);
   if (m->kind == GRMHD_METRIC_KS_LOGSPH)
     hipLaunchKernelGGL(k_reduce<MK_KS>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_chi), part);
@@ -665,6 +714,7 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
                        dptr<int2>(p, pl.o_chi), part);
   hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(256), 0, p->stream, (const double *)part,
                      (int)pl.ch_int.size(), cfl, pl.dxmin, res);
+  }
   LAUNCHCHK(p);
   if (out) {
     double h[16];
@@ -699,6 +749,36 @@ int grmhd_debug_ptrs(grmhd_pack *p, void **flags, void **iters, void **flux)
   if (flags) *flags = p->ws + p->plan.o_flags;
   if (iters) *iters = p->ws + p->plan.o_iters;
   if (flux) *flux = p->ws + p->plan.o_F;
+  return GRMHD_OK;
+}
+
+int grmhd_profile(grmhd_pack *p, int enable)
+{
+  if (!p) return GRMHD_E_INVALID;
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (auto &r : p->ev_rec) {
+    p->ev_free.push_back(std::get<1>(r));
+    p->ev_free.push_back(std::get<2>(r));
+  }
+  p->ev_rec.clear();
+  p->prof = enable != 0;
+  return GRMHD_OK;
+}
+
+int grmhd_profile_read(grmhd_pack *p, double *ms, long long *count)
+{
+  if (!p || !ms || !count) return GRMHD_E_INVALID;
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (int f = 0; f < GRMHD_PROF_NFAM; ++f) { ms[f] = 0.0; count[f] = 0; }
+  for (auto &r : p->ev_rec) {
+    float t = 0.0f;
+    HIPCHK(p, hipEventElapsedTime(&t, std::get<1>(r), std::get<2>(r)));
+    ms[std::get<0>(r)] += t;
+    count[std::get<0>(r)] += 1;
+    p->ev_free.push_back(std::get<1>(r));
+    p->ev_free.push_back(std::get<2>(r));
+  }
+  p->ev_rec.clear();
   return GRMHD_OK;
 }
 

@@ -236,83 +236,6 @@ __global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restr
   face_flux_store<MK, D, RS>(a, b, idx[0], idx[1], c, qL, qR);
 }
 
-// --------------------------------------------------------- sources (KS)
-
-struct Sym4 { double t00, t01, t02, t03, t11, t12, t13, t22, t23, t33; };
-
-// sqrt(-g) (S_1, S_2, S_tau) at a cell centre of Kerr-Schild (x1 = ln r).
-// S_j = T^{mu nu} d_j g_{mu nu} / 2;
-// S_tau = alpha (T^{mu 0} d_mu ln alpha - T^{mu nu} Gamma^0_{mu nu}),
-// Gamma^0_{mu nu} = (g^00 (d_mu g_0nu + d_nu g_0mu) + g^01 (d_mu g_1nu + d_nu g_1mu - d_1 g_mu nu))/2
-// (KS: g^02 = g^03 = 0; stationary and axisymmetric, so only d_1, d_2 act).
-__device__ __forceinline__ void ks_sources(double r, double s, double cth, const MetricP &m,
-                                           const Geo &G, const Sym4 &T, double &S1, double &S2,
-                                           double &St)
-{
-  const double a = m.a, a2 = a * a, s2 = s * s, ds2 = 2.0 * s * cth;
-  const double Sig = r * r + a2 * cth * cth;
-  const double iSig = 1.0 / Sig;
-  const double z = 2.0 * m.M * r * iSig;
-  const double opz = 1.0 + z;
-  const double r2 = r * r;
-  const double dz1 = z * (1.0 - 2.0 * r2 * iSig);
-  const double dz2 = z * 2.0 * a2 * cth * s * iSig;
-  // d_1 g
-  const double a00 = dz1, a01 = r * dz1 + z * r, a03 = -a * s2 * dz1;
-  const double a11 = r2 * dz1 + 2.0 * opz * r2, a13 = -a * s2 * (r * dz1 + opz * r);
-  const double a22 = 2.0 * r2, a33 = s2 * (2.0 * r2 + a2 * s2 * dz1);
-  // d_2 g
-  const double dSig2 = -2.0 * a2 * cth * s;
-  const double c00 = dz2, c01 = r * dz2, c03 = -a * (dz2 * s2 + z * ds2);
-  const double c11 = r2 * dz2, c13 = -a * r * (dz2 * s2 + opz * ds2);
-  const double c22 = dSig2;
-  const double c33 = ds2 * (Sig + a2 * opz * s2) + s2 * (dSig2 + a2 * (dz2 * s2 + opz * ds2));
-  S1 = 0.5 * (T.t00 * a00 + 2.0 * T.t01 * a01 + 2.0 * T.t03 * a03 + T.t11 * a11 +
-              2.0 * T.t13 * a13 + T.t22 * a22 + T.t33 * a33);
-  S2 = 0.5 * (T.t00 * c00 + 2.0 * T.t01 * c01 + 2.0 * T.t03 * c03 + T.t11 * c11 +
-              2.0 * T.t13 * c13 + T.t22 * c22 + T.t33 * c33);
-  // Gamma^0 components (symmetric), X = g^00, Y = g^01
-  const double X = -opz, Y = z / r;
-  // Gamma^0_{mu nu} = X/2 (d_mu g_0nu + d_nu g_0mu) + Y/2 (d_mu g_1nu + d_nu g_1mu - d_1 g_mu nu)
-  const double G00 = 0.5 * Y * (-a00);
-  const double G01 = 0.5 * X * (a00) + 0.5 * Y * (a01 - a01);
-  const double G02 = 0.5 * X * (c00) + 0.5 * Y * (c01);
-  const double G03 = 0.5 * Y * (-a03);
-  const double G11 = 0.5 * X * (2.0 * a01) + 0.5 * Y * (2.0 * a11 - a11);
-  const double G12 = 0.5 * X * (c01) + 0.5 * Y * (c11);
-  const double G13 = 0.5 * X * (a03) + 0.5 * Y * (a13 - a13);
-  const double G22 = 0.5 * Y * (-a22);
-  const double G23 = 0.5 * X * (c03) + 0.5 * Y * (c13);
-  const double G33 = 0.5 * Y * (-a33);
-  const double TG = T.t00 * G00 + 2.0 * (T.t01 * G01 + T.t02 * G02 + T.t03 * G03 +
-                                         T.t12 * G12 + T.t13 * G13 + T.t23 * G23) +
-                    T.t11 * G11 + T.t22 * G22 + T.t33 * G33;
-  const double dla1 = -0.5 * dz1 / opz, dla2 = -0.5 * dz2 / opz;
-  St = G.alpha * (T.t01 * dla1 + T.t02 * dla2 - TG);
-  const double smg = G.alpha * G.sqrtg;
-  S1 *= smg; S2 *= smg; St *= smg;
-}
-
-__device__ __forceinline__ Sym4 tmunu(const Geo &G, const Aux &A)
-{
-  const double wt = A.w + A.b2, pt = A.p + 0.5 * A.b2;
-  const double ia2 = 1.0 / (G.alpha * G.alpha);
-  const double u0 = A.W / G.alpha;
-  const double gi00 = -ia2, gi01 = G.beta1 * ia2, gi11 = G.gi11 - G.beta1 * G.beta1 * ia2;
-  Sym4 T;
-  T.t00 = wt * u0 * u0 + pt * gi00 - A.b0 * A.b0;
-  T.t01 = wt * u0 * A.uc1 + pt * gi01 - A.b0 * A.bc1;
-  T.t02 = wt * u0 * A.uc2 - A.b0 * A.bc2;
-  T.t03 = wt * u0 * A.uc3 - A.b0 * A.bc3;
-  T.t11 = wt * A.uc1 * A.uc1 + pt * gi11 - A.bc1 * A.bc1;
-  T.t12 = wt * A.uc1 * A.uc2 - A.bc1 * A.bc2;
-  T.t13 = wt * A.uc1 * A.uc3 + pt * G.gi13 - A.bc1 * A.bc3;
-  T.t22 = wt * A.uc2 * A.uc2 + pt * G.gi22 - A.bc2 * A.bc2;
-  T.t23 = wt * A.uc2 * A.uc3 - A.bc2 * A.bc3;
-  T.t33 = wt * A.uc3 * A.uc3 + pt * G.gi33 - A.bc3 * A.bc3;
-  return T;
-}
-
 // ------------------------------------------------------------------ update
 
 template <int MK>
@@ -399,41 +322,6 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
 }
 
 // --------------------------------------------------------------- inversion
-
-struct C2P { double q, r2, b2, rb, gam, v2max; };
-
-// Master function f(mu) = mu - 1/(h/W + mu rbar^2) and its derivative.
-__device__ __forceinline__ double master(const C2P &m, double mu, double &df)
-{
-  const double x = 1.0 / (1.0 + mu * m.b2);
-  const double dx = -m.b2 * x * x;
-  const double rb2 = m.rb * m.rb;
-  const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * rb2;
-  const double drbar2 = 2.0 * m.r2 * x * dx + rb2 * (x * (1.0 + x) + mu * (1.0 + 2.0 * x) * dx);
-  const double K = m.b2 * m.r2 - rb2;
-  const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * K;
-  const double dqbar = -K * (mu * x * x + mu * mu * x * dx);
-  double v2 = mu * mu * rbar2, dv2 = 2.0 * mu * rbar2 + mu * mu * drbar2;
-  if (v2 > m.v2max) { v2 = m.v2max; dv2 = 0.0; }
-  const double W = 1.0 / sqrt(1.0 - v2);
-  const double dW = 0.5 * W * W * W * dv2;
-  double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
-  double deps = dW * (1.0 + qbar - mu * rbar2) + W * (dqbar - rbar2 - mu * drbar2);
-  if (eps < 0.0) { eps = 0.0; deps = 0.0; }
-  const double hh = 1.0 + m.gam * eps, dh = m.gam * deps;
-  const double iW = 1.0 / W;
-  const double nu = hh * iW, dnu = dh * iW - hh * dW * iW * iW;
-  const double den = nu + mu * rbar2;
-  const double iden = 1.0 / den;
-  df = 1.0 + (dnu + rbar2 + mu * drbar2) * iden * iden;
-  return mu - iden;
-}
-
-__device__ __forceinline__ double master_f(const C2P &m, double mu)
-{
-  double d;
-  return master(m, mu, d);
-}
 
 template <int MK>
 __device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Geo &G,

@@ -54,7 +54,10 @@ class ReductionOut(ctypes.Structure):
 EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_pack_create", "grmhd_pack_destroy", "grmhd_bind_state", "grmhd_fill_ghosts",
            "grmhd_stage", "grmhd_con2prim", "grmhd_prim_to_cons", "grmhd_reductions",
-           "grmhd_debug_ptrs", "grmhd_last_error"]
+           "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_last_error"]
+
+PROF_FAMILIES = ["flux_x1", "flux_x2", "flux_x3", "flux_plane", "update", "con2prim",
+                 "ghost", "bcc", "reduce"]
 
 _lib = None
 
@@ -85,6 +88,9 @@ def lib():
                                        ctypes.POINTER(ReductionOut)]
         L.grmhd_bind_state.argtypes = [ctypes.c_void_p, ctypes.POINTER(StatePtrs)]
         L.grmhd_debug_ptrs.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 3
+        L.grmhd_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.grmhd_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_longlong)]
         _lib = L
     return _lib
 
@@ -296,6 +302,16 @@ class Pack:
                 "totals": np.array(out.totals[:]), "c2p_fail": out.c2p_fail,
                 "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
                 "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean}
+
+    def profile(self, enable=True):
+        _check(lib().grmhd_profile(self.h, int(enable)), self.h)
+
+    def profile_read(self):
+        n = len(PROF_FAMILIES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_longlong * n)()
+        _check(lib().grmhd_profile_read(self.h, ms, cnt), self.h)
+        return {f: (ms[i], cnt[i]) for i, f in enumerate(PROF_FAMILIES)}
 
     def init(self, P=None, Bf=None):
         """Upload the problem's initial state, fill ghosts, build U."""
