@@ -51,7 +51,7 @@ enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_GUESS_COLD = 0, GRMHD_GUESS_PREV = 1, GRMHD_GUESS_MLP = 2 };
 /* per-cell con2prim flag bits */
 enum { GRMHD_FLAG_RHO_FLOOR = 1, GRMHD_FLAG_U_FLOOR = 2, GRMHD_FLAG_W_CAP = 4,
-       GRMHD_FLAG_C2P_FAIL = 8 };
+       GRMHD_FLAG_C2P_FAIL = 8, GRMHD_FLAG_GUESS_FALLBACK = 16 };
 
 typedef struct grmhd_pack grmhd_pack;
 
@@ -104,6 +104,7 @@ typedef struct {
   double dt, divb_rel, divb_max, totals[5];
   long long c2p_fail, floor_hits;
   double c2p_iter_mean, c2p_iter_wavemax_mean;
+  long long guess_fallback;   /* cells whose learned guess was rejected */
 } grmhd_reduction_out;
 
 int grmhd_abi_version(void);
@@ -172,6 +173,24 @@ int grmhd_prim_to_cons(grmhd_pack *pack, const grmhd_metric *metric, const grmhd
 int grmhd_reductions(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
                      double cfl, grmhd_reduction_out *out);
 
+/*
+ * One SSPRK2 step: stage {1,0,1}, con2prim(guess), ghosts, stage {1/2,1/2,1/2},
+ * con2prim(guess), ghosts, then (cfl > 0) reductions leaving the next dt on the
+ * device.  dt <= 0 uses the device-resident dt.  Asynchronous.
+ */
+int grmhd_step(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos, double dt,
+               int guess, double cfl);
+
+/*
+ * The same step captured once into a HIP graph (dt from the device, no host
+ * round trip) and replayed nsteps times on the pack's stream.  The graph is
+ * re-captured when metric, eos, guess or cfl change; it binds the current
+ * state pointers (re-capture after grmhd_bind_state by changing nothing is not
+ * needed: bind_state drops the graph).
+ */
+int grmhd_step_graph(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
+                     int guess, double cfl, int nsteps);
+
 /* Device pointers to the per-cell int8 flags and uint8 Newton iteration
  * counts of the last con2prim (inside the workspace; same cell layout as P). */
 int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
@@ -187,9 +206,40 @@ int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
 enum { GRMHD_PROF_FLUX_X1 = 0, GRMHD_PROF_FLUX_X2 = 1, GRMHD_PROF_FLUX_X3 = 2,
        GRMHD_PROF_FLUX_PLANE = 3, GRMHD_PROF_UPDATE = 4, GRMHD_PROF_C2P = 5,
        GRMHD_PROF_GHOST = 6, GRMHD_PROF_BCC = 7, GRMHD_PROF_REDUCE = 8,
-       GRMHD_PROF_NFAM = 9 };
+       GRMHD_PROF_MLP = 9, GRMHD_PROF_NFAM = 10 };
 int grmhd_profile(grmhd_pack *pack, int enable);
 int grmhd_profile_read(grmhd_pack *pack, double *ms, long long *count);
+
+/*
+ * Learned initial guess of the inversion (growth on top of the paper's
+ * method; the Newton solve stays the judge).  Network 5 -> 64 -> 64 -> 64 -> 2
+ * with SiLU, GRMHD_MLP_NPARAM FP32 parameters laid out as W1[64][5] b1[64]
+ * W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2] (W[out][in]).
+ * Features of a cell's undensitized conserved state: log10 D, log(1+S^2/D^2),
+ * log(1+tau/D), log(1+B^2/D), log(1+(S.B)^2/D^3), standardised by feat_mean /
+ * feat_std; outputs y0 = log W, y1 = log(hW), guess mu0 = exp(-y1).
+ * All pointers are device pointers; calls are asynchronous on the stream.
+ */
+#define GRMHD_MLP_NPARAM 8834
+/* Copy the FP32 parameters into the pack as BF16 matrix-core operands. */
+int grmhd_mlp_bind(grmhd_pack *pack, const float *params, const float *feat_mean,
+                   const float *feat_std);
+/* Scratch bytes the training / gradient / inference calls need for a batch. */
+size_t grmhd_mlp_scratch_bytes(int batch);
+/* FP32 loss (mean over the batch of the summed squared error) and its
+ * gradient w.r.t. params (same layout).  X: [batch][5] standardised
+ * features, Y: [batch][2] targets. */
+int grmhd_mlp_grad(const float *params, const float *X, const float *Y, int batch, float *grad,
+                   float *loss, void *scratch, size_t scratch_bytes, void *hip_stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step number t >= 1) on the
+ * FP32 master parameters; adam_m / adam_v: moment buffers (GRMHD_MLP_NPARAM). */
+int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *X,
+                         const float *Y, int batch, float lr, int t, float *loss, void *scratch,
+                         size_t scratch_bytes, void *hip_stream);
+/* BF16 matrix-core inference on raw features X [n][5] -> Y [n][2]. */
+int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *feat_std,
+                    const float *X, float *Y, int n, void *scratch, size_t scratch_bytes,
+                    void *hip_stream);
 
 const char *grmhd_last_error(const grmhd_pack *pack);
 

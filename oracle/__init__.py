@@ -136,6 +136,15 @@ def c2p(metric, x, gam, Ud, B):
     return r, out, mu.value
 
 
+def p2c_batch(metric, x, gam, prims):
+    """prims [n, 8] -> undensitized U [n, 8] at one point x."""
+    prims = np.ascontiguousarray(prims, dtype=float)
+    U = np.zeros_like(prims)
+    lib().orc_p2c_batch(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.c_double(gam),
+                        ctypes.c_long(prims.shape[0]), _ptr(prims), _ptr(U))
+    return U
+
+
 def master(gam, q, r2, b2, rb, mu):
     return lib().orc_pt_master(ctypes.c_double(gam), ctypes.c_double(q), ctypes.c_double(r2),
                                ctypes.c_double(b2), ctypes.c_double(rb), ctypes.c_double(mu))

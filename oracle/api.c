@@ -110,6 +110,19 @@ int orc_pt_c2p(const orc_metric *m, const double x[3], double gam, const double 
   return r;
 }
 
+/* n points of one metric location x: prims[n][8] -> U[n][8] (undensitized). */
+void orc_p2c_batch(const orc_metric *m, const double x[3], double gam, long n,
+                   const double *prims, double *U)
+{
+  orc_geom G;
+  orc_geom_at(m, x, &G);
+  for (long k = 0; k < n; ++k) {
+    orc_prim q;
+    unpack(prims + 8 * k, &q);
+    orc_prim_to_cons(&G, gam, &q, U + 8 * k);
+  }
+}
+
 double orc_pt_master(double gam, double q, double r2, double b2, double rb, double mu)
 {
   return orc_c2p_master(gam, q, r2, b2, rb, mu);

@@ -12,7 +12,9 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result",
+    # FP32 (mixed-precision flux path only): hardware divide / sqrt
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+    "-Wall", "-Wno-unused-result",
 ]
 
 

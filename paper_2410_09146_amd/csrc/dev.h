@@ -41,21 +41,42 @@ struct EosP {
 };
 
 // ------------------------------------------------------------------ metric
+//
+// Everything below is templated on the arithmetic type T: FP64 everywhere in
+// the default path; the mixed-precision flux path instantiates the geometry,
+// reconstruction and Riemann solve with float (the densitization by sqrt(-g),
+// U, the face field, the RK accumulation and the inversion stay FP64).
 
-struct Geo {
-  double alpha, beta1;               // lapse, shift (x1 component only)
-  double g11, g13, g22, g33;         // gamma_ij
-  double gi11, gi13, gi22, gi33;     // gamma^ij
-  double sqrtg;                      // sqrt(gamma)
+template <typename T> struct Lim;
+template <> struct Lim<double> {
+  static constexpr double weno_eps = 1e-40;
+  static constexpr bool clamp = false;
+  static constexpr double rmax = 0.0;
+};
+template <> struct Lim<float> {
+  // (tau/(beta+eps))^2 must stay finite in FP32
+  static constexpr float weno_eps = 1e-20f;
+  static constexpr bool clamp = true;
+  static constexpr float rmax = 1e15f;
 };
 
-__device__ __forceinline__ Geo geo_mink()
+template <typename T>
+struct GeoT {
+  T alpha, beta1;               // lapse, shift (x1 component only)
+  T g11, g13, g22, g33;         // gamma_ij
+  T gi11, gi13, gi22, gi33;     // gamma^ij
+  T sqrtg;                      // sqrt(gamma)
+};
+using Geo = GeoT<double>;
+
+template <typename T = double>
+__device__ __forceinline__ GeoT<T> geo_mink()
 {
-  Geo G;
-  G.alpha = 1.0; G.beta1 = 0.0;
-  G.g11 = 1.0; G.g13 = 0.0; G.g22 = 1.0; G.g33 = 1.0;
-  G.gi11 = 1.0; G.gi13 = 0.0; G.gi22 = 1.0; G.gi33 = 1.0;
-  G.sqrtg = 1.0;
+  GeoT<T> G;
+  G.alpha = T(1); G.beta1 = T(0);
+  G.g11 = T(1); G.g13 = T(0); G.g22 = T(1); G.g33 = T(1);
+  G.gi11 = T(1); G.gi13 = T(0); G.gi22 = T(1); G.gi33 = T(1);
+  G.sqrtg = T(1);
   return G;
 }
 
@@ -64,23 +85,24 @@ __device__ __forceinline__ Geo geo_mink()
 // gamma_11 = r^2 (1+z), gamma_13 = -a (1+z) sin^2 r, gamma_22 = Sigma,
 // gamma_33 = sin^2 (Sigma + a^2 (1+z) sin^2); the (1,3) block has
 // determinant r^2 (1+z) sin^2 Sigma, so sqrt(gamma) = r Sigma sin sqrt(1+z).
-__device__ __forceinline__ Geo geo_ks(double r, double s, double c, const MetricP &m)
+template <typename T = double>
+__device__ __forceinline__ GeoT<T> geo_ks(T r, T s, T c, T M, T a)
 {
-  const double a2 = m.a * m.a, s2 = s * s;
-  const double Sig = fma(a2 * c, c, r * r);
-  const double iSig = 1.0 / Sig;
-  const double z = 2.0 * m.M * r * iSig;
-  const double opz = 1.0 + z;
-  const double sq = sqrt(opz);
-  Geo G;
-  G.alpha = 1.0 / sq;
-  const double ir = 1.0 / r;
+  const T a2 = a * a, s2 = s * s;
+  const T Sig = fma(a2 * c, c, r * r);
+  const T iSig = T(1) / Sig;
+  const T z = T(2) * M * r * iSig;
+  const T opz = T(1) + z;
+  const T sq = sqrt(opz);
+  GeoT<T> G;
+  G.alpha = T(1) / sq;
+  const T ir = T(1) / r;
   G.beta1 = z * G.alpha * G.alpha * ir;
   G.g11 = r * r * opz;
-  G.g13 = -m.a * opz * s2 * r;
+  G.g13 = -a * opz * s2 * r;
   G.g22 = Sig;
   G.g33 = s2 * fma(a2 * opz, s2, Sig);
-  const double idet = iSig * ir * ir / (opz * s2);
+  const T idet = iSig * ir * ir / (opz * s2);
   G.gi11 = G.g33 * idet;
   G.gi13 = -G.g13 * idet;
   G.gi33 = G.g11 * idet;
@@ -89,51 +111,60 @@ __device__ __forceinline__ Geo geo_ks(double r, double s, double c, const Metric
   return G;
 }
 
-template <int MK>
-__device__ __forceinline__ Geo geo_at(const Tables &T, const MetricP &m, int ir, bool rface,
-                                      int it, bool tface)
+__device__ __forceinline__ Geo geo_ks(double r, double s, double c, const MetricP &m)
+{
+  return geo_ks<double>(r, s, c, m.M, m.a);
+}
+
+template <int MK, typename T = double>
+__device__ __forceinline__ GeoT<T> geo_at(const Tables &Tb, const MetricP &m, int ir, bool rface,
+                                          int it, bool tface)
 {
   if constexpr (MK == MK_MINK) {
-    return geo_mink();
+    return geo_mink<T>();
   } else {
-    const double r = rface ? T.rf[ir] : T.rc[ir];
-    const double s = tface ? T.sf[it] : T.sc[it];
-    const double c = tface ? T.cf[it] : T.cc[it];
-    return geo_ks(r, s, c, m);
+    const double r = rface ? Tb.rf[ir] : Tb.rc[ir];
+    const double s = tface ? Tb.sf[it] : Tb.sc[it];
+    const double c = tface ? Tb.cf[it] : Tb.cc[it];
+    return geo_ks<T>(T(r), T(s), T(c), T(m.M), T(m.a));
   }
 }
 
 // ------------------------------------------------------------------ physics
 
-struct Prim { double rho, u1, u2, u3, ie, B1, B2, B3; };
+template <typename T> struct PrimT { T rho, u1, u2, u3, ie, B1, B2, B3; };
+using Prim = PrimT<double>;
 
 // Auxiliary 4-vector quantities of a primitive state (Sec. 2.1 kinematics and
 // the b^mu / B^i relation).
-struct Aux {
-  double W, ut2, v1, v2, v3, vl1, vl2, vl3, Bv;
-  double uc1, uc2, uc3;        // u^i (contravariant four-velocity)
-  double b0, bc1, bc2, bc3;    // b^mu
-  double bl1, bl2, bl3;        // b_i
-  double b2, p, w;             // b^2, pressure, rho h
+template <typename T>
+struct AuxT {
+  T W, ut2, v1, v2, v3, vl1, vl2, vl3, Bv;
+  T uc1, uc2, uc3;        // u^i (contravariant four-velocity)
+  T b0, bc1, bc2, bc3;    // b^mu
+  T bl1, bl2, bl3;        // b_i
+  T b2, p, w;             // b^2, pressure, rho h
 };
+using Aux = AuxT<double>;
 
-__device__ __forceinline__ Aux aux_of(const Geo &G, double gam, const Prim &q)
+template <typename T>
+__device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T> &q)
 {
-  Aux A;
-  A.ut2 = G.g11 * q.u1 * q.u1 + 2.0 * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
+  AuxT<T> A;
+  A.ut2 = G.g11 * q.u1 * q.u1 + T(2) * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
           G.g33 * q.u3 * q.u3;
-  A.W = sqrt(1.0 + A.ut2);
-  const double iW = 1.0 / A.W;
+  A.W = sqrt(T(1) + A.ut2);
+  const T iW = T(1) / A.W;
   A.v1 = q.u1 * iW; A.v2 = q.u2 * iW; A.v3 = q.u3 * iW;
   A.vl1 = G.g11 * A.v1 + G.g13 * A.v3;
   A.vl2 = G.g22 * A.v2;
   A.vl3 = G.g13 * A.v1 + G.g33 * A.v3;
   A.Bv = q.B1 * A.vl1 + q.B2 * A.vl2 + q.B3 * A.vl3;
-  const double Bl1 = G.g11 * q.B1 + G.g13 * q.B3;
-  const double Bl2 = G.g22 * q.B2;
-  const double Bl3 = G.g13 * q.B1 + G.g33 * q.B3;
-  const double BB = q.B1 * Bl1 + q.B2 * Bl2 + q.B3 * Bl3;
-  const double ia = 1.0 / G.alpha;
+  const T Bl1 = G.g11 * q.B1 + G.g13 * q.B3;
+  const T Bl2 = G.g22 * q.B2;
+  const T Bl3 = G.g13 * q.B1 + G.g33 * q.B3;
+  const T BB = q.B1 * Bl1 + q.B2 * Bl2 + q.B3 * Bl3;
+  const T ia = T(1) / G.alpha;
   // u^i = W v^i - W beta^i / alpha;  b^i = B^i / W + (alpha b^0 / W) u^i,
   // alpha b^0 = W (B . v)
   A.uc1 = q.u1 - A.W * G.beta1 * ia;
@@ -148,44 +179,46 @@ __device__ __forceinline__ Aux aux_of(const Geo &G, double gam, const Prim &q)
   A.bl2 = G.g22 * A.bc2;
   A.bl3 = G.g13 * (G.beta1 * A.b0 + A.bc1) + G.g33 * A.bc3;
   A.b2 = BB * iW * iW + A.Bv * A.Bv;
-  A.p = (gam - 1.0) * q.ie;
+  A.p = (gam - T(1)) * q.ie;
   A.w = q.rho + q.ie + A.p;
   return A;
 }
 
 // Undensitized conserved vector (D, S_j, tau, B^k).
-__device__ __forceinline__ void cons_of(const Geo &G, const Prim &q, const Aux &A, double U[8])
+template <typename T>
+__device__ __forceinline__ void cons_of(const GeoT<T> &G, const PrimT<T> &q, const AuxT<T> &A,
+                                        T U[8])
 {
-  const double W2 = A.W * A.W;
-  const double D = q.rho * A.W;
-  const double wt = A.w + A.b2;
-  const double ab0 = A.W * A.Bv;     // alpha b^0
+  const T W2 = A.W * A.W;
+  const T D = q.rho * A.W;
+  const T wt = A.w + A.b2;
+  const T ab0 = A.W * A.Bv;     // alpha b^0
   U[0] = D;
   U[1] = wt * W2 * A.vl1 - ab0 * A.bl1;
   U[2] = wt * W2 * A.vl2 - ab0 * A.bl2;
   U[3] = wt * W2 * A.vl3 - ab0 * A.bl3;
   // tau with the rest-mass part rho (W^2 - W) = D ut2 / (W + 1)
-  U[4] = D * A.ut2 / (A.W + 1.0) + (q.ie + A.p + A.b2) * W2 - (A.p + 0.5 * A.b2) - ab0 * ab0;
+  U[4] = D * A.ut2 / (A.W + T(1)) + (q.ie + A.p + A.b2) * W2 - (A.p + T(0.5) * A.b2) - ab0 * ab0;
   U[5] = q.B1; U[6] = q.B2; U[7] = q.B3;
 }
 
 // Undensitized flux along direction DIR (0,1,2) given U.
-template <int DIR>
-__device__ __forceinline__ void flux_of(const Geo &G, const Prim &q, const Aux &A,
-                                        const double U[8], double F[8])
+template <int DIR, typename T>
+__device__ __forceinline__ void flux_of(const GeoT<T> &G, const PrimT<T> &q, const AuxT<T> &A,
+                                        const T U[8], T F[8])
 {
-  const double ia = 1.0 / G.alpha;
-  const double vt1 = G.alpha * A.v1 - G.beta1, vt2 = G.alpha * A.v2, vt3 = G.alpha * A.v3;
-  const double vtd = DIR == 0 ? vt1 : (DIR == 1 ? vt2 : vt3);
-  const double vd = DIR == 0 ? A.v1 : (DIR == 1 ? A.v2 : A.v3);
-  const double Bd = DIR == 0 ? q.B1 : (DIR == 1 ? q.B2 : q.B3);
-  const double pt = A.p + 0.5 * A.b2;
-  const double iW = 1.0 / A.W;
-  const double adv = vtd * ia;
+  const T ia = T(1) / G.alpha;
+  const T vt1 = G.alpha * A.v1 - G.beta1, vt2 = G.alpha * A.v2, vt3 = G.alpha * A.v3;
+  const T vtd = DIR == 0 ? vt1 : (DIR == 1 ? vt2 : vt3);
+  const T vd = DIR == 0 ? A.v1 : (DIR == 1 ? A.v2 : A.v3);
+  const T Bd = DIR == 0 ? q.B1 : (DIR == 1 ? q.B2 : q.B3);
+  const T pt = A.p + T(0.5) * A.b2;
+  const T iW = T(1) / A.W;
+  const T adv = vtd * ia;
   F[0] = U[0] * adv;
-  F[1] = U[1] * adv - A.bl1 * Bd * iW + (DIR == 0 ? pt : 0.0);
-  F[2] = U[2] * adv - A.bl2 * Bd * iW + (DIR == 1 ? pt : 0.0);
-  F[3] = U[3] * adv - A.bl3 * Bd * iW + (DIR == 2 ? pt : 0.0);
+  F[1] = U[1] * adv - A.bl1 * Bd * iW + (DIR == 0 ? pt : T(0));
+  F[2] = U[2] * adv - A.bl2 * Bd * iW + (DIR == 1 ? pt : T(0));
+  F[3] = U[3] * adv - A.bl3 * Bd * iW + (DIR == 2 ? pt : T(0));
   F[4] = U[4] * adv + pt * vd - A.Bv * Bd;
   F[5] = (q.B1 * vtd - Bd * vt1) * ia;
   F[6] = (q.B2 * vtd - Bd * vt2) * ia;
@@ -194,148 +227,164 @@ __device__ __forceinline__ void flux_of(const Geo &G, const Prim &q, const Aux &
 
 // Fast-wave coordinate speeds along DIR from (k.u)^2 (1 - c^2) = c^2 k.k,
 // k_mu = (-lambda, e_DIR), c^2 = cs^2 + ca^2 - cs^2 ca^2.
-template <int DIR>
-__device__ __forceinline__ void speeds_of(const Geo &G, double gam, const Aux &A, double &lm,
-                                          double &lp)
+template <int DIR, typename T>
+__device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T> &A, T &lm, T &lp)
 {
-  const double cs2 = gam * A.p / A.w;
-  const double ca2 = A.b2 / (A.w + A.b2);
-  const double c2 = cs2 + ca2 - cs2 * ca2;
-  const double ia2 = 1.0 / (G.alpha * G.alpha);
-  const double u0 = A.W / G.alpha;
-  const double ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
-  const double g00 = -ia2;
-  const double g0d = DIR == 0 ? G.beta1 * ia2 : 0.0;
-  const double gdd = DIR == 0 ? G.gi11 - G.beta1 * G.beta1 * ia2 : (DIR == 1 ? G.gi22 : G.gi33);
-  const double omc = 1.0 - c2;
-  const double qa = omc * u0 * u0 - c2 * g00;
-  const double qb = -2.0 * (omc * u0 * ud - c2 * g0d);
-  const double qc = omc * ud * ud - c2 * gdd;
-  double disc = qb * qb - 4.0 * qa * qc;
-  disc = disc > 0.0 ? disc : 0.0;
-  const double sq = sqrt(disc);
-  const double i2a = 0.5 / qa;
-  const double l1 = (-qb + sq) * i2a, l2 = (-qb - sq) * i2a;
+  const T cs2 = gam * A.p / A.w;
+  const T ca2 = A.b2 / (A.w + A.b2);
+  const T c2 = cs2 + ca2 - cs2 * ca2;
+  const T ia2 = T(1) / (G.alpha * G.alpha);
+  const T u0 = A.W / G.alpha;
+  const T ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
+  const T g00 = -ia2;
+  const T g0d = DIR == 0 ? G.beta1 * ia2 : T(0);
+  const T gdd = DIR == 0 ? G.gi11 - G.beta1 * G.beta1 * ia2 : (DIR == 1 ? G.gi22 : G.gi33);
+  const T omc = T(1) - c2;
+  const T qa = omc * u0 * u0 - c2 * g00;
+  const T qb = T(-2) * (omc * u0 * ud - c2 * g0d);
+  const T qc = omc * ud * ud - c2 * gdd;
+  T disc = qb * qb - T(4) * qa * qc;
+  disc = disc > T(0) ? disc : T(0);
+  const T sq = sqrt(disc);
+  const T i2a = T(0.5) / qa;
+  const T l1 = (-qb + sq) * i2a, l2 = (-qb - sq) * i2a;
   lp = fmax(l1, l2);
   lm = fmin(l1, l2);
 }
 
-// Densitized face flux (sqrt(-g) F) from left/right states; dissipation on
-// sqrt(gamma) U (speeds are eigenvalues of d(sqrt(-g)F)/d(sqrt(gamma)U)).
+// Face flux of the law d_t(sqrt(gamma) U) + d_i(sqrt(-g) F^i) = ..., returned
+// as two undensitized parts: the densitized flux is sqrt(-g) A + sqrt(gamma) B
+// (the speeds are eigenvalues of d(sqrt(-g)F)/d(sqrt(gamma)U), so the
+// dissipation B acts on sqrt(gamma) U).  The caller densitizes in FP64.
+template <int DIR, int RS, typename T>
+__device__ __forceinline__ void riemann_parts(const GeoT<T> &G, T gam, const PrimT<T> &L,
+                                              const PrimT<T> &R, T A[8], T B[8])
+{
+  T UL[8], UR[8], FL[8], FR[8], lmL, lpL, lmR, lpR;
+  {
+    const AuxT<T> X = aux_of(G, gam, L);
+    cons_of(G, L, X, UL);
+    flux_of<DIR>(G, L, X, UL, FL);
+    speeds_of<DIR>(G, gam, X, lmL, lpL);
+  }
+  {
+    const AuxT<T> X = aux_of(G, gam, R);
+    cons_of(G, R, X, UR);
+    flux_of<DIR>(G, R, X, UR, FR);
+    speeds_of<DIR>(G, gam, X, lmR, lpR);
+  }
+  if constexpr (RS == RS_HLL) {
+    const T cm = fmin(T(0), fmin(lmL, lmR));
+    const T cp = fmax(T(0), fmax(lpL, lpR));
+    const T den = cp - cm;
+    if (den > T(0)) {
+      const T id = T(1) / den;
+      const T a = cp * id, b = cm * id, c = cp * cm * id;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) { A[v] = a * FL[v] - b * FR[v]; B[v] = c * (UR[v] - UL[v]); }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 8; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = T(0); }
+    }
+  } else {
+    const T c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+    const T hc = T(-0.5) * c;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = hc * (UR[v] - UL[v]); }
+  }
+}
+
+// FP64 densitized face flux.
 template <int DIR, int RS>
 __device__ __forceinline__ void riemann(const Geo &G, double gam, const Prim &L, const Prim &R,
                                         double out[8])
 {
-  double UL[8], UR[8], FL[8], FR[8], lmL, lpL, lmR, lpR;
-  {
-    const Aux A = aux_of(G, gam, L);
-    cons_of(G, L, A, UL);
-    flux_of<DIR>(G, L, A, UL, FL);
-    speeds_of<DIR>(G, gam, A, lmL, lpL);
-  }
-  {
-    const Aux A = aux_of(G, gam, R);
-    cons_of(G, R, A, UR);
-    flux_of<DIR>(G, R, A, UR, FR);
-    speeds_of<DIR>(G, gam, A, lmR, lpR);
-  }
-  const double sg = G.sqrtg, smg = G.alpha * G.sqrtg;
-  if constexpr (RS == RS_HLL) {
-    const double cm = fmin(0.0, fmin(lmL, lmR));
-    const double cp = fmax(0.0, fmax(lpL, lpR));
-    const double den = cp - cm;
-    if (den > 0.0) {
-      const double id = 1.0 / den;
-      const double a = cp * smg * id, b = cm * smg * id, c = cp * cm * sg * id;
+  double A[8], B[8];
+  riemann_parts<DIR, RS, double>(G, gam, L, R, A, B);
+  const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) out[v] = a * FL[v] - b * FR[v] + c * (UR[v] - UL[v]);
-    } else {
-#pragma unroll
-      for (int v = 0; v < 8; ++v) out[v] = 0.5 * smg * (FL[v] + FR[v]);
-    }
-  } else {
-    const double c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
-    const double hs = 0.5 * smg, hc = 0.5 * c * sg;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) out[v] = hs * (FL[v] + FR[v]) - hc * (UR[v] - UL[v]);
-  }
+  for (int v = 0; v < 8; ++v) out[v] = smg * A[v] + sg * B[v];
 }
 
 // ---------------------------------------------------------- reconstruction
 
-__device__ __forceinline__ double mc_slope(double dm, double dp)
+template <typename T>
+__device__ __forceinline__ T mc_slope(T dm, T dp)
 {
-  if (dm * dp <= 0.0) return 0.0;
-  const double a = fmin(fmin(2.0 * fabs(dm), 2.0 * fabs(dp)), 0.5 * fabs(dm + dp));
-  return dm > 0.0 ? a : -a;
+  if (dm * dp <= T(0)) return T(0);
+  const T a = fmin(fmin(T(2) * fabs(dm), T(2) * fabs(dp)), T(0.5) * fabs(dm + dp));
+  return dm > T(0) ? a : -a;
 }
 
-__device__ __forceinline__ double minmod_slope(double dm, double dp)
+template <typename T>
+__device__ __forceinline__ T minmod_slope(T dm, T dp)
 {
-  if (dm * dp <= 0.0) return 0.0;
-  const double a = fmin(fabs(dm), fabs(dp));
-  return dm > 0.0 ? a : -a;
+  if (dm * dp <= T(0)) return T(0);
+  const T a = fmin(fabs(dm), fabs(dp));
+  return dm > T(0) ? a : -a;
 }
 
 // One WENO5-Z face value at x_{j+1/2} from f0..f4 = f_{j-2..j+2}; also the
 // per-face measure 3 w0 w1 w2 / (g2 w0 w1 + g1 w0 w2 + g0 w1 w2).
-template <int FV>
-__device__ __forceinline__ double weno_z_face(double f0, double f1, double f2, double f3,
-                                              double f4, double &sig)
+template <int FV, typename T>
+__device__ __forceinline__ T weno_z_face(T f0, T f1, T f2, T f3, T f4, T &sig)
 {
-  constexpr double g0 = FV ? 0.1 : 1.0 / 16.0;
-  constexpr double g1 = FV ? 0.6 : 10.0 / 16.0;
-  constexpr double g2 = FV ? 0.3 : 5.0 / 16.0;
-  const double t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
-  const double t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
-  const double t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
-  constexpr double c13 = 13.0 / 12.0;
-  const double b0 = c13 * t0 * t0 + 0.25 * s0 * s0;
-  const double b1 = c13 * t1 * t1 + 0.25 * s1 * s1;
-  const double b2 = c13 * t2 * t2 + 0.25 * s2 * s2;
-  const double tau = fabs(b0 - b2);
-  const double r0 = tau / (b0 + 1e-40), r1 = tau / (b1 + 1e-40), r2 = tau / (b2 + 1e-40);
-  const double a0 = g0 * (1.0 + r0 * r0), a1 = g1 * (1.0 + r1 * r1), a2 = g2 * (1.0 + r2 * r2);
-  const double is = 1.0 / (a0 + a1 + a2);
-  const double w0 = a0 * is, w1 = a1 * is, w2 = a2 * is;
-  double p0, p1, p2;
-  if constexpr (FV) {
-    p0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * (1.0 / 6.0);
-    p1 = (-f1 + 5.0 * f2 + 2.0 * f3) * (1.0 / 6.0);
-    p2 = (2.0 * f2 + 5.0 * f3 - f4) * (1.0 / 6.0);
-  } else {
-    p0 = (3.0 * f0 - 10.0 * f1 + 15.0 * f2) * 0.125;
-    p1 = (-f1 + 6.0 * f2 + 3.0 * f3) * 0.125;
-    p2 = (3.0 * f2 + 6.0 * f3 - f4) * 0.125;
+  constexpr T g0 = FV ? T(0.1) : T(1.0 / 16.0);
+  constexpr T g1 = FV ? T(0.6) : T(10.0 / 16.0);
+  constexpr T g2 = FV ? T(0.3) : T(5.0 / 16.0);
+  const T t0 = f0 - T(2) * f1 + f2, s0 = f0 - T(4) * f1 + T(3) * f2;
+  const T t1 = f1 - T(2) * f2 + f3, s1 = f1 - f3;
+  const T t2 = f2 - T(2) * f3 + f4, s2 = T(3) * f2 - T(4) * f3 + f4;
+  constexpr T c13 = T(13.0 / 12.0);
+  const T b0 = c13 * t0 * t0 + T(0.25) * s0 * s0;
+  const T b1 = c13 * t1 * t1 + T(0.25) * s1 * s1;
+  const T b2 = c13 * t2 * t2 + T(0.25) * s2 * s2;
+  const T tau = fabs(b0 - b2);
+  constexpr T eps = Lim<T>::weno_eps;
+  T r0 = tau / (b0 + eps), r1 = tau / (b1 + eps), r2 = tau / (b2 + eps);
+  if constexpr (Lim<T>::clamp) {
+    r0 = fmin(r0, Lim<T>::rmax); r1 = fmin(r1, Lim<T>::rmax); r2 = fmin(r2, Lim<T>::rmax);
   }
-  const double w01 = w0 * w1;
-  sig = 3.0 * w01 * w2 / (g2 * w01 + g1 * w0 * w2 + g0 * w1 * w2);
+  const T a0 = g0 * (T(1) + r0 * r0), a1 = g1 * (T(1) + r1 * r1), a2 = g2 * (T(1) + r2 * r2);
+  const T is = T(1) / (a0 + a1 + a2);
+  const T w0 = a0 * is, w1 = a1 * is, w2 = a2 * is;
+  T p0, p1, p2;
+  if constexpr (FV) {
+    p0 = (T(2) * f0 - T(7) * f1 + T(11) * f2) * T(1.0 / 6.0);
+    p1 = (-f1 + T(5) * f2 + T(2) * f3) * T(1.0 / 6.0);
+    p2 = (T(2) * f2 + T(5) * f3 - f4) * T(1.0 / 6.0);
+  } else {
+    p0 = (T(3) * f0 - T(10) * f1 + T(15) * f2) * T(0.125);
+    p1 = (-f1 + T(6) * f2 + T(3) * f3) * T(0.125);
+    p2 = (T(3) * f2 + T(6) * f3 - f4) * T(0.125);
+  }
+  const T w01 = w0 * w1;
+  sig = T(3) * w01 * w2 / (g2 * w01 + g1 * w0 * w2 + g0 * w1 * w2);
   return w0 * p0 + w1 * p1 + w2 * p2;
 }
 
 // Left (j-1/2) and right (j+1/2) face values of cell j.
-template <int RECON, int FV>
-__device__ __forceinline__ void recon5(double f0, double f1, double f2, double f3, double f4,
-                                       double &fl, double &fr)
+template <int RECON, int FV, typename T>
+__device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &fr)
 {
   if constexpr (RECON == RC_CONST) {
     fl = f2; fr = f2;
   } else if constexpr (RECON == RC_PLM_MINMOD) {
-    const double s = minmod_slope(f2 - f1, f3 - f2);
-    fl = f2 - 0.5 * s; fr = f2 + 0.5 * s;
+    const T s = minmod_slope(f2 - f1, f3 - f2);
+    fl = f2 - T(0.5) * s; fr = f2 + T(0.5) * s;
   } else if constexpr (RECON == RC_PLM_MC) {
-    const double s = mc_slope(f2 - f1, f3 - f2);
-    fl = f2 - 0.5 * s; fr = f2 + 0.5 * s;
+    const T s = mc_slope(f2 - f1, f3 - f2);
+    fl = f2 - T(0.5) * s; fr = f2 + T(0.5) * s;
   } else {
-    const double s = mc_slope(f2 - f1, f3 - f2);
-    double sp, sm;
-    const double pr = weno_z_face<FV>(f0, f1, f2, f3, f4, sp);
-    const double pl = weno_z_face<FV>(f4, f3, f2, f1, f0, sm);   // mirror x -> -x
-    double sigma = 2.0 * sp * sm / (sp + sm);
-    sigma = sigma > 0.0 ? sigma : 0.0;                            // also maps NaN to 0
-    sigma = sigma < 1.0 ? sigma : 1.0;
-    fr = sigma * pr + (1.0 - sigma) * (f2 + 0.5 * s);
-    fl = sigma * pl + (1.0 - sigma) * (f2 - 0.5 * s);
+    const T s = mc_slope(f2 - f1, f3 - f2);
+    T sp, sm;
+    const T pr = weno_z_face<FV>(f0, f1, f2, f3, f4, sp);
+    const T pl = weno_z_face<FV>(f4, f3, f2, f1, f0, sm);   // mirror x -> -x
+    T sigma = T(2) * sp * sm / (sp + sm);
+    sigma = sigma > T(0) ? sigma : T(0);                     // also maps NaN to 0
+    sigma = sigma < T(1) ? sigma : T(1);
+    fr = sigma * pr + (T(1) - sigma) * (f2 + T(0.5) * s);
+    fl = sigma * pl + (T(1) - sigma) * (f2 - T(0.5) * s);
   }
 }
 

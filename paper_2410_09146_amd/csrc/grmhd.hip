@@ -43,7 +43,7 @@ struct Plan {
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_tiles[3], o_planes[3], o_chi, o_che,
-      o_chb, o_gP, o_gB, o_part, o_res, o_mlp, total;
+      o_chb, o_gP, o_gB, o_part, o_res, o_mlp, o_mlpw, o_mlpf, total;
 };
 
 int fail(const std::string &m, int code)
@@ -59,7 +59,8 @@ int validate(const grmhd_pack_desc *d)
   if (d->ng != 4) return fail("ng must be 4", GRMHD_E_UNSUPPORTED);
   if (d->recon < 0 || d->recon > 3) return fail("bad recon", GRMHD_E_INVALID);
   if (d->riemann < 0 || d->riemann > 1) return fail("bad riemann", GRMHD_E_INVALID);
-  if (d->precision != GRMHD_PREC_FP64) return fail("only FP64 precision", GRMHD_E_UNSUPPORTED);
+  if (d->precision != GRMHD_PREC_FP64 && d->precision != GRMHD_PREC_MIXED)
+    return fail("bad precision", GRMHD_E_INVALID);
   if (!d->nx || !d->lloc) return fail("null nx/lloc", GRMHD_E_INVALID);
   for (int s = 0; s < 6; ++s)
     if (d->bc[s] < 0 || d->bc[s] > 3) return fail("bad boundary kind", GRMHD_E_INVALID);
@@ -317,6 +318,8 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
   p.o_res = take(sizeof(double) * 32);
   p.o_mlp = take(sizeof(float) * (size_t)p.nct);
+  p.o_mlpw = take(sizeof(unsigned short) * MLPB_N);
+  p.o_mlpf = take(sizeof(float) * MLPF_N);
   p.total = o;
   return GRMHD_OK;
 }
@@ -333,6 +336,12 @@ struct grmhd_pack {
   bool mlp_bound = false;
   // optional per-kernel-family timing with events on the pack's stream
   bool prof = false;
+  // captured SSPRK2 step (dt read on the device)
+  hipGraphExec_t gexec = nullptr;
+  int g_guess = -1;
+  double g_cfl = 0.0;
+  grmhd_metric g_metric{};
+  grmhd_eos g_eos{};
   std::vector<hipEvent_t> ev_free;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_rec;
   KArgs args() const
@@ -441,48 +450,55 @@ const T *dptr(const grmhd_pack *p, size_t off) { return (const T *)(p->ws + off)
 
 // ---- templated launch helpers (host dispatch over compile-time options)
 
-template <int MK, int D, int RC, int FV, int RS>
+template <int MK, int D, int RC, int FV, int RS, typename T>
 void launch_flux(grmhd_pack *p, const KArgs &a)
 {
   const Plan &pl = p->plan;
   if (!pl.tiles[D].empty()) {
     Prof t(p, GRMHD_PROF_FLUX_X1 + D);
-    hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS>), dim3(pl.tiles[D].size()), dim3(256), 0,
+    hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T>), dim3(pl.tiles[D].size()), dim3(256), 0,
                        p->stream, a, dptr<int4>(p, pl.o_tiles[D]));
   }
   if (!pl.planes[D].empty()) {
     Prof t(p, GRMHD_PROF_FLUX_PLANE);
-    hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS>), dim3(pl.planes[D].size()), dim3(256),
+    hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS, T>), dim3(pl.planes[D].size()), dim3(256),
                        0, p->stream, a, dptr<int2>(p, pl.o_planes[D]));
   }
 }
 
-template <int MK, int RC, int FV, int RS>
+template <int MK, int RC, int FV, int RS, typename T>
 void launch_flux3(grmhd_pack *p, const KArgs &a)
 {
-  launch_flux<MK, 0, RC, FV, RS>(p, a);
-  launch_flux<MK, 1, RC, FV, RS>(p, a);
-  launch_flux<MK, 2, RC, FV, RS>(p, a);
+  launch_flux<MK, 0, RC, FV, RS, T>(p, a);
+  launch_flux<MK, 1, RC, FV, RS, T>(p, a);
+  launch_flux<MK, 2, RC, FV, RS, T>(p, a);
 }
 
-template <int MK, int RC, int FV>
+template <int MK, int RC, int FV, typename T>
 void launch_flux_rs(grmhd_pack *p, const KArgs &a, int rs)
 {
-  if (rs == RS_HLL) launch_flux3<MK, RC, FV, RS_HLL>(p, a);
-  else launch_flux3<MK, RC, FV, RS_LLF>(p, a);
+  if (rs == RS_HLL) launch_flux3<MK, RC, FV, RS_HLL, T>(p, a);
+  else launch_flux3<MK, RC, FV, RS_LLF, T>(p, a);
+}
+
+template <int MK, typename T>
+void launch_flux_rc(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs)
+{
+  switch (rc) {
+    case RC_CONST: launch_flux_rs<MK, RC_CONST, 0, T>(p, a, rs); break;
+    case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0, T>(p, a, rs); break;
+    case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0, T>(p, a, rs); break;
+    default:
+      if (fv) launch_flux_rs<MK, RC_WENO, 1, T>(p, a, rs);
+      else launch_flux_rs<MK, RC_WENO, 0, T>(p, a, rs);
+  }
 }
 
 template <int MK>
-void launch_flux_all(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs)
+void launch_flux_all(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs, int prec)
 {
-  switch (rc) {
-    case RC_CONST: launch_flux_rs<MK, RC_CONST, 0>(p, a, rs); break;
-    case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0>(p, a, rs); break;
-    case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0>(p, a, rs); break;
-    default:
-      if (fv) launch_flux_rs<MK, RC_WENO, 1>(p, a, rs);
-      else launch_flux_rs<MK, RC_WENO, 0>(p, a, rs);
-  }
+  if (prec == GRMHD_PREC_MIXED) launch_flux_rc<MK, float>(p, a, rc, fv, rs);
+  else launch_flux_rc<MK, double>(p, a, rc, fv, rs);
 }
 
 }  // namespace
@@ -575,6 +591,7 @@ int grmhd_pack_destroy(grmhd_pack *p)
     (void)hipEventDestroy(std::get<2>(r));
   }
   for (hipEvent_t e : p->ev_free) (void)hipEventDestroy(e);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
   delete p;
   return GRMHD_OK;
 }
@@ -584,6 +601,7 @@ int grmhd_bind_state(grmhd_pack *p, const grmhd_state_ptrs *state)
   if (!p || !state || !state->P || !state->Bf || !state->U || !state->U0 || !state->Bf0)
     return perr(p, "null pointer", GRMHD_E_INVALID);
   p->st = *state;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
   return GRMHD_OK;
 }
 
@@ -628,8 +646,9 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   fill_eos(a, eos);
   const Plan &pl = p->plan;
   const int rc = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
-  if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rc, fv, rs);
-  else launch_flux_all<MK_MINK>(p, a, rc, fv, rs);
+  const int prec = p->desc.precision;
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rc, fv, rs, prec);
+  else launch_flux_all<MK_MINK>(p, a, rc, fv, rs, prec);
   LAUNCHCHK(p);
   const double *dtd = dptr<double>(p, pl.o_res);
   const int save = rk[1] == 0.0;
@@ -659,6 +678,18 @@ int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
   const dim3 g(pl.ch_int.size());
   const int2 *ch = dptr<int2>(p, pl.o_chi);
   const float *mlp = dptr<float>(p, pl.o_mlp);
+  if (guess == GRMHD_GUESS_MLP) {
+    Prof tm(p, GRMHD_PROF_MLP);
+    MlpDev md{dptr<unsigned short>(p, pl.o_mlpw), dptr<float>(p, pl.o_mlpf)};
+    float *mu = (float *)(p->ws + pl.o_mlp);
+    if (m->kind == GRMHD_METRIC_KS_LOGSPH)
+      hipLaunchKernelGGL(k_mlp_guess<MK_KS>, dim3(4 * pl.ch_int.size()), dim3(64), 0, p->stream, a,
+                         md, ch, mu);
+    else
+      hipLaunchKernelGGL(k_mlp_guess<MK_MINK>, dim3(4 * pl.ch_int.size()), dim3(64), 0, p->stream,
+                         a, md, ch, mu);
+    LAUNCHCHK(p);
+  }
   Prof t(p, GRMHD_PROF_C2P);
   if (m->kind == GRMHD_METRIC_KS_LOGSPH) {
     if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
@@ -737,9 +768,139 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
       const long long live = std::min<long long>(256, nb - c.y);
       nwave += (live + 63) / 64;
     }
+    out->guess_fallback = (long long)h[14];
     out->c2p_iter_mean = ncell ? h[10] / ncell : 0.0;
     out->c2p_iter_wavemax_mean = nwave ? h[11] / nwave : 0.0;
   }
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_bind(grmhd_pack *p, const float *params, const float *feat_mean,
+                   const float *feat_std)
+{
+  if (!p || !params || !feat_mean || !feat_std) return perr(p, "null pointer", GRMHD_E_INVALID);
+  const Plan &pl = p->plan;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((64 * 64 + 255) / 256), dim3(256), 0, p->stream, params,
+                     feat_mean, feat_std, (unsigned short *)(p->ws + pl.o_mlpw),
+                     (float *)(p->ws + pl.o_mlpf));
+  LAUNCHCHK(p);
+  p->mlp_bound = true;
+  return GRMHD_OK;
+}
+
+size_t grmhd_mlp_scratch_bytes(int batch)
+{
+  if (batch < 1) return 0;
+  const size_t b = (size_t)batch;
+  // Z1 H1 Z2 H2 Z3 H3 d1 d2 d3 (64 each), out, d4 (2 each), grads, loss partials,
+  // BF16 weights + FP32 biases for the MFMA inference
+  size_t f = 9 * 64 * b + 2 * 2 * b + MLP_NPARAM + (b + 255) / 256 + 4;
+  return align_up(f * sizeof(float)) + align_up(MLPB_N * 2) + align_up(MLPF_N * 4);
+}
+
+namespace {
+struct MlpScratch {
+  float *Z1, *H1, *Z2, *H2, *Z3, *H3, *d1, *d2, *d3, *out, *d4, *grad, *part, *loss;
+  unsigned short *w;
+  float *f;
+};
+MlpScratch carve(void *s, int batch)
+{
+  float *q = (float *)s;
+  const size_t b = (size_t)batch;
+  MlpScratch m;
+  m.Z1 = q; q += 64 * b; m.H1 = q; q += 64 * b; m.Z2 = q; q += 64 * b; m.H2 = q; q += 64 * b;
+  m.Z3 = q; q += 64 * b; m.H3 = q; q += 64 * b; m.d1 = q; q += 64 * b; m.d2 = q; q += 64 * b;
+  m.d3 = q; q += 64 * b; m.out = q; q += 2 * b; m.d4 = q; q += 2 * b;
+  m.grad = q; q += MLP_NPARAM; m.part = q; q += (b + 255) / 256; m.loss = q; q += 4;
+  size_t fb = 9 * 64 * b + 2 * 2 * b + MLP_NPARAM + (b + 255) / 256 + 4;
+  char *c = (char *)s + align_up(fb * sizeof(float));
+  m.w = (unsigned short *)c;
+  m.f = (float *)(c + align_up(MLPB_N * 2));
+  return m;
+}
+
+dim3 g256(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// forward + loss + backward into m.grad; returns 0 or a HIP error
+hipError_t mlp_fwd_bwd(const float *P, const float *X, const float *Y, int B, MlpScratch &m,
+                       hipStream_t st)
+{
+  const float *W1 = P + MLP_OFF_W1, *b1 = P + MLP_OFF_B1, *W2 = P + MLP_OFF_W2,
+              *b2 = P + MLP_OFF_B2, *W3 = P + MLP_OFF_W3, *b3 = P + MLP_OFF_B3,
+              *W4 = P + MLP_OFF_W4, *b4 = P + MLP_OFF_B4;
+  float *g = m.grad;
+  hipLaunchKernelGGL(k_dense_fwd, g256((size_t)B * 64), dim3(256), 0, st, X, 5, W1, b1, 64, m.Z1, m.H1, B, 1);
+  hipLaunchKernelGGL(k_dense_fwd, g256((size_t)B * 64), dim3(256), 0, st, m.H1, 64, W2, b2, 64, m.Z2, m.H2, B, 1);
+  hipLaunchKernelGGL(k_dense_fwd, g256((size_t)B * 64), dim3(256), 0, st, m.H2, 64, W3, b3, 64, m.Z3, m.H3, B, 1);
+  hipLaunchKernelGGL(k_dense_fwd, g256((size_t)B * 2), dim3(256), 0, st, m.H3, 64, W4, b4, 2, m.out, m.out, B, 0);
+  hipLaunchKernelGGL(k_mse, g256(B), dim3(256), 0, st, m.out, Y, B, m.d4, m.part);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, m.part, (B + 255) / 256, m.loss);
+  hipLaunchKernelGGL(k_dense_bwd_weight, g256(2 * 65), dim3(256), 0, st, m.d4, 2, m.H3, 64, B,
+                     g + MLP_OFF_W4, g + MLP_OFF_B4);
+  hipLaunchKernelGGL(k_dense_bwd_data, g256((size_t)B * 64), dim3(256), 0, st, m.d4, 2, W4, 64, m.Z3, m.d3, B);
+  hipLaunchKernelGGL(k_dense_bwd_weight, g256(64 * 65), dim3(256), 0, st, m.d3, 64, m.H2, 64, B,
+                     g + MLP_OFF_W3, g + MLP_OFF_B3);
+  hipLaunchKernelGGL(k_dense_bwd_data, g256((size_t)B * 64), dim3(256), 0, st, m.d3, 64, W3, 64, m.Z2, m.d2, B);
+  hipLaunchKernelGGL(k_dense_bwd_weight, g256(64 * 65), dim3(256), 0, st, m.d2, 64, m.H1, 64, B,
+                     g + MLP_OFF_W2, g + MLP_OFF_B2);
+  hipLaunchKernelGGL(k_dense_bwd_data, g256((size_t)B * 64), dim3(256), 0, st, m.d2, 64, W2, 64, m.Z1, m.d1, B);
+  hipLaunchKernelGGL(k_dense_bwd_weight, g256(64 * 6), dim3(256), 0, st, m.d1, 64, X, 5, B,
+                     g + MLP_OFF_W1, g + MLP_OFF_B1);
+  return hipGetLastError();
+}
+}  // namespace
+
+int grmhd_mlp_grad(const float *params, const float *X, const float *Y, int batch, float *grad,
+                   float *loss, void *scratch, size_t scratch_bytes, void *hip_stream)
+{
+  if (!params || !X || !Y || !grad || !loss || !scratch || batch < 1)
+    return fail("null pointer or empty batch", GRMHD_E_INVALID);
+  if (scratch_bytes < grmhd_mlp_scratch_bytes(batch)) return fail("scratch too small", GRMHD_E_SHAPE);
+  hipStream_t st = (hipStream_t)hip_stream;
+  MlpScratch m = carve(scratch, batch);
+  hipError_t e = mlp_fwd_bwd(params, X, Y, batch, m, st);
+  if (!e) e = hipMemcpyAsync(grad, m.grad, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice, st);
+  if (!e) e = hipMemcpyAsync(loss, m.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e) return fail(std::string("mlp grad: ") + hipGetErrorString(e), GRMHD_E_HIP);
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *X,
+                         const float *Y, int batch, float lr, int t, float *loss, void *scratch,
+                         size_t scratch_bytes, void *hip_stream)
+{
+  if (!params || !adam_m || !adam_v || !X || !Y || !loss || !scratch || batch < 1 || t < 1)
+    return fail("bad argument", GRMHD_E_INVALID);
+  if (scratch_bytes < grmhd_mlp_scratch_bytes(batch)) return fail("scratch too small", GRMHD_E_SHAPE);
+  hipStream_t st = (hipStream_t)hip_stream;
+  MlpScratch m = carve(scratch, batch);
+  hipError_t e = mlp_fwd_bwd(params, X, Y, batch, m, st);
+  if (!e) {
+    hipLaunchKernelGGL(k_adam, g256(MLP_NPARAM), dim3(256), 0, st, params, m.grad, adam_m, adam_v,
+                       MLP_NPARAM, lr, 0.9f, 0.999f, 1e-8f, t);
+    e = hipGetLastError();
+  }
+  if (!e) e = hipMemcpyAsync(loss, m.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e) return fail(std::string("mlp train: ") + hipGetErrorString(e), GRMHD_E_HIP);
+  return GRMHD_OK;
+}
+
+int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *feat_std,
+                    const float *X, float *Y, int n, void *scratch, size_t scratch_bytes,
+                    void *hip_stream)
+{
+  if (!params || !feat_mean || !feat_std || !X || !Y || !scratch || n < 1)
+    return fail("bad argument", GRMHD_E_INVALID);
+  if (scratch_bytes < grmhd_mlp_scratch_bytes(1)) return fail("scratch too small", GRMHD_E_SHAPE);
+  hipStream_t st = (hipStream_t)hip_stream;
+  MlpScratch m = carve(scratch, 1);
+  hipLaunchKernelGGL(k_mlp_pack, dim3((64 * 64 + 255) / 256), dim3(256), 0, st, params,
+                     feat_mean, feat_std, m.w, m.f);
+  MlpDev md{m.w, m.f};
+  hipLaunchKernelGGL(k_mlp_infer, dim3((n + 63) / 64), dim3(64), 0, st, md, X, Y, n);
+  hipError_t e = hipGetLastError();
+  if (e) return fail(std::string("mlp infer: ") + hipGetErrorString(e), GRMHD_E_HIP);
   return GRMHD_OK;
 }
 
@@ -749,6 +910,51 @@ int grmhd_debug_ptrs(grmhd_pack *p, void **flags, void **iters, void **flux)
   if (flags) *flags = p->ws + p->plan.o_flags;
   if (iters) *iters = p->ws + p->plan.o_iters;
   if (flux) *flux = p->ws + p->plan.o_F;
+  return GRMHD_OK;
+}
+
+int grmhd_step(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, double dt, int guess,
+               double cfl)
+{
+  static const double rk1[3] = {1.0, 0.0, 1.0}, rk2[3] = {0.5, 0.5, 0.5};
+  int rc;
+  if ((rc = grmhd_stage(p, m, eos, dt, rk1))) return rc;
+  if ((rc = grmhd_con2prim(p, m, eos, guess))) return rc;
+  if ((rc = grmhd_fill_ghosts(p, m))) return rc;
+  if ((rc = grmhd_stage(p, m, eos, dt, rk2))) return rc;
+  if ((rc = grmhd_con2prim(p, m, eos, guess))) return rc;
+  if ((rc = grmhd_fill_ghosts(p, m))) return rc;
+  if (cfl > 0.0 && (rc = grmhd_reductions(p, m, eos, cfl, nullptr))) return rc;
+  return GRMHD_OK;
+}
+
+int grmhd_step_graph(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess,
+                     double cfl, int nsteps)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  if (!(cfl > 0.0) || nsteps < 0) return perr(p, "need cfl > 0 and nsteps >= 0", GRMHD_E_INVALID);
+  const bool same = p->gexec && p->g_guess == guess && p->g_cfl == cfl &&
+                    !std::memcmp(&p->g_metric, m, sizeof *m) &&
+                    !std::memcmp(&p->g_eos, eos, sizeof *eos);
+  if (!same) {
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    const bool prof = p->prof;
+    p->prof = false;                          // no event records inside the graph
+    HIPCHK(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = grmhd_step(p, m, eos, -1.0, guess, cfl);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(p->stream, &g);
+    p->prof = prof;
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (ec != hipSuccess) return perr(p, std::string("capture: ") + hipGetErrorString(ec), GRMHD_E_HIP);
+    const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return perr(p, std::string("instantiate: ") + hipGetErrorString(ei), GRMHD_E_HIP);
+    p->g_guess = guess; p->g_cfl = cfl; p->g_metric = *m; p->g_eos = *eos;
+  }
+  for (int s = 0; s < nsteps; ++s) HIPCHK(p, hipGraphLaunch(p->gexec, p->stream));
   return GRMHD_OK;
 }
 

@@ -11,6 +11,7 @@
 //   k_reduce / k_reduce_fin CFL dt, div B, conserved totals, inversion stats
 #pragma once
 #include "dev.h"
+#include "mlp.h"
 
 namespace grmhd {
 
@@ -100,10 +101,10 @@ __device__ __forceinline__ Geo geo_face(const KArgs &a, const BlockInfo &b, int 
   return geo_at<MK>(a.tab, a.met, b.tab1 + i, D == 0, b.tab2 + j, D == 1);
 }
 
-template <int D>
-__device__ __forceinline__ Prim make_prim(const double q[7], double bn)
+template <int D, typename T>
+__device__ __forceinline__ PrimT<T> make_prim(const T q[7], T bn)
 {
-  Prim p;
+  PrimT<T> p;
   p.rho = q[0]; p.u1 = q[1]; p.u2 = q[2]; p.u3 = q[3]; p.ie = q[4];
   if constexpr (D == 0) { p.B1 = bn; p.B2 = q[5]; p.B3 = q[6]; }
   if constexpr (D == 1) { p.B1 = q[5]; p.B2 = bn; p.B3 = q[6]; }
@@ -111,10 +112,21 @@ __device__ __forceinline__ Prim make_prim(const double q[7], double bn)
   return p;
 }
 
-template <int MK, int D, int RS>
+template <typename T>
+__device__ __forceinline__ GeoT<T> geo_cast(const Geo &G)
+{
+  GeoT<T> g;
+  g.alpha = T(G.alpha); g.beta1 = T(G.beta1);
+  g.g11 = T(G.g11); g.g13 = T(G.g13); g.g22 = T(G.g22); g.g33 = T(G.g33);
+  g.gi11 = T(G.gi11); g.gi13 = T(G.gi13); g.gi22 = T(G.gi22); g.gi33 = T(G.gi33);
+  g.sqrtg = T(G.sqrtg);
+  return g;
+}
+
+// Riemann solve at one face in arithmetic T; densitization in FP64.
+template <int MK, int D, int RS, typename T>
 __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo &b, int i, int j,
-                                                long long c, const double qL[7],
-                                                const double qR[7])
+                                                long long c, const T qL[7], const T qR[7])
 {
   if (D == 1 && (j == b.pole_lo || j == b.pole_hi)) {   // sqrt(-g) = 0 on the axis
 #pragma unroll
@@ -123,30 +135,37 @@ __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo 
   }
   const Geo G = geo_face<MK, D>(a, b, i, j);
   const double bn = a.Bf[D * a.nct + c] / G.sqrtg;
-  const Prim L = make_prim<D>(qL, bn), R = make_prim<D>(qR, bn);
-  double out[8];
-  riemann<D, RS>(G, a.eos.gam, L, R, out);
+  const PrimT<T> L = make_prim<D>(qL, T(bn)), R = make_prim<D>(qR, T(bn));
+  T A[8], B[8];
+  if constexpr (sizeof(T) == sizeof(double)) {
+    riemann_parts<D, RS, T>(G, a.eos.gam, L, R, A, B);
+  } else {
+    riemann_parts<D, RS, T>(geo_cast<T>(G), T(a.eos.gam), L, R, A, B);
+  }
+  const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
-  for (int v = 0; v < 8; ++v) a.F[(D * 8 + v) * a.nct + c] = out[v];
+  for (int v = 0; v < 8; ++v)
+    a.F[(D * 8 + v) * a.nct + c] = smg * (double)A[v] + sg * (double)B[v];
 }
 
-__device__ __forceinline__ void positivity(int v, double f2, double &l, double &r)
+template <typename T>
+__device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
 {
   if (v == 0 || v == 4) {
-    if (!(l > 0.0) || !isfinite(l)) l = f2;
-    if (!(r > 0.0) || !isfinite(r)) r = f2;
+    if (!(l > T(0)) || !isfinite(l)) l = f2;
+    if (!(r > T(0)) || !isfinite(r)) r = f2;
   }
 }
 
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
-template <int MK, int D, int RECON, int FV, int RS>
+template <int MK, int D, int RECON, int FV, int RS, typename T>
 __global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ tiles)
 {
-  __shared__ double stg[NV * TA * NS];
-  __shared__ double sfl[NV * TA * NR];
-  __shared__ double sfr[NV * TA * NR];
+  __shared__ T stg[NV * TA * NS];
+  __shared__ T sfl[NV * TA * NR];
+  __shared__ T sfr[NV * TA * NR];
   constexpr int AX = (D == 0) ? 1 : 0;
   const int4 t = tiles[blockIdx.x];
   const BlockInfo b = a.blocks[t.x];
@@ -166,16 +185,16 @@ __global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ 
     double val;
     if (v < 5) val = a.P[v * a.nct + c];
     else val = a.Bcc[tcomp<D>(v - 5) * a.nct + c];
-    stg[(v * TA + aa) * NS + s] = val;
+    stg[(v * TA + aa) * NS + s] = T(val);
   }
   __syncthreads();
 
   // reconstruct every (variable, column, cell) of cells org[D]-1 .. org[D]+TD-1
   for (int it = tid; it < NV * TA * NR; it += 256) {
     const int cc = it % NR, aa = (it / NR) % TA, v = it / (NR * TA);
-    const double *f = &stg[(v * TA + aa) * NS + cc];
-    double l, r;
-    recon5<RECON, FV>(f[0], f[1], f[2], f[3], f[4], l, r);
+    const T *f = &stg[(v * TA + aa) * NS + cc];
+    T l, r;
+    recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
     positivity(v, f[2], l, r);
     sfl[it] = l;
     sfr[it] = r;
@@ -191,17 +210,17 @@ __global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ 
   if (idx[D] >= a.ng + b.n[D]) return;
   if (idx[AX] > a.ng + b.n[AX] || idx[AX] >= b.s[AX]) return;
   const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-  double qL[7], qR[7];
+  T qL[7], qR[7];
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     qL[v] = sfr[(v * TA + aa) * NR + fd];        // right face of cell idx[D]-1
     qR[v] = sfl[(v * TA + aa) * NR + fd + 1];    // left face of cell idx[D]
   }
-  face_flux_store<MK, D, RS>(a, b, idx[0], idx[1], c, qL, qR);
+  face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
 }
 
 // Faces on the upper boundary plane along D (index ng + n_D), one per thread.
-template <int MK, int D, int RECON, int FV, int RS>
+template <int MK, int D, int RECON, int FV, int RS, typename T>
 __global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restrict__ chunks)
 {
   constexpr int AX = (D == 0) ? 1 : 0;
@@ -218,22 +237,22 @@ __global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restr
   const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
   const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
   const long long sd = str[D];
-  double qL[7], qR[7];
+  T qL[7], qR[7];
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const double *arr = v < 5 ? a.P + v * a.nct : a.Bcc + tcomp<D>(v - 5) * a.nct;
-    double f[6];
+    T f[6];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) f[m] = arr[c + (m - 3) * sd];
-    double l, r;
-    recon5<RECON, FV>(f[0], f[1], f[2], f[3], f[4], l, r);   // cell idx-1
+    for (int m = 0; m < 6; ++m) f[m] = T(arr[c + (m - 3) * sd]);
+    T l, r;
+    recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);   // cell idx-1
     positivity(v, f[2], l, r);
     qL[v] = r;
-    recon5<RECON, FV>(f[1], f[2], f[3], f[4], f[5], l, r);   // cell idx
+    recon5<RECON, FV, T>(f[1], f[2], f[3], f[4], f[5], l, r);   // cell idx
     positivity(v, f[3], l, r);
     qR[v] = l;
   }
-  face_flux_store<MK, D, RS>(a, b, idx[0], idx[1], c, qL, qR);
+  face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
 }
 
 // ------------------------------------------------------------------ update
@@ -393,6 +412,7 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
         if constexpr (GUESS == 2) {
           const float g = mlp_mu[c];
           if (g > 0.0f && g <= 1.0f) mu = (double)g;
+          else flag |= 16;                       // learned guess rejected: previous P
         }
       }
       if (!(mu > 0.0 && mu <= 1.0)) mu = 0.5;
@@ -445,7 +465,7 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
   }
   a.P[c] = q.rho; a.P[n + c] = q.u1; a.P[2 * n + c] = q.u2; a.P[3 * n + c] = q.u3;
   a.P[4 * n + c] = q.ie;
-  if (flag) cons_store<MK>(a, c, G, q);
+  if (flag & 15) cons_store<MK>(a, c, G, q);
   a.flags[c] = (int8_t)flag;
   a.iters[c] = (uint8_t)min(iters, 255);
 }
@@ -475,7 +495,7 @@ __global__ __launch_bounds__(256) void k_p2c(KArgs a, const int2 *__restrict__ c
 
 // -------------------------------------------------------------- reductions
 
-constexpr int NPART = 12;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax
+constexpr int NPART = 13;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax, guess fallback
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -533,6 +553,7 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict_
     val[8] = (fl & 8) ? 1.0 : 0.0;
     val[9] = (fl & 7) ? 1.0 : 0.0;
     val[10] = (double)a.iters[c];
+    val[12] = (fl & 16) ? 1.0 : 0.0;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const double itmax = wave_max(val[10]);
@@ -541,6 +562,7 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict_
 #pragma unroll
   for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
   val[11] = itmax;
+  val[12] = wave_sum(val[12]);
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
@@ -583,7 +605,53 @@ __global__ __launch_bounds__(256) void k_reduce_fin(const double *__restrict__ p
     res[2] = o[1];
     for (int v = 0; v < 5; ++v) res[3 + v] = o[3 + v];
     res[8] = o[8]; res[9] = o[9]; res[10] = o[10]; res[11] = o[11];
-    res[12] = o[2]; res[13] = o[0];
+    res[12] = o[2]; res[13] = o[0]; res[14] = o[12];
+  }
+}
+
+// ----------------------------------------------------------- learned guess
+
+// mu0 = exp(-y1) of the BF16 network for every interior cell (64-cell
+// wavefronts, 4 per 256-cell chunk); -1 marks a rejected guess.
+template <int MK>
+__global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
+                                                  const int2 *__restrict__ chunks,
+                                                  float *__restrict__ mu_out)
+{
+  __shared__ unsigned short X[64 * 16], H1[64 * 64], H2[64 * 64];
+  __shared__ float out[64 * MLP_OUT];
+  const int lane = threadIdx.x;
+  const int2 ch = chunks[blockIdx.x >> 2];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + 64 * (blockIdx.x & 3) + lane;
+  const bool live = e < b.n[0] * b.n[1] * b.n[2];
+  float x[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  long long c = 0;
+  if (live) {
+    const int ng = a.ng;
+    const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+    const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+    c = b.off + i + sj * j + sk * k;
+    const long long n = a.nct;
+    const Geo G = geo_center<MK>(a, b, i, j);
+    const double isg = 1.0 / G.sqrtg;
+    const double D = a.U[c] * isg, S1 = a.U[n + c] * isg, S2 = a.U[2 * n + c] * isg;
+    const double S3 = a.U[3 * n + c] * isg, tau = a.U[4 * n + c] * isg;
+    const double B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
+    const double B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
+    const double B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
+    const double SS = G.gi11 * S1 * S1 + 2.0 * G.gi13 * S1 * S3 + G.gi22 * S2 * S2 + G.gi33 * S3 * S3;
+    const double BB = G.g11 * B1 * B1 + 2.0 * G.g13 * B1 * B3 + G.g22 * B2 * B2 + G.g33 * B3 * B3;
+    const double SB = S1 * B1 + S2 * B2 + S3 * B3;
+    if (D > 0.0) mlp_features(D, SS, tau, BB, SB, m.f + MLPF_MEAN, m.f + MLPF_ISTD, x);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) X[lane * 16 + q] = q < 5 ? f2bf(x[q]) : 0;
+  __syncthreads();
+  mlp_wave(m, X, H1, H2, out, lane);
+  if (live) {
+    const float mu = expf(-out[lane * 2 + 1]);
+    mu_out[c] = (mu > 0.0f && mu <= 1.0f) ? mu : -1.0f;
   }
 }
 

@@ -48,16 +48,20 @@ class ReductionOut(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("divb_rel", ctypes.c_double),
                 ("divb_max", ctypes.c_double), ("totals", ctypes.c_double * 5),
                 ("c2p_fail", ctypes.c_longlong), ("floor_hits", ctypes.c_longlong),
-                ("c2p_iter_mean", ctypes.c_double), ("c2p_iter_wavemax_mean", ctypes.c_double)]
+                ("c2p_iter_mean", ctypes.c_double), ("c2p_iter_wavemax_mean", ctypes.c_double),
+                ("guess_fallback", ctypes.c_longlong)]
 
 
 EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_pack_create", "grmhd_pack_destroy", "grmhd_bind_state", "grmhd_fill_ghosts",
            "grmhd_stage", "grmhd_con2prim", "grmhd_prim_to_cons", "grmhd_reductions",
-           "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_last_error"]
+           "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_mlp_bind",
+           "grmhd_mlp_scratch_bytes", "grmhd_mlp_grad", "grmhd_mlp_train_step",
+           "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_last_error"]
 
 PROF_FAMILIES = ["flux_x1", "flux_x2", "flux_x3", "flux_plane", "update", "con2prim",
-                 "ghost", "bcc", "reduce"]
+                 "ghost", "bcc", "reduce", "mlp"]
+MLP_NPARAM = 8834
 
 _lib = None
 
@@ -89,6 +93,18 @@ def lib():
         L.grmhd_bind_state.argtypes = [ctypes.c_void_p, ctypes.POINTER(StatePtrs)]
         L.grmhd_debug_ptrs.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_void_p)] * 3
         L.grmhd_profile.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        vp = ctypes.c_void_p
+        L.grmhd_step.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos), ctypes.c_double,
+                                 ctypes.c_int, ctypes.c_double]
+        L.grmhd_step_graph.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos),
+                                       ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.grmhd_mlp_bind.argtypes = [vp, vp, vp, vp]
+        L.grmhd_mlp_scratch_bytes.argtypes = [ctypes.c_int]
+        L.grmhd_mlp_scratch_bytes.restype = ctypes.c_size_t
+        L.grmhd_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
+        L.grmhd_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
+                                           ctypes.c_int, vp, vp, ctypes.c_size_t, vp]
+        L.grmhd_mlp_infer.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
         L.grmhd_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_longlong)]
         _lib = L
@@ -301,7 +317,14 @@ class Pack:
         return {"dt": out.dt, "divb_rel": out.divb_rel, "divb_max": out.divb_max,
                 "totals": np.array(out.totals[:]), "c2p_fail": out.c2p_fail,
                 "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
-                "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean}
+                "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean,
+                "guess_fallback": out.guess_fallback}
+
+    def mlp_bind(self, params, mean, std):
+        """params: float32 device tensor [MLP_NPARAM]; mean/std: float32 device [5]."""
+        self._mlp_keep = (params, mean, std)
+        _check(lib().grmhd_mlp_bind(self.h, params.data_ptr(), mean.data_ptr(), std.data_ptr()),
+               self.h)
 
     def profile(self, enable=True):
         _check(lib().grmhd_profile(self.h, int(enable)), self.h)
@@ -318,6 +341,18 @@ class Pack:
         self.upload(self.prob.P if P is None else P, self.prob.Bf if Bf is None else Bf)
         self.fill_ghosts()
         self.prim_to_cons()
+
+    def step_c(self, dt=None, guess=GUESS_PREV, cfl=None):
+        """One SSPRK2 step through grmhd_step (+ reductions when cfl given)."""
+        _check(lib().grmhd_step(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                ctypes.c_double(-1.0 if dt is None else dt), guess,
+                                ctypes.c_double(0.0 if cfl is None else cfl)), self.h)
+
+    def step_graph(self, nsteps, guess=GUESS_PREV, cfl=None):
+        """nsteps replays of the HIP-graph-captured step (dt on the device)."""
+        _check(lib().grmhd_step_graph(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                      guess, ctypes.c_double(self.cfl if cfl is None else cfl),
+                                      nsteps), self.h)
 
     def step(self, dt=None, guess=GUESS_PREV):
         """One SSPRK2 step (Shu-Osher): ghosts, stage {1,0,1}, con2prim, ghosts,

@@ -1,0 +1,203 @@
+"""Learned inversion guess: kernels against the FP64 reference, and what the
+trained network changes in the Newton solve."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+from paper_2410_09146_amd import inputs as I
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2410_09146_amd import grmhd as G
+    from paper_2410_09146_amd import mlp as M
+    G.lib()
+    return torch, G, M
+
+
+def bf16(x):
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32)
+
+
+def test_gradient_matches_fp64_reference(env):
+    torch, G, M = env
+    X, Y, _, _ = ref.dataset(512, seed=21)
+    mean, std = X.mean(0), X.std(0)
+    Xs = ((X - mean) / std).astype(np.float32)
+    flat = M.init_params(seed=4).astype(np.float32)
+    loss_g, g = M.grad(torch.tensor(flat, device="cuda"), torch.tensor(Xs, device="cuda"),
+                       torch.tensor(Y.astype(np.float32), device="cuda"))
+    P = [(W.astype(np.float64), b.astype(np.float64)) for W, b in M.unflatten(flat.astype(np.float64))]
+    loss_c, gc = ref.loss_and_grad(P, Xs.astype(np.float64), Y.astype(np.float32).astype(np.float64))
+    gcf = np.concatenate([np.concatenate([gw.ravel(), gb]) for gw, gb in gc])
+    gg = g.cpu().numpy().astype(np.float64)
+    rel = np.linalg.norm(gg - gcf) / np.linalg.norm(gcf)
+    per_layer = []
+    o = 0
+    for l in range(4):
+        n = M.LAYERS[l] * M.LAYERS[l + 1] + M.LAYERS[l + 1]
+        per_layer.append(np.linalg.norm(gg[o:o + n] - gcf[o:o + n]) / np.linalg.norm(gcf[o:o + n]))
+        o += n
+    say("grad check: loss", loss_g, loss_c, "rel", rel, "per layer", per_layer)
+    assert loss_g == pytest.approx(loss_c, rel=1e-5)
+    assert rel <= 1e-5 and max(per_layer) <= 1e-5
+
+
+def test_mfma_inference_matches_bf16_reference(env):
+    torch, G, M = env
+    X, _, _, _ = ref.dataset(1000, seed=23)      # 1000: ragged last wavefront
+    mean, std = X.mean(0).astype(np.float32), X.std(0).astype(np.float32)
+    flat = M.init_params(seed=6).astype(np.float32)
+    flat[M.LAYERS[1] * 5:M.LAYERS[1] * 5 + 64] = 0.1     # nonzero biases
+    Yg = M.infer(torch.tensor(flat, device="cuda"), torch.tensor(mean, device="cuda"),
+                 torch.tensor(std, device="cuda"),
+                 torch.tensor(X.astype(np.float32), device="cuda")).cpu().numpy()
+    P = M.unflatten(flat)
+    istd = np.float32(1.0) / std
+    h = bf16((X.astype(np.float32) - mean) * istd)
+    for l, (W, b) in enumerate(P):
+        z = h.astype(np.float64) @ bf16(W).astype(np.float64).T + b.astype(np.float64)
+        z = z.astype(np.float32)
+        h = bf16(z / (np.float32(1) + np.exp(-z))) if l < 3 else z
+    scale = np.abs(h).max()
+    err = np.abs(Yg - h)
+    say("mfma inference: max err", err.max() / scale, "median", np.median(err) / scale)
+    assert err.max() <= 2e-2 * scale
+    assert np.median(err) <= 2e-3 * scale
+
+
+
+
+@pytest.fixture(scope="module")
+def trained(env):
+    """Train on 2e6 oracle pairs (90 / 5 / 5 split) on the GPU."""
+    torch, G, M = env
+    X, Y, U, prims = ref.dataset(2_000_000, seed=3)
+    n = X.shape[0]
+    ntr, nva = int(0.9 * n), int(0.05 * n)
+    mean, std = X[:ntr].mean(0), X[:ntr].std(0)
+    Xs = ((X - mean) / std).astype(np.float32)
+    tr = M.Trainer(M.init_params(seed=0), batch=4096)
+    Xt = torch.tensor(Xs[:ntr], device="cuda")
+    Yt = torch.tensor(Y[:ntr].astype(np.float32), device="cuda")
+    hist = tr.fit(Xt, Yt, epochs=20, lr0=1e-3, seed=0,
+                  log=lambda ep, l: say("epoch", ep, "train loss", l))
+    # validation loss through the FP32 gradient kernel
+    Xv = torch.tensor(Xs[ntr:ntr + nva], device="cuda")
+    Yv = torch.tensor(Y[ntr:ntr + nva].astype(np.float32), device="cuda")
+    vloss, _ = M.grad(tr.p, Xv[:65536].contiguous(), Yv[:65536].contiguous())
+    say("validation loss", vloss, "first/last train loss", hist[0], hist[-1])
+    return {"p": tr.p, "mean": torch.tensor(mean.astype(np.float32), device="cuda"),
+            "std": torch.tensor(std.astype(np.float32), device="cuda"), "X": X, "Y": Y, "U": U,
+            "prims": prims, "ntr": ntr, "nva": nva, "vloss": vloss, "hist": hist}
+
+
+def test_training_converges(trained):
+    assert trained["hist"][-1] < 0.05 * trained["hist"][0]
+    assert trained["vloss"] < 0.05
+
+
+def _box_pack(G, torch, U8, nbox=(64, 64, 32)):
+    """A Minkowski pack whose interior cells hold the given undensitized
+    conserved states (U8: [N, 8] with D, S_j, tau, B^k)."""
+    prob = I.uniform_box(nbox, gamma=13.0 / 9.0)
+    prob.rho_flr0, prob.u_flr0 = 1e-30, 1e-30
+    pack = G.Pack(prob, c2p_max_iter=60)
+    g = prob.ng
+    s = [nbox[d] + 2 * g for d in range(3)]
+    N = nbox[0] * nbox[1] * nbox[2]
+    Uc = np.zeros((5, s[2], s[1], s[0]))
+    Bc = np.zeros((3, nbox[2], nbox[1], nbox[0]))
+    for v in range(5):
+        Uc[v, g:-g, g:-g, g:-g] = U8[:N, v].reshape(nbox[2], nbox[1], nbox[0])
+    for d in range(3):
+        Bc[d] = U8[:N, 5 + d].reshape(nbox[2], nbox[1], nbox[0])
+    Bf = np.zeros((3, s[2], s[1], s[0]))
+    # B^1: faces along x1
+    f = np.zeros((nbox[2], nbox[1]))
+    Bf[0, g:-g, g:-g, g] = f
+    for i in range(nbox[0]):
+        f = 2.0 * Bc[0][:, :, i] - f
+        Bf[0, g:-g, g:-g, g + i + 1] = f
+    f = np.zeros((nbox[2], nbox[0]))
+    for j in range(nbox[1]):
+        f = 2.0 * Bc[1][:, j, :] - f
+        Bf[1, g:-g, g + j + 1, g:-g] = f
+    f = np.zeros((nbox[1], nbox[0]))
+    for k in range(nbox[2]):
+        f = 2.0 * Bc[2][k] - f
+        Bf[2, g + k + 1, g:-g, g:-g] = f
+    P = np.zeros((5,) + tuple(s[::-1]))
+    P[0] = 1.0
+    P[4] = 1.0
+    pack.upload(P, Bf)
+    cnt = s[0] * s[1] * s[2]
+    pack.U[:, :cnt].copy_(torch.from_numpy(Uc.reshape(5, -1)))
+    return pack, prob, P, Uc
+
+
+def test_guess_gain_on_sampled_states(env, trained):
+    """Held-out states: Newton iterations from the learned guess versus the
+    cold guess mu = 1/sqrt(1 + r^2) (the method without prior information).
+    The root is the same: primitives agree to the inversion's conditioning."""
+    torch, G, M = env
+    a = trained["ntr"] + trained["nva"]
+    U8 = trained["U"][a:a + 64 * 64 * 32]
+    res = {}
+    for guess in (G.GUESS_COLD, G.GUESS_MLP):
+        pack, prob, P0, Uc = _box_pack(G, torch, U8)
+        if guess == G.GUESS_MLP:
+            pack.mlp_bind(trained["p"], trained["mean"], trained["std"])
+        pack.con2prim(guess)
+        red = pack.reductions()
+        flags, iters = pack.debug_arrays()
+        it = prob.interior()
+        res[guess] = (pack.download("P"), iters[it].astype(float), red)
+    Pc, ic, rc = res[G.GUESS_COLD]
+    Pm, im, rm = res[G.GUESS_MLP]
+    it = (slice(None),) + I.uniform_box((64, 64, 32)).interior()
+    dP = np.abs(Pm[it] - Pc[it]).max(axis=(1, 2, 3)) / np.abs(Pc[it]).max(axis=(1, 2, 3))
+    say("sampled states: mean iters cold", ic.mean(), "mlp", im.mean(),
+        "| wave-max mean cold", rc["c2p_iter_wavemax_mean"], "mlp", rm["c2p_iter_wavemax_mean"],
+        "| fallback", rm["guess_fallback"], "fail", rc["c2p_fail"], rm["c2p_fail"], "| dP", dP)
+    assert rm["c2p_iter_mean"] < rc["c2p_iter_mean"]
+    assert rm["c2p_iter_wavemax_mean"] <= rc["c2p_iter_wavemax_mean"]
+    assert np.all(dP < 1e-9)
+
+
+def test_torus_deployment(env, trained):
+    """64^3 torus, 20 steps each with the previous-primitive guess and the
+    learned guess: iterations, fallback rate, final-state difference."""
+    torch, G, M = env
+    prob = I.torus(n=(64, 64, 64))
+    out = {}
+    for guess in (G.GUESS_PREV, G.GUESS_MLP, G.GUESS_COLD):
+        pack = G.Pack(prob)
+        if guess == G.GUESS_MLP:
+            pack.mlp_bind(trained["p"], trained["mean"], trained["std"])
+        pack.init()
+        pack.reductions(sync=False)
+        its, wm, fb = [], [], []
+        for _ in range(20):
+            pack.step(None, guess=guess)
+            r = pack.reductions()
+            its.append(r["c2p_iter_mean"]); wm.append(r["c2p_iter_wavemax_mean"])
+            fb.append(r["guess_fallback"])
+        out[guess] = (pack.download("P"), np.mean(its), np.mean(wm), np.sum(fb))
+        del pack
+    Pp = out[G.GUESS_PREV][0]
+    it = (slice(None),) + prob.interior()
+    for gname, gk in (("prev", G.GUESS_PREV), ("mlp", G.GUESS_MLP), ("cold", G.GUESS_COLD)):
+        dP = np.abs(out[gk][0][it] - Pp[it]).max(axis=(1, 2, 3)) / np.abs(Pp[it]).max(axis=(1, 2, 3))
+        say("torus", gname, "mean iters", out[gk][1], "wave-max mean", out[gk][2],
+            "fallbacks", out[gk][3], "max rel dP vs prev", dP.max())
+        assert dP.max() < 1e-8
+    assert out[G.GUESS_MLP][1] < out[G.GUESS_COLD][1]
