@@ -29,6 +29,9 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="cells per direction of the torus")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--persist", type=int, default=0,
+                    help="persistent flux grid size in workgroups (0: one per tile)")
     return ap.parse_args()
 
 
@@ -57,9 +60,11 @@ def main():
     pack = G.Pack(prob, device="cuda:0")
     pack.init()
     pack.reductions(sync=False)        # device-resident dt for the first step
+    tiles, tune_ms = pack.autotune(reps=3) if not args.no_autotune else ([0, 0, 0], None)
+    if args.persist:
+        pack.set_persistent(args.persist)
     for _ in range(args.warmup):
-        pack.step(None)
-        pack.reductions(sync=False)
+        pack.step_c(None, cfl=prob.cfl)
     torch.cuda.synchronize()
 
     stream = pack.stream
@@ -69,14 +74,22 @@ def main():
     torch.cuda.synchronize()
     e0.record(stream)
     for _ in range(args.steps):
-        pack.step(None)
-        pack.reductions(sync=False)
+        pack.step_c(None, cfl=prob.cfl)
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     prof = pack.profile_read()
     pack.profile(False)
     red = pack.reductions()
+
+    # the same steps replayed from a captured HIP graph
+    pack.step_graph(0)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    pack.step_graph(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
 
     ncell = n ** 3
     value = ncell * args.steps / (ms * 1e-3)
@@ -129,6 +142,10 @@ def main():
                                "WENO5-Z-AOAH + LLF, CT, SSPRK2, FP64, one meshblock",
                    "cells": ncell, "parallelism": "single GPU"},
         "roofline": roof, "hbm_view": hbm, "kernels": kernels,
+        "graph_replay": {"ms_per_step": round(ms_graph / args.steps, 4),
+                         "value": round(ncell * args.steps / (ms_graph * 1e-3), 1)},
+        "tiling": {"shape_per_direction": tiles,
+                   "autotune_ms": None if tune_ms is None else tune_ms.round(4).tolist()},
         "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"],
                   "floor_hits": red["floor_hits"], "c2p_iter_mean": red["c2p_iter_mean"],
                   "c2p_iter_wavemax_mean": red["c2p_iter_wavemax_mean"]},

@@ -191,6 +191,25 @@ int grmhd_step(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eo
 int grmhd_step_graph(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
                      int guess, double cfl, int nsteps);
 
+/*
+ * Face-tile shapes of the flux kernels: shape s has TD faces along the flux
+ * direction and 256/TD columns (TD = 16, 32, 8, 64, 4 for s = 0..4).  Shapes
+ * 1..4 exist for the WENO5-Z-AOAH point-value reconstruction; every other
+ * reconstruction runs shape 0.  grmhd_autotune times each shape's tile kernel
+ * per direction (reps launches after one untimed launch, HIP events on the
+ * pack's stream; the kernels only read the state and write the flux scratch),
+ * keeps the fastest in chosen[3] and ms_table[3 * 5] (ms per launch, -1 when
+ * not available) and applies it.  Synchronises the stream.
+ */
+#define GRMHD_NSHAPE 5
+int grmhd_set_tiling(grmhd_pack *pack, const int shape[3]);
+/* workgroups > 0: launch the flux-tile kernels as a persistent grid of that
+ * many workgroups striding over the tile work-list; 0: one workgroup per tile. */
+int grmhd_set_persistent(grmhd_pack *pack, int workgroups);
+int grmhd_get_tiling(const grmhd_pack *pack, int shape[3]);
+int grmhd_autotune(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos, int reps,
+                   int chosen[3], double *ms_table);
+
 /* Device pointers to the per-cell int8 flags and uint8 Newton iteration
  * counts of the last con2prim (inside the workspace; same cell layout as P). */
 int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);

@@ -34,7 +34,7 @@ struct Plan {
   std::vector<long long> off;
   std::vector<BlockInfo> blocks;
   std::vector<double> rc, rf, sc, cc, sf, cf;
-  std::vector<int4> tiles[3];
+  std::vector<int4> tiles[3][NSHAPE];
   std::vector<int2> planes[3];
   std::vector<int2> ch_int, ch_ext, ch_bcc;
   std::vector<GhostP> gP;
@@ -42,8 +42,9 @@ struct Plan {
   int active[3] = {1, 1, 1};
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
-  size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_tiles[3], o_planes[3], o_chi, o_che,
+  size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes[3], o_chi, o_che,
       o_chb, o_gP, o_gB, o_part, o_res, o_mlp, o_mlpw, o_mlpf, total;
+  size_t o_tl[3][NSHAPE];
 };
 
 int fail(const std::string &m, int code)
@@ -203,13 +204,38 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     const BlockInfo &bi = p.blocks[b];
     for (int D = 0; D < 3; ++D) {
       const int AX = D == 0 ? 1 : 0, BX = D == 2 ? 1 : 2;
-      for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
-        for (int a0 = ng - 1; a0 <= ng + bi.n[AX]; a0 += TA)
-          for (int f0 = ng; f0 < ng + bi.n[D]; f0 += TD) {
-            int o[3];
-            o[D] = f0; o[AX] = a0; o[BX] = kb;
-            p.tiles[D].push_back(make_int4(b, o[0], o[1], o[2]));
-          }
+      for (int sh = 0; sh < NSHAPE; ++sh) {
+        const int td = shape_td(sh), ta = shape_ta(sh);
+        for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
+          for (int a0 = ng - 1; a0 <= ng + bi.n[AX]; a0 += ta)
+            for (int f0 = ng; f0 < ng + bi.n[D]; f0 += td) {
+              int o[3];
+              o[D] = f0; o[AX] = a0; o[BX] = kb;
+              p.tiles[D][sh].push_back(make_int4(b, o[0], o[1], o[2]));
+            }
+      }
+    }
+  }
+  // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs, so
+  // entry w of the list is taken from position (w % 8) * ceil(n/8) + w / 8 of
+  // the natural (spatially ordered) list; each XCD then sweeps one contiguous
+  // eighth of the tiles and reuses the stencil halos in its own L2.
+  for (int D = 0; D < 3; ++D)
+    for (int sh = 0; sh < NSHAPE; ++sh) {
+      std::vector<int4> &L = p.tiles[D][sh];
+      const size_t n = L.size(), q = (n + 7) / 8;
+      std::vector<int4> out;
+      out.reserve(n);
+      for (size_t w = 0; w < 8 * q; ++w) {
+        const size_t src = (w % 8) * q + w / 8;
+        if (src < n) out.push_back(L[src]);
+      }
+      L.swap(out);
+    }
+  for (int b = 0; b < p.nb; ++b) {
+    const BlockInfo &bi = p.blocks[b];
+    for (int D = 0; D < 3; ++D) {
+      const int AX = D == 0 ? 1 : 0, BX = D == 2 ? 1 : 2;
       const int np = (bi.n[AX] + 2) * (bi.n[BX] + 2);
       for (int s = 0; s < np; s += 256) p.planes[D].push_back(make_int2(b, s));
     }
@@ -308,7 +334,8 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_iters = take((size_t)p.nct);
   p.o_blocks = take(sizeof(BlockInfo) * p.nb);
   p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
-  for (int D = 0; D < 3; ++D) p.o_tiles[D] = take(sizeof(int4) * p.tiles[D].size());
+  for (int D = 0; D < 3; ++D)
+    for (int sh = 0; sh < NSHAPE; ++sh) p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
   for (int D = 0; D < 3; ++D) p.o_planes[D] = take(sizeof(int2) * p.planes[D].size());
   p.o_chi = take(sizeof(int2) * p.ch_int.size());
   p.o_che = take(sizeof(int2) * p.ch_ext.size());
@@ -336,6 +363,10 @@ struct grmhd_pack {
   bool mlp_bound = false;
   // optional per-kernel-family timing with events on the pack's stream
   bool prof = false;
+  int shape[3] = {0, 0, 0};     // face-tile shape per direction (autotuned)
+  int tune_sh = -1;             // >= 0 while the autotuner times one shape
+  int tune_dir = -1;            // direction being timed (-1: all)
+  int persist = 0;              // > 0: persistent flux grid of this many workgroups
   // captured SSPRK2 step (dt read on the device)
   hipGraphExec_t gexec = nullptr;
   int g_guess = -1;
@@ -450,15 +481,41 @@ const T *dptr(const grmhd_pack *p, size_t off) { return (const T *)(p->ws + off)
 
 // ---- templated launch helpers (host dispatch over compile-time options)
 
+template <int MK, int D, int RC, int FV, int RS, typename T, int SH>
+void launch_tiles(grmhd_pack *p, const KArgs &a)
+{
+  const Plan &pl = p->plan;
+  if (pl.tiles[D][SH].empty()) return;
+  Prof t(p, GRMHD_PROF_FLUX_X1 + D);
+  const int nt = (int)pl.tiles[D][SH].size();
+  const int grid = p->persist > 0 ? std::min(nt, p->persist) : nt;
+  hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH>), dim3(grid), dim3(256), 0, p->stream, a,
+                     dptr<int4>(p, pl.o_tl[D][SH]), nt);
+}
+
+// Every shape is instantiated for the WENO5-Z-AOAH point-value path (the
+// production reconstruction); the other reconstructions use 16 x 16 tiles.
+template <int MK, int D, int RC, int FV, int RS, typename T>
+void launch_tiles_sh(grmhd_pack *p, const KArgs &a, int sh)
+{
+  if constexpr (RC == RC_WENO && FV == 0) {
+    switch (sh) {
+      case 1: launch_tiles<MK, D, RC, FV, RS, T, 1>(p, a); return;
+      case 2: launch_tiles<MK, D, RC, FV, RS, T, 2>(p, a); return;
+      case 3: launch_tiles<MK, D, RC, FV, RS, T, 3>(p, a); return;
+      case 4: launch_tiles<MK, D, RC, FV, RS, T, 4>(p, a); return;
+      default: break;
+    }
+  }
+  launch_tiles<MK, D, RC, FV, RS, T, 0>(p, a);
+}
+
 template <int MK, int D, int RC, int FV, int RS, typename T>
 void launch_flux(grmhd_pack *p, const KArgs &a)
 {
   const Plan &pl = p->plan;
-  if (!pl.tiles[D].empty()) {
-    Prof t(p, GRMHD_PROF_FLUX_X1 + D);
-    hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T>), dim3(pl.tiles[D].size()), dim3(256), 0,
-                       p->stream, a, dptr<int4>(p, pl.o_tiles[D]));
-  }
+  launch_tiles_sh<MK, D, RC, FV, RS, T>(p, a, p->tune_sh >= 0 ? p->tune_sh : p->shape[D]);
+  if (p->tune_sh >= 0) return;     // autotuning times the tile kernels alone
   if (!pl.planes[D].empty()) {
     Prof t(p, GRMHD_PROF_FLUX_PLANE);
     hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS, T>), dim3(pl.planes[D].size()), dim3(256),
@@ -469,9 +526,9 @@ void launch_flux(grmhd_pack *p, const KArgs &a)
 template <int MK, int RC, int FV, int RS, typename T>
 void launch_flux3(grmhd_pack *p, const KArgs &a)
 {
-  launch_flux<MK, 0, RC, FV, RS, T>(p, a);
-  launch_flux<MK, 1, RC, FV, RS, T>(p, a);
-  launch_flux<MK, 2, RC, FV, RS, T>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T>(p, a);
 }
 
 template <int MK, int RC, int FV, typename T>
@@ -560,7 +617,8 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   if (!e) e = up(pl.o_blocks, pl.blocks.data(), sizeof(BlockInfo) * pl.blocks.size());
   if (!e) e = up(pl.o_tab, tab.data(), sizeof(double) * tab.size());
   for (int D = 0; D < 3; ++D) {
-    if (!e) e = up(pl.o_tiles[D], pl.tiles[D].data(), sizeof(int4) * pl.tiles[D].size());
+    for (int sh = 0; sh < NSHAPE; ++sh)
+      if (!e) e = up(pl.o_tl[D][sh], pl.tiles[D][sh].data(), sizeof(int4) * pl.tiles[D][sh].size());
     if (!e) e = up(pl.o_planes[D], pl.planes[D].data(), sizeof(int2) * pl.planes[D].size());
   }
   if (!e) e = up(pl.o_chi, pl.ch_int.data(), sizeof(int2) * pl.ch_int.size());
@@ -956,6 +1014,85 @@ int grmhd_step_graph(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
   }
   for (int s = 0; s < nsteps; ++s) HIPCHK(p, hipGraphLaunch(p->gexec, p->stream));
   return GRMHD_OK;
+}
+
+int grmhd_set_tiling(grmhd_pack *p, const int shape[3])
+{
+  if (!p || !shape) return GRMHD_E_INVALID;
+  for (int d = 0; d < 3; ++d)
+    if (shape[d] < 0 || shape[d] >= NSHAPE) return perr(p, "bad tile shape", GRMHD_E_INVALID);
+  for (int d = 0; d < 3; ++d) p->shape[d] = shape[d];
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  return GRMHD_OK;
+}
+
+int grmhd_set_persistent(grmhd_pack *p, int workgroups)
+{
+  if (!p || workgroups < 0) return GRMHD_E_INVALID;
+  p->persist = workgroups;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  return GRMHD_OK;
+}
+
+int grmhd_get_tiling(const grmhd_pack *p, int shape[3])
+{
+  if (!p || !shape) return GRMHD_E_INVALID;
+  for (int d = 0; d < 3; ++d) shape[d] = p->shape[d];
+  return GRMHD_OK;
+}
+
+int grmhd_autotune(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int reps,
+                   int chosen[3], double *ms_table)
+{
+  if (!p || !chosen) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (int rc = check_eos(p, eos)) return rc;
+  if (reps < 1) reps = 1;
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  fill_eos(a, eos);
+  const int rcn = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
+  const int prec = p->desc.precision;
+  const bool all = rcn == RC_WENO && fv == 0;
+  hipEvent_t e0, e1;
+  HIPCHK(p, hipEventCreate(&e0));
+  HIPCHK(p, hipEventCreate(&e1));
+  const bool prof = p->prof;
+  p->prof = false;
+  int status = GRMHD_OK;
+  for (int d = 0; d < 3 && !status; ++d) {
+    double best = 1e300;
+    int bsh = 0;
+    for (int sh = 0; sh < NSHAPE; ++sh) {
+      double ms = -1.0;
+      if (sh == 0 || all) {
+        p->tune_dir = d;
+        p->tune_sh = sh;
+        // one untimed launch, then reps timed launches
+        for (int r = 0; r <= reps; ++r) {
+          if (r == 1) (void)hipEventRecord(e0, p->stream);
+          if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rcn, fv, rs, prec);
+          else launch_flux_all<MK_MINK>(p, a, rcn, fv, rs, prec);
+        }
+        (void)hipEventRecord(e1, p->stream);
+        hipError_t err = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (!err) err = hipEventElapsedTime(&t, e0, e1);
+        if (err) { status = perr(p, std::string("autotune: ") + hipGetErrorString(err), GRMHD_E_HIP); break; }
+        ms = t / reps;
+        if (ms < best) { best = ms; bsh = sh; }
+      }
+      if (ms_table) ms_table[d * NSHAPE + sh] = ms;
+    }
+    chosen[d] = bsh;
+  }
+  p->tune_dir = -1;
+  p->tune_sh = -1;
+  p->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status) return status;
+  return grmhd_set_tiling(p, chosen);
 }
 
 int grmhd_profile(grmhd_pack *p, int enable)

@@ -90,7 +90,18 @@ __global__ __launch_bounds__(256) void k_bcc(KArgs a, const int2 *__restrict__ c
 
 // ------------------------------------------------------------------- fluxes
 
-constexpr int TD = 16, TA = 16, NS = TD + 5, NR = TD + 1, NV = 7;
+constexpr int NV = 7;
+// Face-tile shapes: TD faces along the flux direction x TA columns (256 faces);
+// the columns run along x1 when the direction is x2 or x3.
+template <int SH> struct Shape;
+template <> struct Shape<0> { static constexpr int TD = 16, TA = 16; };
+template <> struct Shape<1> { static constexpr int TD = 32, TA = 8; };
+template <> struct Shape<2> { static constexpr int TD = 8, TA = 32; };
+template <> struct Shape<3> { static constexpr int TD = 64, TA = 4; };
+template <> struct Shape<4> { static constexpr int TD = 4, TA = 64; };
+constexpr int NSHAPE = 5;
+__host__ __device__ constexpr int shape_td(int sh) { return sh == 0 ? 16 : sh == 1 ? 32 : sh == 2 ? 8 : sh == 3 ? 64 : 4; }
+__host__ __device__ constexpr int shape_ta(int sh) { return 256 / shape_td(sh); }
 
 // transverse field components reconstructed along D
 template <int D> __device__ constexpr int tcomp(int w) { return D == 0 ? 1 + w : (D == 1 ? 2 * w : w); }
@@ -160,63 +171,71 @@ __device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
-template <int MK, int D, int RECON, int FV, int RS, typename T>
-__global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ tiles)
+template <int MK, int D, int RECON, int FV, int RS, typename T, int SH>
+__global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
 {
+  constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NS = TD + 5, NR = TD + 1;
   __shared__ T stg[NV * TA * NS];
   __shared__ T sfl[NV * TA * NR];
   __shared__ T sfr[NV * TA * NR];
   constexpr int AX = (D == 0) ? 1 : 0;
-  const int4 t = tiles[blockIdx.x];
-  const BlockInfo b = a.blocks[t.x];
-  const int org[3] = {t.y, t.z, t.w};
-  const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
   const int tid = threadIdx.x;
 
-  // stage P and the transverse cell-centred field: cells org[D]-3 .. org[D]+TD+1
-  for (int it = tid; it < NV * TA * NS; it += 256) {
-    int s, aa, v;
-    if constexpr (D == 0) { s = it % NS; aa = (it / NS) % TA; v = it / (NS * TA); }
-    else                  { aa = it % TA; s = (it / TA) % NS; v = it / (TA * NS); }
+  // persistent: the grid strides over the tile work-list (every thread of a
+  // workgroup runs the same number of iterations, so the barriers match)
+  for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int4 t = tiles[ti];
+    const BlockInfo b = a.blocks[t.x];
+    const int org[3] = {t.y, t.z, t.w};
+    const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
+
+    // stage P and the transverse cell-centred field: cells org[D]-3 .. org[D]+TD+1
+    for (int it = tid; it < NV * TA * NS; it += 256) {
+      int s, aa, v;
+      if constexpr (D == 0) { s = it % NS; aa = (it / NS) % TA; v = it / (NS * TA); }
+      else                  { aa = it % TA; s = (it / TA) % NS; v = it / (TA * NS); }
+      int idx[3] = {org[0], org[1], org[2]};
+      idx[D] = min(max(org[D] - 3 + s, 0), b.s[D] - 1);
+      idx[AX] = min(org[AX] + aa, b.s[AX] - 1);
+      const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+      double val;
+      if (v < 5) val = a.P[v * a.nct + c];
+      else val = a.Bcc[tcomp<D>(v - 5) * a.nct + c];
+      stg[(v * TA + aa) * NS + s] = T(val);
+    }
+    __syncthreads();
+
+    // reconstruct every (variable, column, cell) of cells org[D]-1 .. org[D]+TD-1
+    for (int it = tid; it < NV * TA * NR; it += 256) {
+      const int cc = it % NR, aa = (it / NR) % TA, v = it / (NR * TA);
+      const T *f = &stg[(v * TA + aa) * NS + cc];
+      T l, r;
+      recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
+      positivity(v, f[2], l, r);
+      sfl[it] = l;
+      sfr[it] = r;
+    }
+    __syncthreads();
+
+    int fd, aa;
+    if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
+    else                  { aa = tid % TA; fd = tid / TA; }
     int idx[3] = {org[0], org[1], org[2]};
-    idx[D] = min(max(org[D] - 3 + s, 0), b.s[D] - 1);
-    idx[AX] = min(org[AX] + aa, b.s[AX] - 1);
-    const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-    double val;
-    if (v < 5) val = a.P[v * a.nct + c];
-    else val = a.Bcc[tcomp<D>(v - 5) * a.nct + c];
-    stg[(v * TA + aa) * NS + s] = T(val);
-  }
-  __syncthreads();
-
-  // reconstruct every (variable, column, cell) of cells org[D]-1 .. org[D]+TD-1
-  for (int it = tid; it < NV * TA * NR; it += 256) {
-    const int cc = it % NR, aa = (it / NR) % TA, v = it / (NR * TA);
-    const T *f = &stg[(v * TA + aa) * NS + cc];
-    T l, r;
-    recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
-    positivity(v, f[2], l, r);
-    sfl[it] = l;
-    sfr[it] = r;
-  }
-  __syncthreads();
-
-  int fd, aa;
-  if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
-  else                  { aa = tid % TA; fd = tid / TA; }
-  int idx[3] = {org[0], org[1], org[2]};
-  idx[D] = org[D] + fd;
-  idx[AX] = org[AX] + aa;
-  if (idx[D] >= a.ng + b.n[D]) return;
-  if (idx[AX] > a.ng + b.n[AX] || idx[AX] >= b.s[AX]) return;
-  const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-  T qL[7], qR[7];
+    idx[D] = org[D] + fd;
+    idx[AX] = org[AX] + aa;
+    const bool live = idx[D] < a.ng + b.n[D] && idx[AX] <= a.ng + b.n[AX] && idx[AX] < b.s[AX];
+    if (live) {
+      const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+      T qL[7], qR[7];
 #pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    qL[v] = sfr[(v * TA + aa) * NR + fd];        // right face of cell idx[D]-1
-    qR[v] = sfl[(v * TA + aa) * NR + fd + 1];    // left face of cell idx[D]
+      for (int v = 0; v < 7; ++v) {
+        qL[v] = sfr[(v * TA + aa) * NR + fd];        // right face of cell idx[D]-1
+        qR[v] = sfl[(v * TA + aa) * NR + fd + 1];    // left face of cell idx[D]
+      }
+      face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
+    }
+    __syncthreads();   // LDS is restaged by the next tile
   }
-  face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
 }
 
 // Faces on the upper boundary plane along D (index ng + n_D), one per thread.

@@ -57,7 +57,9 @@ EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_stage", "grmhd_con2prim", "grmhd_prim_to_cons", "grmhd_reductions",
            "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_mlp_bind",
            "grmhd_mlp_scratch_bytes", "grmhd_mlp_grad", "grmhd_mlp_train_step",
-           "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_last_error"]
+           "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_set_tiling",
+           "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_last_error"]
+NSHAPE = 5
 
 PROF_FAMILIES = ["flux_x1", "flux_x2", "flux_x3", "flux_plane", "update", "con2prim",
                  "ghost", "bcc", "reduce", "mlp"]
@@ -96,6 +98,11 @@ def lib():
         vp = ctypes.c_void_p
         L.grmhd_step.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos), ctypes.c_double,
                                  ctypes.c_int, ctypes.c_double]
+        L.grmhd_autotune.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos), ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        L.grmhd_set_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.grmhd_set_persistent.argtypes = [vp, ctypes.c_int]
+        L.grmhd_get_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.grmhd_step_graph.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos),
                                        ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.grmhd_mlp_bind.argtypes = [vp, vp, vp, vp]
@@ -141,7 +148,7 @@ class Pack:
     """
 
     def __init__(self, prob, nblk=(1, 1, 1), device="cuda:0", precision=PREC_FP64,
-                 c2p_tol=1e-14, c2p_max_iter=40):
+                 c2p_tol=1e-14, c2p_max_iter=40, layout=None):
         import torch
         if not torch.cuda.is_available():
             raise GrmhdError("no GPU available: the HIP path has no CPU fallback")
@@ -149,12 +156,14 @@ class Pack:
         self.prob = prob
         self.device = torch.device(device)
         self.ng = prob.ng
-        for d in range(3):
-            if prob.n[d] % nblk[d]:
-                raise GrmhdError("block split must divide the grid")
-        self.nblk = tuple(nblk)
-        nx, lloc = block_split(prob.n, nblk)
-        self.nb = nblk[0] * nblk[1] * nblk[2]
+        if layout is not None:
+            nx, lloc = list(layout[0]), list(layout[1])
+        else:
+            for d in range(3):
+                if prob.n[d] % nblk[d]:
+                    raise GrmhdError("block split must divide the grid")
+            nx, lloc = block_split(prob.n, nblk)
+        self.nb = len(nx) // 3
         self._nx = (ctypes.c_int * len(nx))(*nx)
         self._lloc = (ctypes.c_int * len(lloc))(*lloc)
         self._level = (ctypes.c_int * self.nb)(*([0] * self.nb))
@@ -341,6 +350,20 @@ class Pack:
         self.upload(self.prob.P if P is None else P, self.prob.Bf if Bf is None else Bf)
         self.fill_ghosts()
         self.prim_to_cons()
+
+    def autotune(self, reps=3):
+        """Time every face-tile shape per direction; keep and return the fastest."""
+        ch = (ctypes.c_int * 3)()
+        tab = (ctypes.c_double * (3 * NSHAPE))()
+        _check(lib().grmhd_autotune(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                                    reps, ch, tab), self.h)
+        return list(ch), np.array(tab[:]).reshape(3, NSHAPE)
+
+    def set_persistent(self, workgroups):
+        _check(lib().grmhd_set_persistent(self.h, int(workgroups)), self.h)
+
+    def set_tiling(self, shape):
+        _check(lib().grmhd_set_tiling(self.h, (ctypes.c_int * 3)(*shape)), self.h)
 
     def step_c(self, dt=None, guess=GUESS_PREV, cfl=None):
         """One SSPRK2 step through grmhd_step (+ reductions when cfl given)."""

@@ -559,3 +559,65 @@ def random_prims(count, seed=3, rho=(1e-8, 1.0), p_over_rho=(1e-6, 10.0), W=(1.0
     ut = v * Wl[:, None]
     u = pr * r / (gamma - 1.0)
     return {"rho": r, "ut": ut, "u": u, "B": B, "W": Wl, "gamma": gamma}
+
+
+# ---------------------------------------------------------------------------
+# Uneven meshblock layouts (batching)
+# ---------------------------------------------------------------------------
+
+def octree_layout(n, base=64, smallest=16, p_split=(0.45, 0.35), dense=None, p_dense=(0.9, 0.6),
+                  seed=7):
+    """Seeded octree cover of a root grid n[3] by cubic blocks of base, base/2,
+    ... down to `smallest` cells.  A block of size s splits into 8 children
+    with probability p_split[k] (k = level of s below base), or p_dense[k] when
+    dense(lo, size) says it holds dense gas.  Returns (nx, lloc) flat lists."""
+    rng = np.random.default_rng(seed)
+    nx, lloc = [], []
+
+    def visit(lo, s, k):
+        if s > smallest:
+            p = p_split[k] if k < len(p_split) else 0.0
+            if dense is not None and dense(lo, s):
+                p = p_dense[k] if k < len(p_dense) else 0.0
+            if rng.uniform() < p:
+                h = s // 2
+                for dz in (0, h):
+                    for dy in (0, h):
+                        for dx in (0, h):
+                            visit((lo[0] + dx, lo[1] + dy, lo[2] + dz), h, k + 1)
+                return
+        nx.extend([s, s, s])
+        lloc.extend(list(lo))
+
+    for z in range(0, n[2], base):
+        for y in range(0, n[1], base):
+            for x in range(0, n[0], base):
+                visit((x, y, z), base, 0)
+    return nx, lloc
+
+
+def torus_dense_fn(prob, thresh=1e-2):
+    """dense(lo, size): does the block's cube hold rho > thresh * rho_max?"""
+    g = prob.ng
+    rho = prob.P[0][g:-g, g:-g, g:-g]          # (z, y, x)
+    big = rho > thresh * rho.max()
+
+    def dense(lo, s):
+        return bool(big[lo[2]:lo[2] + s, lo[1]:lo[1] + s, lo[0]:lo[0] + s].any())
+    return dense
+
+
+def batch_layout(prob, target=640, base=64, seed=7):
+    """Octree layout of the torus with about `target` blocks: the split
+    probabilities are scaled (deterministically, from the seed) until the
+    block count is the closest to the target."""
+    dense = torus_dense_fn(prob)
+    best = None
+    for scale in np.linspace(0.2, 2.0, 181):
+        ps = tuple(min(1.0, scale * p) for p in (0.45, 0.35))
+        pd = tuple(min(1.0, scale * p) for p in (0.9, 0.6))
+        nx, lloc = octree_layout(prob.n, base, 16, ps, dense, pd, seed)
+        nb = len(nx) // 3
+        if best is None or abs(nb - target) < abs(best[0] - target):
+            best = (nb, nx, lloc)
+    return best[1], best[2]
