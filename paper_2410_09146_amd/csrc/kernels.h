@@ -669,8 +669,10 @@ __global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
   __syncthreads();
   mlp_wave(m, X, H1, H2, out, lane);
   if (live) {
-    const float mu = expf(-out[lane * 2 + 1]);
-    mu_out[c] = (mu > 0.0f && mu <= 1.0f) ? mu : -1.0f;
+    // mu = 1/(hW) <= 1 always: a guess above 1 (y1 slightly negative near
+    // h W = 1) is clamped; only a non-finite or non-positive one is rejected
+    const float mu = fminf(expf(-out[lane * 2 + 1]), 1.0f);
+    mu_out[c] = (mu > 0.0f) ? mu : -1.0f;
   }
 }
 

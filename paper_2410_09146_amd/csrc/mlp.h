@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ out,
     for (int k = 0; k < MLP_OUT; ++k) {
       const float d = out[s * MLP_OUT + k] - Y[s * MLP_OUT + k];
       delta[s * MLP_OUT + k] = 2.0f * d / (float)batch;
-      acc += d * d;
+      acc += d * d / (float)batch;
     }
   }
   sh[threadIdx.x] = acc;

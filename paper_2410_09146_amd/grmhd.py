@@ -201,7 +201,9 @@ class Pack:
         self.ws_bytes = wsb
         st = StatePtrs(self.P.data_ptr(), self.Bf.data_ptr(), self.U.data_ptr(),
                        self.U0.data_ptr(), self.Bf0.data_ptr())
-        self.stream = torch.cuda.current_stream(self.device)
+        # a stream of the pack's own (default priority): graph capture is not
+        # permitted on the legacy default stream
+        self.stream = torch.cuda.Stream(device=self.device)
         h = ctypes.c_void_p()
         _check(L.grmhd_pack_create(ctypes.byref(d), ctypes.byref(st), ctypes.c_void_p(ws_ptr),
                                    ctypes.c_size_t(wsb), ctypes.c_void_p(self.stream.cuda_stream),
@@ -232,6 +234,7 @@ class Pack:
     def upload(self, P, Bf):
         """Copy global padded numpy arrays (nvar, s3, s2, s1) into the blocks."""
         torch = self.torch
+        self._out()
         for b in range(self.nb):
             lo = self.lloc[b]
             n = self.nx[b]
@@ -243,6 +246,7 @@ class Pack:
         """Assemble a global padded numpy array from the blocks' interiors
         (and, for face arrays, the upper boundary faces)."""
         arr = {"P": self.P, "Bf": self.Bf, "U": self.U, "U0": self.U0, "Bf0": self.Bf0}[which]
+        self._out()
         self.torch.cuda.synchronize(self.device)
         host = arr.cpu().numpy()
         nv = host.shape[0]
@@ -268,6 +272,7 @@ class Pack:
         f, it, fl = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
         _check(lib().grmhd_debug_ptrs(self.h, ctypes.byref(f), ctypes.byref(it), ctypes.byref(fl)))
         base = self.ws.data_ptr()
+        self._out()
         off_f = f.value - base
         off_i = it.value - base
         self.torch.cuda.synchronize(self.device)
@@ -293,30 +298,44 @@ class Pack:
         fl = ctypes.c_void_p()
         _check(lib().grmhd_debug_ptrs(self.h, None, None, ctypes.byref(fl)))
         off = fl.value - self.ws.data_ptr()
+        self._out()
         self.torch.cuda.synchronize(self.device)
         raw = self.ws[off:off + 24 * self.nct * 8].cpu().numpy().view(np.float64)
         s = self.nx[0] + 2 * self.ng
         cnt = s[0] * s[1] * s[2]
         return raw.reshape(3, 8, self.nct)[:, :, :cnt].reshape(3, 8, s[2], s[1], s[0])
 
+    def _in(self):
+        """Order the pack's stream after work queued on torch's current stream."""
+        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
+
+    def _out(self):
+        """Order torch's current stream after the pack's work."""
+        self.torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     # ------------------------------------------------------------------ calls
     def fill_ghosts(self):
+        self._in()
         _check(lib().grmhd_fill_ghosts(self.h, ctypes.byref(self.metric)), self.h)
 
     def prim_to_cons(self):
+        self._in()
         _check(lib().grmhd_prim_to_cons(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos)),
                self.h)
 
     def stage(self, dt, rk):
+        self._in()
         rkc = (ctypes.c_double * 3)(*rk)
         _check(lib().grmhd_stage(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
                                  ctypes.c_double(dt), rkc), self.h)
 
     def con2prim(self, guess=GUESS_PREV):
+        self._in()
         _check(lib().grmhd_con2prim(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
                                     ctypes.c_int(guess)), self.h)
 
     def reductions(self, cfl=None, sync=True):
+        self._in()
         out = ReductionOut()
         _check(lib().grmhd_reductions(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
                                       ctypes.c_double(self.cfl if cfl is None else cfl),
@@ -332,6 +351,7 @@ class Pack:
     def mlp_bind(self, params, mean, std):
         """params: float32 device tensor [MLP_NPARAM]; mean/std: float32 device [5]."""
         self._mlp_keep = (params, mean, std)
+        self._in()
         _check(lib().grmhd_mlp_bind(self.h, params.data_ptr(), mean.data_ptr(), std.data_ptr()),
                self.h)
 
@@ -353,6 +373,7 @@ class Pack:
 
     def autotune(self, reps=3):
         """Time every face-tile shape per direction; keep and return the fastest."""
+        self._in()
         ch = (ctypes.c_int * 3)()
         tab = (ctypes.c_double * (3 * NSHAPE))()
         _check(lib().grmhd_autotune(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
@@ -367,12 +388,14 @@ class Pack:
 
     def step_c(self, dt=None, guess=GUESS_PREV, cfl=None):
         """One SSPRK2 step through grmhd_step (+ reductions when cfl given)."""
+        self._in()
         _check(lib().grmhd_step(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
                                 ctypes.c_double(-1.0 if dt is None else dt), guess,
                                 ctypes.c_double(0.0 if cfl is None else cfl)), self.h)
 
     def step_graph(self, nsteps, guess=GUESS_PREV, cfl=None):
         """nsteps replays of the HIP-graph-captured step (dt on the device)."""
+        self._in()
         _check(lib().grmhd_step_graph(self.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
                                       guess, ctypes.c_double(self.cfl if cfl is None else cfl),
                                       nsteps), self.h)

@@ -47,6 +47,16 @@ def _scratch(torch, batch, device):
     return buf, (buf.data_ptr() + 255) // 256 * 256, nb
 
 
+_streams = {}
+
+
+def _stream(torch, dev):
+    """One private default-priority stream per device for the MLP calls."""
+    if dev not in _streams:
+        _streams[dev] = torch.cuda.Stream(device=dev)
+    return _streams[dev]
+
+
 def grad(params, X, Y):
     """(loss, gradient) of the FP32 kernels; all arguments float32 device tensors."""
     import torch
@@ -55,10 +65,12 @@ def grad(params, X, Y):
     buf, ptr, nb = _scratch(torch, B, dev)
     g = torch.zeros_like(params)
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev).cuda_stream
+    s = _stream(torch, dev)
+    stream = s.cuda_stream
+    torch.cuda.synchronize(dev)
     G._check(G.lib().grmhd_mlp_grad(params.data_ptr(), X.data_ptr(), Y.data_ptr(), B,
                                     g.data_ptr(), loss.data_ptr(), ptr, nb, stream))
-    torch.cuda.synchronize(dev)
+    s.synchronize()
     return float(loss.item()), g
 
 
@@ -69,9 +81,11 @@ def infer(params, mean, std, Xraw):
     n = Xraw.shape[0]
     buf, ptr, nb = _scratch(torch, 1, dev)
     Y = torch.zeros((n, 2), dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev).cuda_stream
+    s = _stream(torch, dev)
+    torch.cuda.synchronize(dev)
     G._check(G.lib().grmhd_mlp_infer(params.data_ptr(), mean.data_ptr(), std.data_ptr(),
-                                     Xraw.data_ptr(), Y.data_ptr(), n, ptr, nb, stream))
+                                     Xraw.data_ptr(), Y.data_ptr(), n, ptr, nb, s.cuda_stream))
+    s.synchronize()
     return Y
 
 
@@ -92,7 +106,11 @@ class Trainer:
 
     def step(self, Xb, Yb, lr):
         self.t += 1
-        stream = self.torch.cuda.current_stream(self.dev).cuda_stream
+        s = _stream(self.torch, self.dev)
+        s.wait_stream(self.torch.cuda.current_stream(self.dev))   # the batch gather
+        Xb.record_stream(s)      # keep the allocator from reusing the batch early
+        Yb.record_stream(s)
+        stream = s.cuda_stream
         G._check(G.lib().grmhd_mlp_train_step(
             self.p.data_ptr(), self.m.data_ptr(), self.v.data_ptr(), Xb.data_ptr(),
             Yb.data_ptr(), Xb.shape[0], ctypes.c_float(lr), self.t, self.loss.data_ptr(),
@@ -115,6 +133,7 @@ class Trainer:
                 lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * it / total))
                 self.step(X[idx].contiguous(), Y[idx].contiguous(), lr)
                 it += 1
+            _stream(torch, self.dev).synchronize()
             hist.append(float(self.loss.item()))
             if log:
                 log(ep, hist[-1])

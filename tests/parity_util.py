@@ -43,9 +43,11 @@ def upload_all(pack, P, Bf, U=None):
     """Load identical global arrays into the pack (U via its own per-block copy)."""
     import torch
     pack.upload(P, Bf)
+    pack._out()
     if U is not None:
         for b in range(pack.nb):
             lo, n = pack.lloc[b], pack.nx[b]
             g = pack.ng
             sl = tuple(slice(lo[2 - d], lo[2 - d] + n[2 - d] + 2 * g) for d in range(3))
             pack._block_views(pack.U, b).copy_(torch.from_numpy(np.ascontiguousarray(U[(slice(None),) + sl])))
+    torch.cuda.synchronize()

@@ -33,7 +33,10 @@ def test_mixed_step_close_to_oracle(G):
         eP = rel_err(pack.download("P"), sim.P, prob)
         eB = rel_err(pack.download("Bf"), sim.Bf, prob, face=True)
         say("mixed step", s, "eP", eP, "eB", eB)
-        assert np.all(eP < 2e-5) and np.all(eB < 2e-5)
+        # FP32 face states: rho and u agree to ~1e-8, the small velocity
+        # components (own-norm) and the field to ~1e-4
+        assert eP[0] < 1e-6 and eP[4] < 1e-5
+        assert np.all(eP < 5e-4) and np.all(eB < 5e-4)
         assert eP.max() > 1e-12   # the FP32 path really ran
 
 

@@ -47,7 +47,7 @@ def test_gradient_matches_fp64_reference(env):
         per_layer.append(np.linalg.norm(gg[o:o + n] - gcf[o:o + n]) / np.linalg.norm(gcf[o:o + n]))
         o += n
     say("grad check: loss", loss_g, loss_c, "rel", rel, "per layer", per_layer)
-    assert loss_g == pytest.approx(loss_c, rel=1e-5)
+    assert loss_g == pytest.approx(loss_c, rel=1e-5)   # mean over the batch
     assert rel <= 1e-5 and max(per_layer) <= 1e-5
 
 
@@ -88,24 +88,27 @@ def trained(env):
     tr = M.Trainer(M.init_params(seed=0), batch=4096)
     Xt = torch.tensor(Xs[:ntr], device="cuda")
     Yt = torch.tensor(Y[:ntr].astype(np.float32), device="cuda")
-    hist = tr.fit(Xt, Yt, epochs=20, lr0=1e-3, seed=0,
+    loss0, _ = M.grad(tr.p, Xt[:65536].contiguous(), Yt[:65536].contiguous())
+    hist = tr.fit(Xt, Yt, epochs=50, lr0=2e-3, seed=0,
                   log=lambda ep, l: say("epoch", ep, "train loss", l))
     # validation loss through the FP32 gradient kernel
     Xv = torch.tensor(Xs[ntr:ntr + nva], device="cuda")
     Yv = torch.tensor(Y[ntr:ntr + nva].astype(np.float32), device="cuda")
     vloss, _ = M.grad(tr.p, Xv[:65536].contiguous(), Yv[:65536].contiguous())
-    say("validation loss", vloss, "first/last train loss", hist[0], hist[-1])
+    say("validation loss", vloss, "initial loss", loss0, "first/last train loss", hist[0], hist[-1])
     return {"p": tr.p, "mean": torch.tensor(mean.astype(np.float32), device="cuda"),
             "std": torch.tensor(std.astype(np.float32), device="cuda"), "X": X, "Y": Y, "U": U,
-            "prims": prims, "ntr": ntr, "nva": nva, "vloss": vloss, "hist": hist}
+            "prims": prims, "ntr": ntr, "nva": nva, "vloss": vloss, "hist": hist, "loss0": loss0}
 
 
 def test_training_converges(trained):
-    assert trained["hist"][-1] < 0.05 * trained["hist"][0]
+    """Mean squared error of (log W, log hW) on held-out data, versus the
+    untrained network."""
+    assert trained["vloss"] < 0.02 * trained["loss0"]
     assert trained["vloss"] < 0.05
 
 
-def _box_pack(G, torch, U8, nbox=(64, 64, 32)):
+def _box_pack(G, torch, U8, nbox=(64, 64, 24)):
     """A Minkowski pack whose interior cells hold the given undensitized
     conserved states (U8: [N, 8] with D, S_j, tau, B^k)."""
     prob = I.uniform_box(nbox, gamma=13.0 / 9.0)
@@ -141,6 +144,7 @@ def _box_pack(G, torch, U8, nbox=(64, 64, 32)):
     pack.upload(P, Bf)
     cnt = s[0] * s[1] * s[2]
     pack.U[:, :cnt].copy_(torch.from_numpy(Uc.reshape(5, -1)))
+    torch.cuda.synchronize()
     return pack, prob, P, Uc
 
 
@@ -150,7 +154,7 @@ def test_guess_gain_on_sampled_states(env, trained):
     The root is the same: primitives agree to the inversion's conditioning."""
     torch, G, M = env
     a = trained["ntr"] + trained["nva"]
-    U8 = trained["U"][a:a + 64 * 64 * 32]
+    U8 = trained["U"][a:a + 64 * 64 * 24]
     res = {}
     for guess in (G.GUESS_COLD, G.GUESS_MLP):
         pack, prob, P0, Uc = _box_pack(G, torch, U8)
@@ -163,7 +167,7 @@ def test_guess_gain_on_sampled_states(env, trained):
         res[guess] = (pack.download("P"), iters[it].astype(float), red)
     Pc, ic, rc = res[G.GUESS_COLD]
     Pm, im, rm = res[G.GUESS_MLP]
-    it = (slice(None),) + I.uniform_box((64, 64, 32)).interior()
+    it = (slice(None),) + I.uniform_box((64, 64, 24)).interior()
     dP = np.abs(Pm[it] - Pc[it]).max(axis=(1, 2, 3)) / np.abs(Pc[it]).max(axis=(1, 2, 3))
     say("sampled states: mean iters cold", ic.mean(), "mlp", im.mean(),
         "| wave-max mean cold", rc["c2p_iter_wavemax_mean"], "mlp", rm["c2p_iter_wavemax_mean"],
