@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["metric.c", "physics.c", "recon.c", "c2p.c", "stage.c", "api.c"]
+SOURCES = ["metric.c", "physics.c", "recon.c", "c2p.c", "stage.c", "api.c", "mesh.c"]
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
           "-std=c11", "-Wall"]
 
@@ -267,6 +267,118 @@ class Sim:
         if dt is None:
             dt = self.dt()
         U0, Bf0 = self.U.copy(), self.Bf.copy()
+        self.stage(dt, (1.0, 0.0, 1.0), U0, Bf0)
+        self.stage(dt, (0.5, 0.5, 0.5), U0, Bf0)
+        self.t += dt
+        return dt
+
+
+class _MeshDesc(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("ng", ctypes.c_int), ("root_nx", ctypes.c_int * 3),
+                ("bc", ctypes.c_int * 6), ("level", ctypes.POINTER(ctypes.c_int)),
+                ("nx", ctypes.POINTER(ctypes.c_int)), ("lloc", ctypes.POINTER(ctypes.c_int))]
+
+
+BC_FIXED = 3
+
+
+class Mesh:
+    """A two-level block mesh evaluated block by block with the oracle's stage,
+    its ghost zones filled by orc_mesh_fill_ghosts (prolongation, restriction
+    and same-level copies; see mesh.c for the reading).
+
+    root: the level-0 problem description (domain, boundaries, physics);
+    level[nb], nx[nb,3], lloc[nb,3] (level units); P_blocks / Bf_blocks:
+    per-block padded arrays (nvar, s3, s2, s1) with the interiors set.
+    One global dt, no flux or EMF correction at level boundaries."""
+
+    def __init__(self, root, level, nx, lloc, P_blocks, Bf_blocks, nthreads=1):
+        self.root = root
+        self.level = np.asarray(level, dtype=np.int32)
+        self.nx = np.asarray(nx, dtype=np.int32).reshape(-1, 3)
+        self.lloc = np.asarray(lloc, dtype=np.int32).reshape(-1, 3)
+        self.nb = len(self.level)
+        self.nthreads = nthreads
+        self.cfl = root.cfl
+        self.blocks = []
+        for b in range(self.nb):
+            blk = Block(root)
+            l = int(self.level[b])
+            g = blk.grid
+            for d in range(3):
+                dxl = root.dx[d] / (1 << l)
+                g.n[d] = int(self.nx[b, d])
+                g.dx[d] = dxl
+                g.xmin[d] = root.xmin[d] + int(self.lloc[b, d]) * dxl
+                nl = root.n[d] << l
+                g.bc[2 * d] = root.bc[2 * d] if self.lloc[b, d] == 0 else BC_FIXED
+                g.bc[2 * d + 1] = root.bc[2 * d + 1] if self.lloc[b, d] + self.nx[b, d] == nl \
+                    else BC_FIXED
+            blk.shape = tuple(int(self.nx[b, 2 - d]) + 2 * root.ng for d in range(3))
+            self.blocks.append(blk)
+        self.P = [np.ascontiguousarray(p, dtype=np.float64).copy() for p in P_blocks]
+        self.Bf = [np.ascontiguousarray(p, dtype=np.float64).copy() for p in Bf_blocks]
+        self.fill_ghosts()
+        self.U = [blk.prim_to_cons(P, Bf) for blk, P, Bf in zip(self.blocks, self.P, self.Bf)]
+        self.t = 0.0
+
+    def fill_ghosts(self, P=None, Bf=None):
+        P = self.P if P is None else P
+        Bf = self.Bf if Bf is None else Bf
+        d = _MeshDesc()
+        d.nb, d.ng = self.nb, self.root.ng
+        for k in range(3):
+            d.root_nx[k] = self.root.n[k]
+        for s in range(6):
+            d.bc[s] = self.root.bc[s]
+        lev = np.ascontiguousarray(self.level, dtype=np.int32)
+        nx = np.ascontiguousarray(self.nx.ravel(), dtype=np.int32)
+        ll = np.ascontiguousarray(self.lloc.ravel(), dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        d.level, d.nx, d.lloc = lev.ctypes.data_as(ip), nx.ctypes.data_as(ip), ll.ctypes.data_as(ip)
+        pp = (_P * self.nb)(*[_ptr(a) for a in P])
+        bp = (_P * self.nb)(*[_ptr(a) for a in Bf])
+        if lib().orc_mesh_fill_ghosts(ctypes.byref(d), pp, bp) != 0:
+            raise RuntimeError("blocks do not tile the domain")
+
+    def reductions(self):
+        outs = [blk.reductions(P, Bf, U, self.cfl)
+                for blk, P, Bf, U in zip(self.blocks, self.P, self.Bf, self.U)]
+        g = self.root.ng
+        bmax = 0.0
+        for b in range(self.nb):
+            n = self.nx[b]
+            for c in range(3):
+                ext = [n[d] + (1 if d == c else 0) for d in range(3)]
+                a = self.Bf[b][c, g:g + ext[2], g:g + ext[1], g:g + ext[0]]
+                bmax = max(bmax, float(np.abs(a).max()))
+        lmax = int(self.level.max())
+        dxmin = min(self.root.dx[d] / (1 << lmax) for d in range(3) if self.root.n[d] > 1)
+        dmax = max(o["divb_max"] for o in outs)
+        tot = np.zeros(5)
+        for o in outs:
+            tot += o["totals"]
+        return {"dt": min(o["dt"] for o in outs), "divb_max": dmax,
+                "divb_rel": dmax / (bmax / dxmin) if bmax > 0 else dmax, "totals": tot}
+
+    def dt(self):
+        return self.reductions()["dt"]
+
+    def stage(self, dt, rk, U0, Bf0):
+        nfail = 0
+        for b, blk in enumerate(self.blocks):
+            self.U[b], self.Bf[b] = blk.stage(self.P[b], self.Bf[b], U0[b], Bf0[b], self.U[b],
+                                              dt, rk, self.nthreads)
+        for b, blk in enumerate(self.blocks):
+            nfail += blk.con2prim(self.U[b], self.Bf[b], self.P[b], self.nthreads)[1]
+        self.fill_ghosts()
+        return nfail
+
+    def step(self, dt=None):
+        if dt is None:
+            dt = self.dt()
+        U0 = [u.copy() for u in self.U]
+        Bf0 = [b.copy() for b in self.Bf]
         self.stage(dt, (1.0, 0.0, 1.0), U0, Bf0)
         self.stage(dt, (0.5, 0.5, 0.5), U0, Bf0)
         self.t += dt

@@ -13,6 +13,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/grmhd.h"
@@ -39,11 +40,18 @@ struct Plan {
   std::vector<int2> ch_int, ch_ext, ch_bcc;
   std::vector<GhostP> gP;
   std::vector<GhostB> gB;
+  std::vector<GhostR> gR;          // two-level meshes: restriction + staging
+  std::vector<GhostPro> gPro;      // prolongation of P into fine ghosts
+  std::vector<GhostBR> gBR;
+  std::vector<GhostBPro> gBPro;
+  long long nsP = 0, nsB = 0;      // staged coarse-view cells / faces
+  int maxlev = 0;
   int active[3] = {1, 1, 1};
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes[3], o_chi, o_che,
-      o_chb, o_gP, o_gB, o_part, o_res, o_mlp, o_mlpw, o_mlpf, total;
+      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_part, o_res, o_mlp,
+      o_mlpw, o_mlpf, total;
   size_t o_tl[3][NSHAPE];
 };
 
@@ -74,21 +82,29 @@ int validate(const grmhd_pack_desc *d)
   if ((d->bc[0] == GRMHD_BC_POLAR) || (d->bc[1] == GRMHD_BC_POLAR) ||
       (d->bc[4] == GRMHD_BC_POLAR) || (d->bc[5] == GRMHD_BC_POLAR))
     return fail("polar boundaries only along x2", GRMHD_E_UNSUPPORTED);
+  int maxlev = 0;
   for (int b = 0; b < d->nblocks; ++b) {
     const int lev = d->level ? d->level[b] : 0;
-    if (lev != 0) return fail("refined blocks not supported by this build", GRMHD_E_UNSUPPORTED);
+    if (lev < 0 || lev > 1) return fail("levels 0 and 1 only", GRMHD_E_UNSUPPORTED);
+    maxlev = std::max(maxlev, lev);
     for (int dd = 0; dd < 3; ++dd) {
-      const int n = d->nx[3 * b + dd], l = d->lloc[3 * b + dd];
+      const int n = d->nx[3 * b + dd], l = d->lloc[3 * b + dd], N = d->root_nx[dd] << lev;
       if (n < 1 || n > 4096) return fail("block size out of range", GRMHD_E_SHAPE);
-      if (l < 0 || l + n > d->root_nx[dd]) return fail("block outside the domain", GRMHD_E_SHAPE);
-      if (n < d->ng && d->root_nx[dd] != n) return fail("split blocks need n >= ng", GRMHD_E_SHAPE);
+      if (l < 0 || l + n > N) return fail("block outside the domain", GRMHD_E_SHAPE);
+      if (n < d->ng && N != n) return fail("split blocks need n >= ng", GRMHD_E_SHAPE);
+      if (lev == 1 && ((n | l) & 1)) return fail("level-1 blocks need even size and offset", GRMHD_E_SHAPE);
     }
   }
-  // blocks must tile the domain exactly once
+  if (maxlev > 0)
+    for (int dd = 0; dd < 3; ++dd)
+      if (d->root_nx[dd] < 2 * d->ng) return fail("two-level meshes need root_nx >= 2 ng", GRMHD_E_SHAPE);
+  // blocks must tile the domain exactly once (volume in level-1 cells)
   long long vol = 0;
-  for (int b = 0; b < d->nblocks; ++b)
-    vol += (long long)d->nx[3 * b] * d->nx[3 * b + 1] * d->nx[3 * b + 2];
-  if (vol != (long long)d->root_nx[0] * d->root_nx[1] * d->root_nx[2])
+  for (int b = 0; b < d->nblocks; ++b) {
+    const int lev = d->level ? d->level[b] : 0;
+    vol += ((long long)d->nx[3 * b] * d->nx[3 * b + 1] * d->nx[3 * b + 2]) << (3 * (1 - lev));
+  }
+  if (vol != 8LL * d->root_nx[0] * d->root_nx[1] * d->root_nx[2])
     return fail("blocks do not cover the domain", GRMHD_E_SHAPE);
   return GRMHD_OK;
 }
@@ -106,13 +122,15 @@ void layout(const grmhd_pack_desc *d, std::vector<long long> &off, long long &nc
   nct = o;
 }
 
-// owner lookup of level-0 cells: granularity g cells
+// owner lookup over level-0 cells at a granularity of g cells; a level-l
+// cell is looked up through its level-0 ancestor
 struct Owner {
   int g[3], dims[3];
   std::vector<int> id;
-  int at(const int c[3]) const
+  int at(int l, const int c[3]) const
   {
-    return id[(c[0] / g[0]) + (size_t)dims[0] * ((c[1] / g[1]) + (size_t)dims[1] * (c[2] / g[2]))];
+    const int x = (c[0] >> l) / g[0], y = (c[1] >> l) / g[1], z = (c[2] >> l) / g[2];
+    return id[x + (size_t)dims[0] * (y + (size_t)dims[1] * z)];
   }
 };
 
@@ -126,20 +144,23 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.ng = d->ng;
   const int ng = d->ng;
   layout(d, p.off, p.nct);
+  auto lev_of = [&](int b) { return d->level ? d->level[b] : 0; };
+  for (int b = 0; b < p.nb; ++b) p.maxlev = std::max(p.maxlev, lev_of(b));
   double dx[3];
   for (int dd = 0; dd < 3; ++dd) dx[dd] = (d->xmax[dd] - d->xmin[dd]) / d->root_nx[dd];
   p.dxmin = 1e300;
   for (int dd = 0; dd < 3; ++dd) {
     p.active[dd] = d->root_nx[dd] > 1;
-    if (p.active[dd]) p.dxmin = std::min(p.dxmin, dx[dd]);
+    if (p.active[dd]) p.dxmin = std::min(p.dxmin, dx[dd] / (1 << p.maxlev));
   }
-  if (p.dxmin == 1e300) p.dxmin = dx[0];
+  if (p.dxmin == 1e300) p.dxmin = dx[0] / (1 << p.maxlev);
 
-  // owner grid
+  // owner grid (level-0 cells; level-1 blocks are aligned to them)
   Owner own;
   for (int dd = 0; dd < 3; ++dd) {
     int g = d->root_nx[dd];
-    for (int b = 0; b < p.nb; ++b) g = gcd(g, gcd(d->nx[3 * b + dd], d->lloc[3 * b + dd]));
+    for (int b = 0; b < p.nb; ++b)
+      g = gcd(g, gcd(d->nx[3 * b + dd] >> lev_of(b), d->lloc[3 * b + dd] >> lev_of(b)));
     own.g[dd] = g;
     own.dims[dd] = d->root_nx[dd] / g;
   }
@@ -147,8 +168,8 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   for (int b = 0; b < p.nb; ++b) {
     int lo[3], hi[3];
     for (int dd = 0; dd < 3; ++dd) {
-      lo[dd] = d->lloc[3 * b + dd] / own.g[dd];
-      hi[dd] = (d->lloc[3 * b + dd] + d->nx[3 * b + dd]) / own.g[dd];
+      lo[dd] = (d->lloc[3 * b + dd] >> lev_of(b)) / own.g[dd];
+      hi[dd] = ((d->lloc[3 * b + dd] + d->nx[3 * b + dd]) >> lev_of(b)) / own.g[dd];
     }
     for (int z = lo[2]; z < hi[2]; ++z)
       for (int y = lo[1]; y < hi[1]; ++y)
@@ -162,35 +183,38 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   // blocks and coordinate tables
   p.blocks.resize(p.nb);
   const bool plo = d->bc[2] == GRMHD_BC_POLAR, phi = d->bc[3] == GRMHD_BC_POLAR;
-  const int N2 = d->root_nx[1];
   for (int b = 0; b < p.nb; ++b) {
     BlockInfo &bi = p.blocks[b];
     std::memset(&bi, 0, sizeof bi);
+    const int lev = lev_of(b);
+    double dxl[3];
     for (int dd = 0; dd < 3; ++dd) {
+      dxl[dd] = dx[dd] / (1 << lev);
       bi.n[dd] = d->nx[3 * b + dd];
       bi.s[dd] = bi.n[dd] + 2 * ng;
-      bi.dx[dd] = dx[dd];
+      bi.dx[dd] = dxl[dd];
     }
+    const int N2 = d->root_nx[1] << lev;
     bi.off = p.off[b];
     bi.tab1 = (int)p.rc.size();
     bi.tab2 = (int)p.sc.size();
     for (int i = 0; i < bi.s[0]; ++i) {
       const int g = d->lloc[3 * b] + i - ng;
-      p.rc.push_back(std::exp(d->xmin[0] + ((double)g + 0.5) * dx[0]));
-      p.rf.push_back(std::exp(d->xmin[0] + ((double)g) * dx[0]));
+      p.rc.push_back(std::exp(d->xmin[0] + ((double)g + 0.5) * dxl[0]));
+      p.rf.push_back(std::exp(d->xmin[0] + ((double)g) * dxl[0]));
     }
     bi.pole_lo = bi.pole_hi = -1;
     for (int j = 0; j < bi.s[1]; ++j) {
       int g = d->lloc[3 * b + 1] + j - ng;
       if (plo && g < 0) g = -1 - g;
       if (phi && g >= N2) g = 2 * N2 - 1 - g;
-      const double th = d->xmin[1] + ((double)g + 0.5) * dx[1];
+      const double th = d->xmin[1] + ((double)g + 0.5) * dxl[1];
       p.sc.push_back(std::sin(th));
       p.cc.push_back(std::cos(th));
       int gf = d->lloc[3 * b + 1] + j - ng;
       if (plo && gf < 0) gf = -gf;
       if (phi && gf > N2) gf = 2 * N2 - gf;
-      const double tf = d->xmin[1] + ((double)gf) * dx[1];
+      const double tf = d->xmin[1] + ((double)gf) * dxl[1];
       const bool pole = (plo && gf == 0) || (phi && gf == N2);
       p.sf.push_back(pole ? 0.0 : std::sin(tf));
       p.cf.push_back(std::cos(tf));
@@ -247,10 +271,10 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     for (long long s = 0; s < nbc; s += 256) p.ch_bcc.push_back(make_int2(b, (int)s));
   }
 
-  // ghost maps.  Per axis: global index -> (source global index, flags);
-  // returns 0 interior, 1 mapped, -1 fixed (leave).
-  auto map_axis = [&](int dd, int g, bool normal, int &src, int &flip, int &ofl) -> int {
-    const int N = d->root_nx[dd];
+  // ghost maps.  Per axis at level l: global index -> (source global index,
+  // flags); returns 0 interior, 1 mapped, -1 fixed (leave).
+  auto map_axis = [&](int l, int dd, int g, bool normal, int &src, int &flip, int &ofl) -> int {
+    const int N = d->root_nx[dd] << l;
     const int hiN = normal ? N : N - 1;
     flip = 0; ofl = 0;
     if (g >= 0 && g <= hiN) { src = g; return 0; }
@@ -266,9 +290,84 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
       default: return -1;
     }
   };
+  // linear index of level-l global index X inside block ob (same level)
+  auto lin_in = [&](int ob, const int X[3]) -> long long {
+    const BlockInfo &sb = p.blocks[ob];
+    long long lin = 0, mul = 1;
+    for (int dd = 0; dd < 3; ++dd) {
+      lin += mul * (X[dd] - d->lloc[3 * ob + dd] + ng);
+      mul *= sb.s[dd];
+    }
+    return sb.off + lin;
+  };
+  // owner of a level-l face (the cell above it, or below at the upper edge)
+  auto face_owner = [&](int l, int comp, const int F[3]) -> int {
+    int C[3] = {F[0], F[1], F[2]};
+    C[comp] = std::min(C[comp], (d->root_nx[comp] << l) - 1);
+    return own.at(l, C);
+  };
+  // staged level-0 views: cells keyed by (mapped index, flags), faces by
+  // (component, index)
+  std::unordered_map<long long, int> stP, stB;
+  auto key3 = [&](int l, const int X[3]) -> long long {
+    const long long N0 = (long long)(d->root_nx[0] << l) + 1, N1 = (long long)(d->root_nx[1] << l) + 1;
+    return X[0] + N0 * (X[1] + N1 * (long long)X[2]);
+  };
+  // coarse-view staging row of level-0 cell C (any index); -1 beyond a fixed
+  // boundary
+  auto stage_cell = [&](const int Cin[3]) -> int {
+    int C[3], flags = 0;
+    for (int dd = 0; dd < 3; ++dd) {
+      int fl, ofl;
+      if (map_axis(0, dd, Cin[dd], false, C[dd], fl, ofl) < 0) return -1;
+      if (fl) flags |= 1 << dd;
+      if (ofl & 1) flags |= 8 << (2 * dd);
+      if (ofl & 2) flags |= 16 << (2 * dd);
+    }
+    const long long key = key3(0, C) * 512 + flags;
+    auto it = stP.find(key);
+    if (it != stP.end()) return it->second;
+    const int idx = (int)p.nsP++;
+    stP.emplace(key, idx);
+    const int ob = own.at(0, C);
+    GhostR r{};
+    r.dst = idx; r.flags = flags; r.tgt = 1;
+    if (lev_of(ob) == 0) {
+      r.src = lin_in(ob, C); r.n = 1;
+    } else {
+      const int X[3] = {2 * C[0], 2 * C[1], 2 * C[2]};
+      r.src = lin_in(ob, X); r.n = 8;
+      r.sj = p.blocks[ob].s[0]; r.sk = (long long)p.blocks[ob].s[0] * p.blocks[ob].s[1];
+    }
+    p.gR.push_back(r);
+    return idx;
+  };
+  // mean of the 4 level-1 child faces of level-0 face Q, as a GhostBR
+  auto child_faces = [&](int ob, int comp, const int Q[3], GhostBR &r) {
+    const int t1 = (comp + 1) % 3, t2 = (comp + 2) % 3;
+    const int X[3] = {2 * Q[0], 2 * Q[1], 2 * Q[2]};
+    const long long str[3] = {1, p.blocks[ob].s[0], (long long)p.blocks[ob].s[0] * p.blocks[ob].s[1]};
+    r.src = lin_in(ob, X); r.n = 4; r.st1 = str[t1]; r.st2 = str[t2];
+  };
+  // staging row of level-0 face Q (inside the domain)
+  auto stage_face = [&](int comp, const int Q[3]) -> int {
+    const long long key = key3(0, Q) * 3 + comp;
+    auto it = stB.find(key);
+    if (it != stB.end()) return it->second;
+    const int idx = (int)p.nsB++;
+    stB.emplace(key, idx);
+    const int ob = face_owner(0, comp, Q);
+    GhostBR r{};
+    r.dst = idx; r.comp = comp; r.flip = 0; r.tgt = 1;
+    if (lev_of(ob) == 0) { r.src = lin_in(ob, Q); r.n = 1; }
+    else child_faces(ob, comp, Q, r);
+    p.gBR.push_back(r);
+    return idx;
+  };
   for (int b = 0; b < p.nb; ++b) {
     const BlockInfo &bi = p.blocks[b];
     const int *ll = &d->lloc[3 * b];
+    const int l = lev_of(b);
     for (int comp = -1; comp < 3; ++comp) {   // -1: cell-centred P
       for (int k = 0; k < bi.s[2]; ++k)
         for (int j = 0; j < bi.s[1]; ++j)
@@ -285,33 +384,62 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
             for (int dd = 0; dd < 3; ++dd) {
               int fl, ofl;
               const int g = ll[dd] + idx[dd] - ng;
-              const int r = map_axis(dd, g, comp == dd, src[dd], fl, ofl);
+              const int r = map_axis(l, dd, g, comp == dd, src[dd], fl, ofl);
               if (r < 0) fixed = true;
               if (fl) { flags |= 1 << dd; if (comp == dd) flipn = 1; }
               if (ofl & 1) flags |= 8 << (2 * dd);
               if (ofl & 2) flags |= 16 << (2 * dd);
             }
             if (fixed) continue;
-            // owning block of the source (faces on the upper domain edge
-            // belong to the cell below)
-            int cell[3];
-            for (int dd = 0; dd < 3; ++dd)
-              cell[dd] = std::min(src[dd], d->root_nx[dd] - 1);
-            const int ob = own.at(cell);
-            if (ob < 0) return fail("ghost source not covered", GRMHD_E_SHAPE);
-            const BlockInfo &sb = p.blocks[ob];
-            long long lin = 0, mul = 1;
-            for (int dd = 0; dd < 3; ++dd) {
-              lin += mul * (src[dd] - d->lloc[3 * ob + dd] + ng);
-              mul *= sb.s[dd];
-            }
             const long long dst = bi.off + i + (long long)bi.s[0] * (j + (long long)bi.s[1] * k);
-            if (comp < 0) {
-              GhostP gp{dst, sb.off + lin, flags, 0};
-              p.gP.push_back(gp);
-            } else {
-              GhostB gb{dst, sb.off + lin, comp, flipn};
-              p.gB.push_back(gb);
+            const int ob = comp < 0 ? own.at(l, src) : face_owner(l, comp, src);
+            if (ob < 0) return fail("ghost source not covered", GRMHD_E_SHAPE);
+            const int lo = lev_of(ob);
+            if (lo == l) {
+              if (comp < 0) p.gP.push_back(GhostP{dst, lin_in(ob, src), flags, 0});
+              else p.gB.push_back(GhostB{dst, lin_in(ob, src), comp, flipn});
+            } else if (comp < 0 && lo < l) {          // prolongation from level 0
+              GhostPro g{};
+              g.dst = dst; g.flags = flags;
+              const int C[3] = {src[0] >> 1, src[1] >> 1, src[2] >> 1};
+              g.s[0] = stage_cell(C);
+              if (g.s[0] < 0) return fail("internal: parent beyond a fixed boundary", GRMHD_E_SHAPE);
+              for (int dd = 0; dd < 3; ++dd) {
+                int Q[3] = {C[0], C[1], C[2]};
+                Q[dd] = C[dd] - 1;
+                const int sm = stage_cell(Q);
+                Q[dd] = C[dd] + 1;
+                const int sp = stage_cell(Q);
+                g.s[1 + 2 * dd] = sm < 0 ? g.s[0] : sm;
+                g.s[2 + 2 * dd] = sp < 0 ? g.s[0] : sp;
+                g.oct |= (src[dd] & 1) << dd;
+              }
+              p.gPro.push_back(g);
+            } else if (comp < 0) {                     // restriction from level 1
+              GhostR r{};
+              const int X[3] = {2 * src[0], 2 * src[1], 2 * src[2]};
+              r.dst = dst; r.src = lin_in(ob, X); r.n = 8; r.flags = flags; r.tgt = 0;
+              r.sj = p.blocks[ob].s[0]; r.sk = (long long)p.blocks[ob].s[0] * p.blocks[ob].s[1];
+              p.gR.push_back(r);
+            } else if (lo < l) {                       // face prolongation
+              GhostBPro g{};
+              g.dst = dst; g.comp = comp; g.flip = flipn;
+              int Q[3] = {src[0] >> 1, src[1] >> 1, src[2] >> 1};
+              if ((src[comp] & 1) == 0) {
+                Q[comp] = src[comp] / 2;
+                g.sa = stage_face(comp, Q); g.sb = -1;
+              } else {
+                Q[comp] = (src[comp] - 1) / 2;
+                g.sa = stage_face(comp, Q);
+                Q[comp] = (src[comp] + 1) / 2;
+                g.sb = stage_face(comp, Q);
+              }
+              p.gBPro.push_back(g);
+            } else {                                   // face restriction
+              GhostBR r{};
+              r.dst = dst; r.comp = comp; r.flip = flipn; r.tgt = 0;
+              child_faces(ob, comp, src, r);
+              p.gBR.push_back(r);
             }
           }
     }
@@ -324,6 +452,28 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   for (const GhostB &g : p.gB)
     if (g.dst < 0 || g.dst >= p.nct || g.src < 0 || g.src >= p.nct || g.comp < 0 || g.comp > 2)
       return fail("internal: face ghost map out of range", GRMHD_E_SHAPE);
+  for (const GhostR &g : p.gR) {
+    const long long last = g.n == 1 ? g.src : g.src + 1 + g.sj + g.sk;
+    const long long lim = g.tgt ? p.nsP : p.nct;
+    if (g.dst < 0 || g.dst >= lim || g.src < 0 || last >= p.nct || (g.n != 1 && g.n != 8))
+      return fail("internal: restriction map out of range", GRMHD_E_SHAPE);
+  }
+  for (const GhostPro &g : p.gPro) {
+    if (g.dst < 0 || g.dst >= p.nct) return fail("internal: prolongation map out of range", GRMHD_E_SHAPE);
+    for (int q = 0; q < 7; ++q)
+      if (g.s[q] < 0 || g.s[q] >= p.nsP) return fail("internal: prolongation stencil out of range", GRMHD_E_SHAPE);
+  }
+  for (const GhostBR &g : p.gBR) {
+    const long long last = g.n == 1 ? g.src : g.src + g.st1 + g.st2;
+    const long long lim = g.tgt ? p.nsB : p.nct;
+    if (g.dst < 0 || g.dst >= lim || g.src < 0 || last >= p.nct || g.comp < 0 || g.comp > 2 ||
+        (g.n != 1 && g.n != 4))
+      return fail("internal: face restriction map out of range", GRMHD_E_SHAPE);
+  }
+  for (const GhostBPro &g : p.gBPro)
+    if (g.dst < 0 || g.dst >= p.nct || g.comp < 0 || g.comp > 2 || g.sa < 0 || g.sa >= p.nsB ||
+        g.sb >= p.nsB)
+      return fail("internal: face prolongation map out of range", GRMHD_E_SHAPE);
 
   // workspace carve-up
   size_t o = 0;
@@ -342,6 +492,12 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_chb = take(sizeof(int2) * p.ch_bcc.size());
   p.o_gP = take(sizeof(GhostP) * std::max<size_t>(p.gP.size(), 1));
   p.o_gB = take(sizeof(GhostB) * std::max<size_t>(p.gB.size(), 1));
+  p.o_gR = take(sizeof(GhostR) * p.gR.size());
+  p.o_gPro = take(sizeof(GhostPro) * p.gPro.size());
+  p.o_gBR = take(sizeof(GhostBR) * p.gBR.size());
+  p.o_gBPro = take(sizeof(GhostBPro) * p.gBPro.size());
+  p.o_SP = take(sizeof(double) * 5 * (size_t)p.nsP);
+  p.o_SB = take(sizeof(double) * (size_t)p.nsB);
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
   p.o_res = take(sizeof(double) * 32);
   p.o_mlp = take(sizeof(float) * (size_t)p.nct);
@@ -395,6 +551,9 @@ struct grmhd_pack {
     a.nct = plan.nct;
     a.ng = plan.ng;
     for (int d = 0; d < 3; ++d) a.active[d] = plan.active[d];
+    a.SP = (double *)(ws + plan.o_SP);
+    a.SB = (double *)(ws + plan.o_SB);
+    a.nsp = plan.nsP;
     return a;
   }
 };
@@ -626,6 +785,10 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   if (!e) e = up(pl.o_chb, pl.ch_bcc.data(), sizeof(int2) * pl.ch_bcc.size());
   if (!e) e = up(pl.o_gP, pl.gP.data(), sizeof(GhostP) * pl.gP.size());
   if (!e) e = up(pl.o_gB, pl.gB.data(), sizeof(GhostB) * pl.gB.size());
+  if (!e) e = up(pl.o_gR, pl.gR.data(), sizeof(GhostR) * pl.gR.size());
+  if (!e) e = up(pl.o_gPro, pl.gPro.data(), sizeof(GhostPro) * pl.gPro.size());
+  if (!e) e = up(pl.o_gBR, pl.gBR.data(), sizeof(GhostBR) * pl.gBR.size());
+  if (!e) e = up(pl.o_gBPro, pl.gBPro.data(), sizeof(GhostBPro) * pl.gBPro.size());
   // flags / iteration counters / flux scratch start defined
   if (!e) e = hipMemsetAsync(p->ws + pl.o_flags, 0, 2 * align_up(pl.nct), p->stream);
   if (!e) e = hipMemsetAsync(p->ws + pl.o_F, 0, sizeof(double) * 24 * (size_t)pl.nct, p->stream);
@@ -678,6 +841,20 @@ int grmhd_fill_ghosts(grmhd_pack *p, const grmhd_metric *m)
   if (!pl.gB.empty())
     hipLaunchKernelGGL(k_ghost_B, dim3((pl.gB.size() + 255) / 256), dim3(256), 0, p->stream, a,
                        dptr<GhostB>(p, pl.o_gB), (int)pl.gB.size());
+  // two-level meshes: restriction + coarse-view staging, then prolongation
+  // (every gather above reads block interiors only)
+  if (!pl.gR.empty())
+    hipLaunchKernelGGL(k_ghost_avg, dim3((pl.gR.size() + 255) / 256), dim3(256), 0, p->stream, a,
+                       dptr<GhostR>(p, pl.o_gR), (int)pl.gR.size());
+  if (!pl.gBR.empty())
+    hipLaunchKernelGGL(k_ghost_bavg, dim3((pl.gBR.size() + 255) / 256), dim3(256), 0, p->stream,
+                       a, dptr<GhostBR>(p, pl.o_gBR), (int)pl.gBR.size());
+  if (!pl.gPro.empty())
+    hipLaunchKernelGGL(k_prolong_P, dim3((pl.gPro.size() + 255) / 256), dim3(256), 0, p->stream,
+                       a, dptr<GhostPro>(p, pl.o_gPro), (int)pl.gPro.size());
+  if (!pl.gBPro.empty())
+    hipLaunchKernelGGL(k_prolong_B, dim3((pl.gBPro.size() + 255) / 256), dim3(256), 0, p->stream,
+                       a, dptr<GhostBPro>(p, pl.o_gBPro), (int)pl.gBPro.size());
   }
   {
   Prof tb(p, GRMHD_PROF_BCC);
@@ -856,6 +1033,8 @@ size_t grmhd_mlp_scratch_bytes(int batch)
   return align_up(f * sizeof(float)) + align_up(MLPB_N * 2) + align_up(MLPF_N * 4);
 }
 
+}  // extern "C"
+
 namespace {
 struct MlpScratch {
   float *Z1, *H1, *Z2, *H2, *Z3, *H3, *d1, *d2, *d3, *out, *d4, *grad, *part, *loss;
@@ -908,6 +1087,8 @@ hipError_t mlp_fwd_bwd(const float *P, const float *X, const float *Y, int B, Ml
   return hipGetLastError();
 }
 }  // namespace
+
+extern "C" {
 
 int grmhd_mlp_grad(const float *params, const float *X, const float *Y, int batch, float *grad,
                    float *loss, void *scratch, size_t scratch_bytes, void *hip_stream)

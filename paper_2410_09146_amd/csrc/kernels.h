@@ -28,13 +28,32 @@ struct KArgs {
   long long nct;
   int ng;
   int active[3];        // directions with more than one cell (CFL sum)
+  double *SP, *SB;      // staged coarse-view rows of P [5][nsp] and face B [nsb]
+  long long nsp;
 };
 
 struct GhostP { long long dst, src; int flags, pad; };
 struct GhostB { long long dst, src; int comp, flip; };
+// Two-level meshes.  A coarse-view value is the mean of n = 1 cell or of the
+// n = 8 children src + {0,1} + {0,sj} + {0,sk} of a coarse cell; tgt = 0
+// writes a ghost cell of P (restriction), tgt = 1 a row of the staging
+// buffer that the prolongation reads.
+struct GhostR { long long dst, src, sk; int flags, n, sj, tgt; };
+// Fine ghost cell from staged coarse values: s = parent, parent -/+ x1,
+// -/+ x2, -/+ x3; oct bit d set = the child lies on the upper side along d.
+struct GhostPro { long long dst; int s[7]; int flags, oct, pad; };
+// Face field: mean of n = 1 face or of the 4 child faces src + {0,st1} +
+// {0,st2} (tgt as above), and fine ghost faces from one staged coarse face
+// (sb < 0) or the mean of two.
+struct GhostBR { long long dst, src, st1, st2; int comp, flip, n, tgt; };
+struct GhostBPro { long long dst; int sa, sb, comp, flip; };
 
 // ------------------------------------------------------------------ ghosts
 
+__device__ __forceinline__ void bc_flags(int flags, double v[5]);
+
+// flags: bit d = polar mirror along d (velocity d flips); 8 << 2d / 16 << 2d
+// = low / high outflow along d (inflow velocity zeroed)
 __global__ __launch_bounds__(256) void k_ghost_P(KArgs a, const GhostP *__restrict__ map, int n)
 {
   const int e = blockIdx.x * 256 + threadIdx.x;
@@ -43,12 +62,7 @@ __global__ __launch_bounds__(256) void k_ghost_P(KArgs a, const GhostP *__restri
   double v[5];
 #pragma unroll
   for (int q = 0; q < 5; ++q) v[q] = a.P[q * a.nct + g.src];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (g.flags & (8 << (2 * d))) v[1 + d] = v[1 + d] > 0.0 ? 0.0 : v[1 + d];   // lo outflow
-    if (g.flags & (16 << (2 * d))) v[1 + d] = v[1 + d] < 0.0 ? 0.0 : v[1 + d];  // hi outflow
-    if (g.flags & (1 << d)) v[1 + d] = -v[1 + d];                                // mirror
-  }
+  bc_flags(g.flags, v);
 #pragma unroll
   for (int q = 0; q < 5; ++q) a.P[q * a.nct + g.dst] = v[q];
 }
@@ -60,6 +74,109 @@ __global__ __launch_bounds__(256) void k_ghost_B(KArgs a, const GhostB *__restri
   const GhostB g = map[e];
   const double v = a.Bf[g.comp * a.nct + g.src];
   a.Bf[g.comp * a.nct + g.dst] = g.flip ? -v : v;
+}
+
+__device__ __forceinline__ void bc_flags(int flags, double v[5])
+{
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (flags & (8 << (2 * d))) v[1 + d] = v[1 + d] > 0.0 ? 0.0 : v[1 + d];
+    if (flags & (16 << (2 * d))) v[1 + d] = v[1 + d] < 0.0 ? 0.0 : v[1 + d];
+    if (flags & (1 << d)) v[1 + d] = -v[1 + d];
+  }
+}
+
+// restriction into coarse ghosts and coarse-view staging rows
+__global__ __launch_bounds__(256) void k_ghost_avg(KArgs a, const GhostR *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostR g = map[e];
+  double v[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double *p = a.P + q * a.nct + g.src;
+    if (g.n == 1) {
+      v[q] = p[0];
+    } else {
+      double acc = 0.0;
+      for (int z = 0; z < 2; ++z)
+        for (int y = 0; y < 2; ++y)
+          for (int x = 0; x < 2; ++x) acc += p[x + y * (long long)g.sj + z * g.sk];
+      v[q] = 0.125 * acc;
+    }
+  }
+  bc_flags(g.flags, v);
+  if (g.tgt) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a.SP[q * a.nsp + g.dst] = v[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) a.P[q * a.nct + g.dst] = v[q];
+  }
+}
+
+__device__ __forceinline__ double mc_lim(double dm, double dp)
+{
+  if (dm * dp <= 0.0) return 0.0;
+  const double s = fmin(fmin(2.0 * fabs(dm), 2.0 * fabs(dp)), 0.5 * fabs(dm + dp));
+  return dm > 0.0 ? s : -s;
+}
+
+// fine ghost cells: parent + MC-limited slopes toward the child's octant;
+// a non-positive density or internal energy keeps the parent value
+__global__ __launch_bounds__(256) void k_prolong_P(KArgs a, const GhostPro *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostPro g = map[e];
+  double v[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const double *S = a.SP + q * a.nsp;
+    const double c0 = S[g.s[0]];
+    double sum = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double sl = mc_lim(c0 - S[g.s[1 + 2 * d]], S[g.s[2 + 2 * d]] - c0);
+      sum += ((g.oct >> d) & 1) ? sl : -sl;
+    }
+    v[q] = c0 + 0.25 * sum;
+    if ((q == 0 || q == 4) && (!(v[q] > 0.0) || !isfinite(v[q]))) v[q] = c0;
+  }
+  bc_flags(g.flags, v);
+#pragma unroll
+  for (int q = 0; q < 5; ++q) a.P[q * a.nct + g.dst] = v[q];
+}
+
+__global__ __launch_bounds__(256) void k_ghost_bavg(KArgs a, const GhostBR *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostBR g = map[e];
+  const double *p = a.Bf + g.comp * a.nct + g.src;
+  double v;
+  if (g.n == 1) {
+    v = p[0];
+  } else {
+    double acc = 0.0;
+    for (int t2 = 0; t2 < 2; ++t2)
+      for (int t1 = 0; t1 < 2; ++t1) acc += p[t1 * g.st1 + t2 * g.st2];
+    v = 0.25 * acc;
+  }
+  if (g.flip) v = -v;
+  if (g.tgt) a.SB[g.dst] = v;
+  else a.Bf[g.comp * a.nct + g.dst] = v;
+}
+
+__global__ __launch_bounds__(256) void k_prolong_B(KArgs a, const GhostBPro *__restrict__ map, int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const GhostBPro g = map[e];
+  double v = g.sb < 0 ? a.SB[g.sa] : 0.5 * (a.SB[g.sa] + a.SB[g.sb]);
+  if (g.flip) v = -v;
+  a.Bf[g.comp * a.nct + g.dst] = v;
 }
 
 // ------------------------------------------------------------ cell-centred B

@@ -141,10 +141,13 @@ def block_split(n, nblk):
 
 
 class Pack:
-    """A pack of same-level meshblocks covering a problem's domain.
+    """A pack of meshblocks covering a problem's domain.
 
-    prob: a problem description (paper_2410_09146_amd.inputs.Problem).
-    nblk: blocks per direction (uniform split).
+    prob: a problem description (paper_2410_09146_amd.inputs.Problem); for a
+          two-level layout it describes level 0.
+    nblk: blocks per direction (uniform split), or
+    layout: (nx, lloc) flat lists of one level, or (nx, lloc, level) with
+            levels 0 / 1 and lloc in cells of the block's own level.
     """
 
     def __init__(self, prob, nblk=(1, 1, 1), device="cuda:0", precision=PREC_FP64,
@@ -156,8 +159,11 @@ class Pack:
         self.prob = prob
         self.device = torch.device(device)
         self.ng = prob.ng
+        level = None
         if layout is not None:
             nx, lloc = list(layout[0]), list(layout[1])
+            if len(layout) > 2:
+                level = [int(v) for v in layout[2]]
         else:
             for d in range(3):
                 if prob.n[d] % nblk[d]:
@@ -166,7 +172,10 @@ class Pack:
         self.nb = len(nx) // 3
         self._nx = (ctypes.c_int * len(nx))(*nx)
         self._lloc = (ctypes.c_int * len(lloc))(*lloc)
-        self._level = (ctypes.c_int * self.nb)(*([0] * self.nb))
+        if level is None:
+            level = [0] * self.nb
+        self.level = np.array(level, dtype=np.int32)
+        self._level = (ctypes.c_int * self.nb)(*level)
         self.nx = np.array(nx).reshape(-1, 3)
         self.lloc = np.array(lloc).reshape(-1, 3)
         d = PackDesc()
@@ -231,8 +240,37 @@ class Pack:
         cnt = int(s[0] * s[1] * s[2])
         return arr[:, o:o + cnt].reshape(arr.shape[0], s[2], s[1], s[0])
 
+    def upload_blocks(self, Ps, Bfs):
+        """Copy per-block padded numpy arrays (nvar, s3, s2, s1) into the pack."""
+        torch = self.torch
+        self._out()
+        for b in range(self.nb):
+            self._block_views(self.P, b).copy_(torch.from_numpy(np.ascontiguousarray(Ps[b])))
+            self._block_views(self.Bf, b).copy_(torch.from_numpy(np.ascontiguousarray(Bfs[b])))
+
+    def download_blocks(self, which="P"):
+        """Per-block padded numpy arrays (ghosts included) of one state array."""
+        arr = {"P": self.P, "Bf": self.Bf, "U": self.U, "U0": self.U0, "Bf0": self.Bf0}[which]
+        self._out()
+        self.torch.cuda.synchronize(self.device)
+        host = arr.cpu().numpy()
+        out = []
+        for b in range(self.nb):
+            s = self.nx[b] + 2 * self.ng
+            o = self.offsets[b]
+            out.append(host[:, o:o + s[0] * s[1] * s[2]].reshape(host.shape[0], s[2], s[1], s[0]).copy())
+        return out
+
+    def init_blocks(self, Ps, Bfs):
+        """Upload per-block initial arrays, fill ghosts, build U."""
+        self.upload_blocks(Ps, Bfs)
+        self.fill_ghosts()
+        self.prim_to_cons()
+
     def upload(self, P, Bf):
         """Copy global padded numpy arrays (nvar, s3, s2, s1) into the blocks."""
+        if self.level.any():
+            raise GrmhdError("a two-level pack takes per-block arrays (upload_blocks)")
         torch = self.torch
         self._out()
         for b in range(self.nb):
@@ -245,6 +283,8 @@ class Pack:
     def download(self, which="P"):
         """Assemble a global padded numpy array from the blocks' interiors
         (and, for face arrays, the upper boundary faces)."""
+        if self.level.any():
+            raise GrmhdError("a two-level pack has no global array (download_blocks)")
         arr = {"P": self.P, "Bf": self.Bf, "U": self.U, "U0": self.U0, "Bf0": self.Bf0}[which]
         self._out()
         self.torch.cuda.synchronize(self.device)

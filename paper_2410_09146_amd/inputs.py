@@ -621,3 +621,143 @@ def batch_layout(prob, target=640, base=64, seed=7):
         if best is None or abs(nb - target) < abs(best[0] - target):
             best = (nb, nx, lloc)
     return best[1], best[2]
+
+
+# ---------------------------------------------------------------------------
+# Two-level block meshes
+# ---------------------------------------------------------------------------
+
+def two_level_layout(root_n, node, dense, p_coarse=(0.5,), p_fine=(0.5, 0.35), smallest=16,
+                     seed=7):
+    """Seeded two-level block layout.  The level-0 root grid root_n[3] is cut
+    into node^3 regions; a region where dense(lo, node) holds is refined into a
+    (2 node)^3 region of level-1 cells, the others stay at level 0.  Each region
+    is then split by the seeded octree (p_coarse / p_fine: split probability
+    per octree depth) down to `smallest` cells.  Returns flat lists
+    (level, nx, lloc), lloc in cells of the block's own level."""
+    rng = np.random.default_rng(seed)
+    level, nx, lloc = [], [], []
+
+    def visit(lev, lo, s, k, probs):
+        if s > smallest and k < len(probs) and rng.uniform() < probs[k]:
+            h = s // 2
+            for dz in (0, h):
+                for dy in (0, h):
+                    for dx in (0, h):
+                        visit(lev, (lo[0] + dx, lo[1] + dy, lo[2] + dz), h, k + 1, probs)
+            return
+        level.append(lev)
+        nx.extend([s, s, s])
+        lloc.extend(list(lo))
+
+    for d in range(3):
+        if root_n[d] % node:
+            raise ValueError("root grid must be a multiple of the region size")
+    for z in range(0, root_n[2], node):
+        for y in range(0, root_n[1], node):
+            for x in range(0, root_n[0], node):
+                if dense((x, y, z), node):
+                    visit(1, (2 * x, 2 * y, 2 * z), 2 * node, 0, p_fine)
+                else:
+                    visit(0, (x, y, z), node, 0, p_coarse)
+    return level, nx, lloc
+
+
+def fine_dense_fn(prob_fine, thresh=1e-2):
+    """dense(lo, size) on level-0 regions: does the region hold a level-1
+    cell of prob_fine with rho > thresh * rho_max?"""
+    g = prob_fine.ng
+    rho = prob_fine.P[0][g:-g, g:-g, g:-g]
+    big = rho > thresh * rho.max()
+
+    def dense(lo, s):
+        return bool(big[2 * lo[2]:2 * (lo[2] + s), 2 * lo[1]:2 * (lo[1] + s),
+                        2 * lo[0]:2 * (lo[0] + s)].any())
+    return dense
+
+
+def amr_layout(prob_fine, target=640, node=32, smallest=16, seed=7, thresh=1e-2):
+    """Two-level layout of a problem given at the level-1 resolution (level 0 =
+    half of it): regions holding rho > thresh rho_max are refined; the octree
+    split probabilities are scaled (deterministically) until the block count
+    is the closest to `target`."""
+    root_n = tuple(n // 2 for n in prob_fine.n)
+    dense = fine_dense_fn(prob_fine, thresh)
+    best = None
+    for scale in np.linspace(0.1, 2.0, 96):
+        pc = (min(1.0, 0.5 * scale),)
+        pf = (min(1.0, 0.8 * scale), min(1.0, 0.45 * scale))
+        lay = two_level_layout(root_n, node, dense, pc, pf, smallest, seed)
+        nb = len(lay[0])
+        if best is None or abs(nb - target) < abs(len(best[0]) - target):
+            best = lay
+    return best
+
+
+def coarse_problem(prob_fine):
+    """Level-0 description of a problem given at the level-1 resolution (same
+    domain and physics, half the cells, no state arrays)."""
+    import copy
+    root = copy.copy(prob_fine)
+    root.n = tuple(n // 2 for n in prob_fine.n)
+    root.P = None
+    root.Bf = None
+    root.meta = dict(prob_fine.meta)
+    return root
+
+
+def mesh_blocks(prob_fine, level, nx, lloc):
+    """Per-block padded initial arrays (P [5, s3, s2, s1], Bf [3, ...]) of a
+    two-level layout: level-1 blocks copy prob_fine's interior; level-0 blocks
+    hold its restriction (cell means of the 8 children; face means of the 4
+    child faces, so the coarse field is divergence-free whenever the fine one
+    is).  Ghost zones are left zero."""
+    g = prob_fine.ng
+    Pf, Bff = prob_fine.P, prob_fine.Bf
+    nx = np.asarray(nx).reshape(-1, 3)
+    lloc = np.asarray(lloc).reshape(-1, 3)
+    Ps, Bs = [], []
+    for b in range(len(level)):
+        n = nx[b]
+        s = n + 2 * g
+        P = np.zeros((5, s[2], s[1], s[0]))
+        Bf = np.zeros((3, s[2], s[1], s[0]))
+        lo = lloc[b]
+        if level[b] == 1:
+            P[:, g:g + n[2], g:g + n[1], g:g + n[0]] = \
+                Pf[:, g + lo[2]:g + lo[2] + n[2], g + lo[1]:g + lo[1] + n[1], g + lo[0]:g + lo[0] + n[0]]
+            for c in range(3):
+                e = [n[d] + (1 if d == c else 0) for d in range(3)]
+                Bf[c, g:g + e[2], g:g + e[1], g:g + e[0]] = \
+                    Bff[c, g + lo[2]:g + lo[2] + e[2], g + lo[1]:g + lo[1] + e[1],
+                        g + lo[0]:g + lo[0] + e[0]]
+        else:
+            f0 = 2 * lo
+            blk = Pf[:, g + f0[2]:g + f0[2] + 2 * n[2], g + f0[1]:g + f0[1] + 2 * n[1],
+                     g + f0[0]:g + f0[0] + 2 * n[0]]
+            acc = np.zeros((5, n[2], n[1], n[0]))
+            for dz in (0, 1):
+                for dy in (0, 1):
+                    for dx in (0, 1):
+                        acc += blk[:, dz::2, dy::2, dx::2]
+            P[:, g:g + n[2], g:g + n[1], g:g + n[0]] = 0.125 * acc
+            for c in range(3):
+                e = [n[d] + (1 if d == c else 0) for d in range(3)]
+                # child faces: normal index 2 F, transverse 2 t + {0, 1}
+                ext = [2 * n[d] if d != c else 2 * n[d] + 1 for d in range(3)]
+                fb = Bff[c, g + f0[2]:g + f0[2] + ext[2], g + f0[1]:g + f0[1] + ext[1],
+                         g + f0[0]:g + f0[0] + ext[0]]
+                sl = [None, None, None]
+                acc = 0.0
+                for t1 in (0, 1):
+                    for t2 in (0, 1):
+                        off = [0, 0, 0]
+                        off[(c + 1) % 3] = t1
+                        off[(c + 2) % 3] = t2
+                        for d in range(3):
+                            sl[d] = slice(off[d], ext[d], 2)
+                        acc = acc + fb[sl[2], sl[1], sl[0]]
+                Bf[c, g:g + e[2], g:g + e[1], g:g + e[0]] = 0.25 * acc
+        Ps.append(P)
+        Bs.append(Bf)
+    return Ps, Bs

@@ -99,3 +99,43 @@ def test_python_binding_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(G.GrmhdError):
         G.Pack(I.linear_wave((16, 16, 16)))
+
+
+def _desc_layout(prob, nx, lloc, level):
+    nb = len(level)
+    d = G.PackDesc()
+    d.nblocks, d.ng = nb, prob.ng
+    d.recon, d.riemann, d.precision, d.weno_fv = prob.recon, prob.riemann, 0, 0
+    keep = [(ctypes.c_int * len(nx))(*nx), (ctypes.c_int * nb)(*level),
+            (ctypes.c_int * len(lloc))(*lloc)]
+    d.nx, d.level, d.lloc = keep
+    for k in range(3):
+        d.root_nx[k], d.xmin[k], d.xmax[k] = prob.n[k], prob.xmin[k], prob.xmax[k]
+    for s in range(6):
+        d.bc[s] = prob.bc[s]
+    return d, keep
+
+
+def test_two_level_plan_builds_and_checks_maps(L):
+    """The host plan of the two-level torus layout builds (its gather maps
+    pass their own bounds checks); malformed level layouts are refused."""
+    fine = I.torus(n=(64, 64, 32))
+    lev, nx, ll = I.amr_layout(fine, target=60, node=8, smallest=8)
+    root = I.coarse_problem(fine)
+    d, keep = _desc_layout(root, nx, ll, lev)
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d)) > 0, L.grmhd_last_error(None)
+    # a level-1 block at an odd offset
+    b = lev.index(1)
+    ll2 = list(ll)
+    ll2[3 * b] += 1
+    d, keep = _desc_layout(root, nx, ll2, lev)
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d)) == 0
+    # level 2 is not supported
+    lev3 = list(lev)
+    lev3[b] = 2
+    d, keep = _desc_layout(root, nx, ll, lev3)
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d)) == 0
+    assert b"level" in L.grmhd_last_error(None)
+    # two blocks over the same cells
+    d, keep = _desc_layout(root, nx + nx[:3], ll + ll[:3], lev + lev[:1])
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d)) == 0
