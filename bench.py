@@ -94,21 +94,23 @@ def main():
     ncell = n ** 3
     value = ncell * args.steps / (ms * 1e-3)
 
-    # dominant kernel family and its roofline (algorithmic FP64 flops per face)
-    fam = max(prof, key=lambda k: prof[k][0])
+    # dominant kernel: the face-flux tile kernel k_flux (one launch per
+    # direction and stage; the three directions are one template); roofline
+    # from algorithmic FP64 flops per face
     opc = json.load(open(os.path.join(ROOT, "paper_2410_09146_amd", "opcount", "opcount.json")))
     per_face = opc["per_face_flux_ks_weno_llf"]
-    roof = None
-    if fam.startswith("flux_x"):
-        t_ms, cnt = prof[fam]
-        avg_ms = t_ms / cnt
-        flops = per_face * flux_faces(n)
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None, "kernel": f"k_flux ({fam})",
-                "avg_launch_ms": round(avg_ms, 4), "flops_per_face": per_face,
-                "faces_per_launch": flux_faces(n)}
+    fams = ("flux_x1", "flux_x2", "flux_x3")
+    t_ms = sum(prof[f][0] for f in fams)
+    cnt = sum(prof[f][1] for f in fams)
+    avg_ms = t_ms / cnt
+    flops = per_face * flux_faces(n)
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "traffic": None, "kernel": "k_flux (x1, x2, x3 launches)",
+            "avg_launch_ms": round(avg_ms, 4), "flops_per_face": per_face,
+            "faces_per_launch": flux_faces(n),
+            "share_of_step": round(t_ms / args.steps / (ms / args.steps), 3)}
     # HBM view of the whole step: 480 algorithmic bytes per zone-cycle
     hbm = {"algorithmic_bytes_per_zone_cycle": 480,
            "achieved_GBs": round(480 * value / 1e9, 1),
@@ -131,6 +133,15 @@ def main():
                "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_steps} SSPRK2 step(s) of the same {n}^3 torus, "
                          f"{t_cpu:.1f} s wall, {threads} OpenMP threads"}
+        # one thread, on a slab of the same torus (same r-theta grid, 8 phi cells)
+        slab = I.torus(n=(n, n, 8))
+        sim1 = oracle.Sim(slab, nthreads=1)
+        dt1 = sim1.dt()
+        t0 = time.perf_counter()
+        sim1.step(dt1)
+        t1 = time.perf_counter() - t0
+        cpu["single_thread"] = {"value": round(n * n * 8 / t1, 1), "cores": 1,
+                                "sample": f"1 SSPRK2 step of the torus at {n}x{n}x8, {t1:.1f} s wall"}
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "zone-cycles/s", "n_gpus": 1,

@@ -45,7 +45,7 @@ enum { GRMHD_OK = 0, GRMHD_E_INVALID = -1, GRMHD_E_SHAPE = -2, GRMHD_E_HIP = -3,
 enum { GRMHD_METRIC_MINKOWSKI = 0, GRMHD_METRIC_KS_LOGSPH = 1 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2, GRMHD_BC_FIXED = 3 };
 enum { GRMHD_RECON_CONST = 0, GRMHD_RECON_PLM_MC = 1, GRMHD_RECON_WENO5Z_AOAH = 2,
-       GRMHD_RECON_PLM_MINMOD = 3 };
+       GRMHD_RECON_PLM_MINMOD = 3, GRMHD_RECON_MP5 = 4 };
 enum { GRMHD_RIEMANN_HLL = 0, GRMHD_RIEMANN_LLF = 1 };
 enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_GUESS_COLD = 0, GRMHD_GUESS_PREV = 1, GRMHD_GUESS_MLP = 2 };
@@ -71,12 +71,21 @@ typedef struct {
 
 /*
  * Pack descriptor.  nblocks blocks, block b has nx[3b..3b+2] interior cells,
- * refinement level level[b] and logical location lloc[3b..3b+2] = global index
- * (in cells of its level) of its first interior cell.  The whole domain spans
- * [xmin, xmax] with root_nx cells at level 0.  bc[6] = boundary kind at
- * (x1 lo, x1 hi, x2 lo, x2 hi, x3 lo, x3 hi).  ng must be 4.
- * weno_fv: 0 = WENO candidates interpolate point values (App. B wording),
- *          1 = cell-average candidates.
+ * refinement level level[b] (0 or 1; NULL = all 0) and logical location
+ * lloc[3b..3b+2] = global index (in cells of its level) of its first interior
+ * cell.  The whole domain spans [xmin, xmax] with root_nx cells at level 0
+ * (root_nx << 1 at level 1); the blocks must tile it exactly once, level-1
+ * blocks with even sizes and offsets.  Ghost zones between levels are filled
+ * by restriction (cell means of 8 children, face means of 4 child faces) and
+ * prolongation (parent plus monotonized-central limited slopes; faces constant
+ * across a coarse face and linear along its normal); no flux or EMF correction
+ * at level boundaries (paper Sec. 1 and 3 use Parthenon's block-structured
+ * refinement).  bc[6] = boundary kind at (x1 lo, x1 hi, x2 lo, x2 hi, x3 lo,
+ * x3 hi).  ng must be 4.
+ * recon: GRMHD_RECON_* (Sec. 3.1 list: constant, linear with minmod or MC,
+ *        mp5 of Suresh & Huynh 1997, WENO5-Z-AOAH of App. B).
+ * weno_fv: 0 = the fifth-order candidates interpolate point values (App. B
+ *          wording), 1 = cell-average reconstruction (WENO5 and MP5 alike).
  */
 typedef struct {
   int nblocks, ng;

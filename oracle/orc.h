@@ -27,7 +27,7 @@
 enum { ORC_MINKOWSKI = 0, ORC_KS_LOGSPH = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_POLAR = 2, ORC_BC_FIXED = 3 };
 enum { ORC_RECON_CONST = 0, ORC_RECON_PLM_MC = 1, ORC_RECON_WENO5Z_AOAH = 2,
-       ORC_RECON_PLM_MINMOD = 3 };
+       ORC_RECON_PLM_MINMOD = 3, ORC_RECON_MP5 = 4 };
 enum { ORC_RIEMANN_HLL = 0, ORC_RIEMANN_LLF = 1 };
 enum { ORC_LOC_CENTER = 0, ORC_LOC_FACE1 = 1, ORC_LOC_FACE2 = 2, ORC_LOC_FACE3 = 3 };
 

@@ -102,8 +102,60 @@ static double weno_face(int fv, const double f[5], double *sigma_side)
   return w[0] * p[0] + w[1] * p[1] + w[2] * p[2];
 }
 
+/*
+ * MP5, the monotonicity-preserving fifth-order scheme of Suresh & Huynh
+ * (J. Comput. Phys. 136, 1997), which the paper lists among its
+ * reconstructions without further detail.  Face j+1/2 from f[0..4]:
+ *   the unlimited fifth-order value (Lagrange interpolation of the point
+ *   values, or the cell-average reconstruction when fv = 1);
+ *   f_MP = f_j + minmod(f_{j+1} - f_j, alpha (f_j - f_{j-1})), alpha = 4;
+ *   if (f5 - f_j)(f5 - f_MP) <= 0 the value is kept; otherwise it is moved
+ *   to the nearest point of [f_min, f_max] built from the curvatures
+ *   d_i = f_{i-1} - 2 f_i + f_{i+1} and their M4 minmod combinations
+ *   (upper limit f_UL, average f_AV, median f_MD, large-curvature f_LC).
+ */
+static double minmod2(double a, double b)
+{
+  if (a * b <= 0.0) return 0.0;
+  return sgn(a) * fmin(fabs(a), fabs(b));
+}
+
+static double minmod4(double a, double b, double c, double d)
+{
+  const double s = sgn(a);
+  if (sgn(b) != s || sgn(c) != s || sgn(d) != s) return 0.0;
+  return s * fmin(fmin(fabs(a), fabs(b)), fmin(fabs(c), fabs(d)));
+}
+
+static double mp5_face(int fv, const double f[5])
+{
+  const double alpha = 4.0;
+  const double fm2 = f[0], fm1 = f[1], f0 = f[2], fp1 = f[3], fp2 = f[4];
+  const double f5 = fv ? (2.0 * fm2 - 13.0 * fm1 + 47.0 * f0 + 27.0 * fp1 - 3.0 * fp2) / 60.0
+                       : (3.0 * fm2 - 20.0 * fm1 + 90.0 * f0 + 60.0 * fp1 - 5.0 * fp2) / 128.0;
+  const double fmp = f0 + minmod2(fp1 - f0, alpha * (f0 - fm1));
+  if ((f5 - f0) * (f5 - fmp) <= 0.0) return f5;
+  const double dm = fm2 - 2.0 * fm1 + f0, d0 = fm1 - 2.0 * f0 + fp1, dp = f0 - 2.0 * fp1 + fp2;
+  const double dM4p = minmod4(4.0 * d0 - dp, 4.0 * dp - d0, d0, dp);
+  const double dM4m = minmod4(4.0 * d0 - dm, 4.0 * dm - d0, d0, dm);
+  const double fUL = f0 + alpha * (f0 - fm1);
+  const double fAV = 0.5 * (f0 + fp1);
+  const double fMD = fAV - 0.5 * dM4p;
+  const double fLC = f0 + 0.5 * (f0 - fm1) + (4.0 / 3.0) * dM4m;
+  const double fmin_ = fmax(fmin(fmin(f0, fp1), fMD), fmin(fmin(f0, fUL), fLC));
+  const double fmax_ = fmin(fmax(fmax(f0, fp1), fMD), fmax(fmax(f0, fUL), fLC));
+  /* median(f5, fmin, fmax) */
+  return f5 + minmod2(fmin_ - f5, fmax_ - f5);
+}
+
 void orc_recon1(int method, int fv, const double f[5], double *fl, double *fr)
 {
+  if (method == ORC_RECON_MP5) {
+    const double fm[5] = {f[4], f[3], f[2], f[1], f[0]};   /* x -> -x */
+    *fr = mp5_face(fv, f);
+    *fl = mp5_face(fv, fm);
+    return;
+  }
   if (method == ORC_RECON_CONST) {
     *fl = f[2]; *fr = f[2];
     return;

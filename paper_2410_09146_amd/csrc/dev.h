@@ -13,7 +13,7 @@
 namespace grmhd {
 
 enum { MK_MINK = 0, MK_KS = 1 };
-enum { RC_CONST = 0, RC_PLM_MC = 1, RC_WENO = 2, RC_PLM_MINMOD = 3 };
+enum { RC_CONST = 0, RC_PLM_MC = 1, RC_WENO = 2, RC_PLM_MINMOD = 3, RC_MP5 = 4 };
 enum { RS_HLL = 0, RS_LLF = 1 };
 
 // ------------------------------------------------------------------ layout
@@ -230,9 +230,9 @@ __device__ __forceinline__ void flux_of(const GeoT<T> &G, const PrimT<T> &q, con
 template <int DIR, typename T>
 __device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T> &A, T &lm, T &lp)
 {
-  const T cs2 = gam * A.p / A.w;
-  const T ca2 = A.b2 / (A.w + A.b2);
-  const T c2 = cs2 + ca2 - cs2 * ca2;
+  // c^2 = cs^2 + ca^2 - cs^2 ca^2 = 1 - (1 - cs^2)(1 - ca^2), with
+  // cs^2 = gam p / w and ca^2 = b^2 / (w + b^2), is (gam p + b^2) / (w + b^2)
+  const T c2 = (gam * A.p + A.b2) / (A.w + A.b2);
   const T ia2 = T(1) / (G.alpha * G.alpha);
   const T u0 = A.W / G.alpha;
   const T ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
@@ -363,11 +363,109 @@ __device__ __forceinline__ T weno_z_face(T f0, T f1, T f2, T f3, T f4, T &sig)
   return w0 * p0 + w1 * p1 + w2 * p2;
 }
 
+// Both WENO5-Z faces of cell j in FP64 with three divisions instead of
+// eleven.  The smoothness indicators of the left face are those of the right
+// face mirrored (beta_0 <-> beta_2), and with q_k = beta_k + eps the weights
+// alpha_k = gamma_k (1 + (tau/q_k)^2) are proportional to the homogeneous
+//   a_k = gamma_k (q_k^2 + tau^2) prod_{m != k} q_m^2,
+// so one division normalises each face (q >= eps = 1e-40 keeps every a_k a
+// normal number for |f| below ~1e25).  The blend sigma = 2 s+ s- / (s+ + s-)
+// of the per-face measures s = N / D (N = 3 w0 w1 w2, D = g2 w0 w1 + g1 w0 w2
+// + g0 w1 w2) is 2 N+ N- / (N+ D- + N- D+): the third division.  Returns
+// false (and nothing) if a normalising sum is not a finite positive number.
+template <int FV>
+__device__ __forceinline__ bool weno_pair(double f0, double f1, double f2, double f3, double f4,
+                                          double &pl, double &pr, double &sigma)
+{
+  constexpr double g0 = FV ? 0.1 : 1.0 / 16.0;
+  constexpr double g1 = FV ? 0.6 : 10.0 / 16.0;
+  constexpr double g2 = FV ? 0.3 : 5.0 / 16.0;
+  const double t0 = f0 - 2.0 * f1 + f2, s0 = f0 - 4.0 * f1 + 3.0 * f2;
+  const double t1 = f1 - 2.0 * f2 + f3, s1 = f1 - f3;
+  const double t2 = f2 - 2.0 * f3 + f4, s2 = 3.0 * f2 - 4.0 * f3 + f4;
+  constexpr double c13 = 13.0 / 12.0;
+  const double b0 = c13 * t0 * t0 + 0.25 * s0 * s0;
+  const double b1 = c13 * t1 * t1 + 0.25 * s1 * s1;
+  const double b2 = c13 * t2 * t2 + 0.25 * s2 * s2;
+  const double tau = fabs(b0 - b2), tt = tau * tau;
+  constexpr double eps = Lim<double>::weno_eps;
+  const double q0 = b0 + eps, q1 = b1 + eps, q2 = b2 + eps;
+  const double E0 = q0 * q0 + tt, E1 = q1 * q1 + tt, E2 = q2 * q2 + tt;
+  const double m01 = q0 * q1, m02 = q0 * q2, m12 = q1 * q2;
+  const double Q01 = m01 * m01, Q02 = m02 * m02, Q12 = m12 * m12;
+  // right face j+1/2 and its mirror j-1/2
+  const double ar0 = g0 * E0 * Q12, ar1 = g1 * E1 * Q02, ar2 = g2 * E2 * Q01;
+  const double al0 = g0 * E2 * Q01, al1 = g1 * E1 * Q02, al2 = g2 * E0 * Q12;
+  const double Sr = ar0 + ar1 + ar2, Sl = al0 + al1 + al2;
+  if (!(Sr > 0.0 && Sr <= 1.7e308 && Sl > 0.0 && Sl <= 1.7e308)) return false;
+  const double ir = 1.0 / Sr, il = 1.0 / Sl;
+  const double wr0 = ar0 * ir, wr1 = ar1 * ir, wr2 = ar2 * ir;
+  const double wl0 = al0 * il, wl1 = al1 * il, wl2 = al2 * il;
+  double pr0, pr1, pr2, pl0, pl1, pl2;
+  if constexpr (FV) {
+    pr0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * (1.0 / 6.0);
+    pr1 = (-f1 + 5.0 * f2 + 2.0 * f3) * (1.0 / 6.0);
+    pr2 = (2.0 * f2 + 5.0 * f3 - f4) * (1.0 / 6.0);
+    pl0 = (2.0 * f4 - 7.0 * f3 + 11.0 * f2) * (1.0 / 6.0);
+    pl1 = (-f3 + 5.0 * f2 + 2.0 * f1) * (1.0 / 6.0);
+    pl2 = (2.0 * f2 + 5.0 * f1 - f0) * (1.0 / 6.0);
+  } else {
+    pr0 = (3.0 * f0 - 10.0 * f1 + 15.0 * f2) * 0.125;
+    pr1 = (-f1 + 6.0 * f2 + 3.0 * f3) * 0.125;
+    pr2 = (3.0 * f2 + 6.0 * f3 - f4) * 0.125;
+    pl0 = (3.0 * f4 - 10.0 * f3 + 15.0 * f2) * 0.125;
+    pl1 = (-f3 + 6.0 * f2 + 3.0 * f1) * 0.125;
+    pl2 = (3.0 * f2 + 6.0 * f1 - f0) * 0.125;
+  }
+  pr = wr0 * pr0 + wr1 * pr1 + wr2 * pr2;
+  pl = wl0 * pl0 + wl1 * pl1 + wl2 * pl2;
+  const double Nr = 3.0 * wr0 * wr1 * wr2, Dr = g2 * wr0 * wr1 + g1 * wr0 * wr2 + g0 * wr1 * wr2;
+  const double Nl = 3.0 * wl0 * wl1 * wl2, Dl = g2 * wl0 * wl1 + g1 * wl0 * wl2 + g0 * wl1 * wl2;
+  sigma = 2.0 * Nr * Nl / (Nr * Dl + Nl * Dr);
+  return true;
+}
+
+// Monotonicity-preserving fifth-order face value at x_{j+1/2} (Suresh &
+// Huynh 1997) from f0..f4 = f_{j-2..j+2}, alpha = 4: the unlimited value is
+// kept when it lies between f_j and the monotone bound f_MP; otherwise it is
+// moved into [f_min, f_max] built from the M4-limited curvatures.
+template <typename T>
+__device__ __forceinline__ T minmod4(T a, T b, T c, T d)
+{
+  const bool pos = a > T(0) && b > T(0) && c > T(0) && d > T(0);
+  const bool neg = a < T(0) && b < T(0) && c < T(0) && d < T(0);
+  const T m = fmin(fmin(fabs(a), fabs(b)), fmin(fabs(c), fabs(d)));
+  return pos ? m : (neg ? -m : T(0));
+}
+
+template <int FV, typename T>
+__device__ __forceinline__ T mp5_face(T fm2, T fm1, T f0, T fp1, T fp2)
+{
+  constexpr T alpha = T(4);
+  const T f5 = FV ? (T(2) * fm2 - T(13) * fm1 + T(47) * f0 + T(27) * fp1 - T(3) * fp2) * T(1.0 / 60.0)
+                  : (T(3) * fm2 - T(20) * fm1 + T(90) * f0 + T(60) * fp1 - T(5) * fp2) * T(1.0 / 128.0);
+  const T fmp = f0 + minmod_slope(fp1 - f0, alpha * (f0 - fm1));
+  if ((f5 - f0) * (f5 - fmp) <= T(0)) return f5;
+  const T dm = fm2 - T(2) * fm1 + f0, d0 = fm1 - T(2) * f0 + fp1, dp = f0 - T(2) * fp1 + fp2;
+  const T dM4p = minmod4(T(4) * d0 - dp, T(4) * dp - d0, d0, dp);
+  const T dM4m = minmod4(T(4) * d0 - dm, T(4) * dm - d0, d0, dm);
+  const T fUL = f0 + alpha * (f0 - fm1);
+  const T fAV = T(0.5) * (f0 + fp1);
+  const T fMD = fAV - T(0.5) * dM4p;
+  const T fLC = f0 + T(0.5) * (f0 - fm1) + T(4.0 / 3.0) * dM4m;
+  const T lo = fmax(fmin(fmin(f0, fp1), fMD), fmin(fmin(f0, fUL), fLC));
+  const T hi = fmin(fmax(fmax(f0, fp1), fMD), fmax(fmax(f0, fUL), fLC));
+  return f5 + minmod_slope(lo - f5, hi - f5);     // median(f5, lo, hi)
+}
+
 // Left (j-1/2) and right (j+1/2) face values of cell j.
 template <int RECON, int FV, typename T>
 __device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &fr)
 {
-  if constexpr (RECON == RC_CONST) {
+  if constexpr (RECON == RC_MP5) {
+    fr = mp5_face<FV>(f0, f1, f2, f3, f4);
+    fl = mp5_face<FV>(f4, f3, f2, f1, f0);
+  } else if constexpr (RECON == RC_CONST) {
     fl = f2; fr = f2;
   } else if constexpr (RECON == RC_PLM_MINMOD) {
     const T s = minmod_slope(f2 - f1, f3 - f2);
@@ -377,10 +475,17 @@ __device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &f
     fl = f2 - T(0.5) * s; fr = f2 + T(0.5) * s;
   } else {
     const T s = mc_slope(f2 - f1, f3 - f2);
-    T sp, sm;
-    const T pr = weno_z_face<FV>(f0, f1, f2, f3, f4, sp);
-    const T pl = weno_z_face<FV>(f4, f3, f2, f1, f0, sm);   // mirror x -> -x
-    T sigma = T(2) * sp * sm / (sp + sm);
+    T pr, pl, sigma;
+    bool done = false;
+#ifndef GRMHD_OPCOUNT   // the operation count is taken on the per-face definition
+    if constexpr (sizeof(T) == sizeof(double)) done = weno_pair<FV>(f0, f1, f2, f3, f4, pl, pr, sigma);
+#endif
+    if (!done) {
+      T sp, sm;
+      pr = weno_z_face<FV>(f0, f1, f2, f3, f4, sp);
+      pl = weno_z_face<FV>(f4, f3, f2, f1, f0, sm);   // mirror x -> -x
+      sigma = T(2) * sp * sm / (sp + sm);
+    }
     sigma = sigma > T(0) ? sigma : T(0);                     // also maps NaN to 0
     sigma = sigma < T(1) ? sigma : T(1);
     fr = sigma * pr + (T(1) - sigma) * (f2 + T(0.5) * s);

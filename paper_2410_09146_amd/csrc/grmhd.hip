@@ -66,7 +66,7 @@ int validate(const grmhd_pack_desc *d)
   if (!d) return fail("null descriptor", GRMHD_E_INVALID);
   if (d->nblocks < 1 || d->nblocks > (1 << 20)) return fail("nblocks out of range", GRMHD_E_INVALID);
   if (d->ng != 4) return fail("ng must be 4", GRMHD_E_UNSUPPORTED);
-  if (d->recon < 0 || d->recon > 3) return fail("bad recon", GRMHD_E_INVALID);
+  if (d->recon < 0 || d->recon > 4) return fail("bad recon", GRMHD_E_INVALID);
   if (d->riemann < 0 || d->riemann > 1) return fail("bad riemann", GRMHD_E_INVALID);
   if (d->precision != GRMHD_PREC_FP64 && d->precision != GRMHD_PREC_MIXED)
     return fail("bad precision", GRMHD_E_INVALID);
@@ -704,6 +704,10 @@ void launch_flux_rc(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs)
     case RC_CONST: launch_flux_rs<MK, RC_CONST, 0, T>(p, a, rs); break;
     case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0, T>(p, a, rs); break;
     case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0, T>(p, a, rs); break;
+    case RC_MP5:
+      if (fv) launch_flux_rs<MK, RC_MP5, 1, T>(p, a, rs);
+      else launch_flux_rs<MK, RC_MP5, 0, T>(p, a, rs);
+      break;
     default:
       if (fv) launch_flux_rs<MK, RC_WENO, 1, T>(p, a, rs);
       else launch_flux_rs<MK, RC_WENO, 0, T>(p, a, rs);

@@ -731,11 +731,17 @@ __global__ __launch_bounds__(256) void k_reduce_fin(const double *__restrict__ p
   }
   for (int q = 0; q < NPART; ++q) sh[threadIdx.x][q] = o[q];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int t = 1; t < 256; ++t) {
-      for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], sh[t][q]);
-      for (int q = 3; q < NPART; ++q) o[q] += sh[t][q];
+  // pairwise tree in a fixed order (deterministic)
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const int t = threadIdx.x;
+      for (int q = 0; q < 3; ++q) sh[t][q] = fmax(sh[t][q], sh[t + w][q]);
+      for (int q = 3; q < NPART; ++q) sh[t][q] += sh[t + w][q];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < NPART; ++q) o[q] = sh[0][q];
     res[0] = o[0] > 0.0 ? cfl / o[0] : 0.0;
     res[1] = o[2] > 0.0 ? o[1] / (o[2] / dxmin) : o[1];
     res[2] = o[1];

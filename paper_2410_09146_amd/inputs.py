@@ -21,7 +21,7 @@ import numpy as np
 
 # boundary kinds, reconstructions, Riemann solvers, metrics (ABI values)
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_FIXED = 0, 1, 2, 3
-RECON_CONST, RECON_PLM_MC, RECON_WENO5Z, RECON_PLM_MINMOD = 0, 1, 2, 3
+RECON_CONST, RECON_PLM_MC, RECON_WENO5Z, RECON_PLM_MINMOD, RECON_MP5 = 0, 1, 2, 3, 4
 RIEMANN_HLL, RIEMANN_LLF = 0, 1
 MINKOWSKI, KS_LOGSPH = 0, 1
 

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 
+#define GRMHD_OPCOUNT 1
 #define __device__
 #define __forceinline__ inline
 

@@ -190,19 +190,25 @@ def test_torus_deployment(env, trained):
         pack.init()
         pack.reductions(sync=False)
         its, wm, fb = [], [], []
+        pack.profile(True)
         for _ in range(20):
             pack.step(None, guess=guess)
             r = pack.reductions()
             its.append(r["c2p_iter_mean"]); wm.append(r["c2p_iter_wavemax_mean"])
             fb.append(r["guess_fallback"])
-        out[guess] = (pack.download("P"), np.mean(its), np.mean(wm), np.sum(fb))
+        prof = pack.profile_read()
+        pack.profile(False)
+        # inversion kernel time per call (40 calls), network inference included
+        ms = (prof["con2prim"][0] + prof["mlp"][0]) / max(prof["con2prim"][1], 1)
+        out[guess] = (pack.download("P"), np.mean(its), np.mean(wm), np.sum(fb), ms)
         del pack
     Pp = out[G.GUESS_PREV][0]
     it = (slice(None),) + prob.interior()
     for gname, gk in (("prev", G.GUESS_PREV), ("mlp", G.GUESS_MLP), ("cold", G.GUESS_COLD)):
         dP = np.abs(out[gk][0][it] - Pp[it]).max(axis=(1, 2, 3)) / np.abs(Pp[it]).max(axis=(1, 2, 3))
         say("torus", gname, "mean iters", out[gk][1], "wave-max mean", out[gk][2],
-            "fallbacks", out[gk][3], "max rel dP vs prev", dP.max())
+            "fallbacks", out[gk][3], "max rel dP vs prev", dP.max(),
+            "inversion ms per call", out[gk][4])
         assert dP.max() < 1e-8
     # On the torus most cells are near-static atmosphere, where the cold guess
     # 1/sqrt(1 + r^2) is already close; the learned guess (log hW to a few per

@@ -35,6 +35,10 @@ def _cases():
                                                   recon=I.RECON_PLM_MINMOD, riemann=I.RIEMANN_LLF),
         "box_const_hll": lambda: I.random_smooth_box((16, 16, 16), seed=3, amp=0.1,
                                                      recon=I.RECON_CONST),
+        "box_mp5": lambda: I.random_smooth_box((20, 18, 16), seed=4, amp=0.2,
+                                               recon=I.RECON_MP5, riemann=I.RIEMANN_LLF),
+        "shock_mp5_fv": lambda: _fv(I.shock_tube(64, recon=I.RECON_MP5)),
+        "torus_mp5": lambda: I.torus(n=(24, 24, 8), recon=I.RECON_MP5),
         "torus": lambda: I.torus(n=(32, 32, 16)),
         "torus_hll_fv": lambda: _fv(I.torus(n=(24, 24, 8), riemann=I.RIEMANN_HLL)),
         "shock": lambda: I.shock_tube(64),
@@ -173,7 +177,8 @@ def test_reductions_parity(grmhd, case):
     assert np.allclose(rg["totals"], ro["totals"], rtol=1e-13, atol=1e-13 * np.abs(ro["totals"]).max())
 
 
-@pytest.mark.parametrize("case,nsteps", [("wave", 3), ("torus", 2), ("torus_hll_fv", 2)])
+@pytest.mark.parametrize("case,nsteps", [("wave", 3), ("torus", 2), ("torus_hll_fv", 2),
+                                         ("torus_mp5", 2), ("box_mp5", 2)])
 def test_steps_from_identical_state(grmhd, case, nsteps):
     """Full SSPRK2 steps on the GPU; each step is compared with one oracle
     step taken from the same input state (per-step gate)."""

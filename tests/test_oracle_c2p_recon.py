@@ -91,16 +91,16 @@ def test_invalid_state_flagged():
 
 # ------------------------------------------------------------- reconstruction
 
-CONST, MC, WENO, MINMOD = 0, 1, 2, 3
+CONST, MC, WENO, MINMOD, MP5 = 0, 1, 2, 3, 4
 
 
-@pytest.mark.parametrize("method", [CONST, MC, WENO, MINMOD])
+@pytest.mark.parametrize("method", [CONST, MC, WENO, MINMOD, MP5])
 def test_constant_exact(method):
     fl, fr = oracle.recon(method, [2.5] * 5)
     assert fl == 2.5 and fr == 2.5
 
 
-@pytest.mark.parametrize("method", [MC, WENO, MINMOD])
+@pytest.mark.parametrize("method", [MC, WENO, MINMOD, MP5])
 def test_linear_exact(method):
     f = 0.3 + 0.7 * np.arange(-2, 3)
     fl, fr = oracle.recon(method, f)
@@ -146,7 +146,7 @@ def test_weno_beta_brute_force():
 
 def test_mirror_symmetry():
     rng = np.random.default_rng(8)
-    for method in (MC, WENO, MINMOD):
+    for method in (MC, WENO, MINMOD, MP5):
         for _ in range(50):
             f = rng.normal(size=5)
             fl, fr = oracle.recon(method, f)
@@ -187,3 +187,61 @@ def test_weno_fifth_order_smooth():
         errs.append(e)
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 4.5), (errs, orders)
+
+
+# ---------------------------------------------------------------- MP5
+
+def test_mp5_quartic_exact_both_readings():
+    """Smooth monotone quartic: the limiter stays inactive and the face value
+    is the exact fifth-order one (point-value interpolation, or cell averages
+    with fv = 1)."""
+    c = [1.0, 0.5, 0.05, 0.01, 0.002]
+    q = lambda x: sum(ck * x ** k for k, ck in enumerate(c))
+    xs = np.arange(-2, 3).astype(float)
+    fl, fr = oracle.recon(MP5, q(xs), fv=0)
+    assert fr == pytest.approx(q(0.5), abs=1e-14)
+    assert fl == pytest.approx(q(-0.5), abs=1e-14)
+
+    def avg(x):          # exact cell average of the quartic over [x-1/2, x+1/2]
+        P = np.polynomial.Polynomial(c).integ()
+        return P(x + 0.5) - P(x - 0.5)
+    fl, fr = oracle.recon(MP5, avg(xs), fv=1)
+    assert fr == pytest.approx(q(0.5), abs=1e-14)
+    assert fl == pytest.approx(q(-0.5), abs=1e-14)
+
+
+def test_mp5_monotone_data_no_new_extrema():
+    """On monotone data every face value lies between its two neighbouring
+    cell values (the monotonicity-preserving property)."""
+    rng = np.random.default_rng(12)
+    for _ in range(2000):
+        inc = rng.exponential(size=5) * (rng.uniform(size=5) < 0.7)
+        f = np.cumsum(inc) * rng.choice([-1.0, 1.0])
+        for fv in (0, 1):
+            fl, fr = oracle.recon(MP5, f, fv=fv)
+            assert min(f[2], f[3]) - 1e-13 <= fr <= max(f[2], f[3]) + 1e-13
+            assert min(f[1], f[2]) - 1e-13 <= fl <= max(f[1], f[2]) + 1e-13
+
+
+def test_mp5_step_and_extremum():
+    fl, fr = oracle.recon(MP5, [0.0, 0.0, 0.0, 1.0, 1.0])
+    assert 0.0 <= fr <= 1.0 and fl == 0.0
+    # a sharp isolated peak is not amplified
+    fl, fr = oracle.recon(MP5, [0.0, 0.0, 1.0, 0.0, 0.0])
+    assert 0.0 <= fl <= 1.0 and 0.0 <= fr <= 1.0
+
+
+def test_mp5_fifth_order_smooth():
+    errs = []
+    for N in (32, 64, 128, 256):
+        h = 1.0 / N
+        x = (np.arange(N) + 0.5) * h
+        fun = lambda y: np.sin(2 * np.pi * y + 0.3)
+        e = 0.0
+        for j in range(N):
+            st = fun(x[j] + h * np.arange(-2, 3))
+            fl, fr = oracle.recon(MP5, st)
+            e = max(e, abs(fr - fun(x[j] + 0.5 * h)), abs(fl - fun(x[j] - 0.5 * h)))
+        errs.append(e)
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 4.5, (errs, orders)

@@ -82,18 +82,19 @@ def test_linear_fast_wave_second_order():
     assert tot[-1] < 0.05
 
 
-@pytest.mark.parametrize("case", ["sod", "strong"])
+@pytest.mark.parametrize("case", ["sod", "strong", "sod_mp5"])
 def test_shock_tube_vs_exact(case):
     """B = 0 shock tube against the exact SR Riemann solution: L1(rho)
     converges at about first order (discontinuities)."""
-    if case == "sod":
+    recon = I.RECON_MP5 if case.endswith("mp5") else I.RECON_PLM_MC
+    if case.startswith("sod"):
         L, R, g, tend = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 5.0 / 3.0, 0.4
     else:
         L, R, g, tend = (10.0, 0.0, 13.33), (1.0, 0.0, 0.01333), 5.0 / 3.0, 0.35
     ex = ExactRiemann(L, R, g)
     errs = []
     for N in (100, 200, 400):
-        prob = I.shock_tube(N, L, R, g)
+        prob = I.shock_tube(N, L, R, g, recon=recon)
         sim = oracle.Sim(prob, NT)
         while sim.t < tend - 1e-14:
             sim.step(min(sim.dt(), tend - sim.t))
@@ -104,7 +105,7 @@ def test_shock_tube_vs_exact(case):
     errs = np.array(errs)
     orders = np.log2(errs[:-1] / errs[1:])
     assert np.all(orders > 0.6), (errs, orders)
-    assert errs[-1] < (0.01 if case == "sod" else 0.05)
+    assert errs[-1] < (0.01 if case.startswith("sod") else 0.05)
 
 
 def test_michel_inflow_held_to_truncation_error():
