@@ -32,7 +32,46 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--persist", type=int, default=0,
                     help="persistent flux grid size in workgroups (0: one per tile)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of exactly 1 GiB, three times."""
+    import torch
+    n = 1 << 27                                  # float64 elements = 1 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
+
+
+KERNEL_SOURCES = ("paper_2410_09146_amd/csrc/kernels.h", "paper_2410_09146_amd/csrc/dev.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(faces):
+    """HBM bytes per k_flux launch from the committed rocprofv3 counter
+    summary, if it was taken on the kernel sources as they are now."""
+    path = os.path.join(ROOT, "profiles", "k_flux_torus128_traffic.json")
+    if not os.path.exists(path):
+        return None
+    s = json.load(open(path))
+    if s.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return s["hbm_bytes_per_launch"]
 
 
 def flux_faces(n):
@@ -43,6 +82,9 @@ def flux_faces(n):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "nothing here spans a second GPU", file=sys.stderr)
@@ -107,7 +149,7 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": None, "kernel": "k_flux (x1, x2, x3 launches)",
+            "traffic": measured_traffic(flux_faces(n)), "kernel": "k_flux (x1, x2, x3 launches)",
             "avg_launch_ms": round(avg_ms, 4), "flops_per_face": per_face,
             "faces_per_launch": flux_faces(n),
             "share_of_step": round(t_ms / args.steps / (ms / args.steps), 3)}

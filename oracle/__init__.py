@@ -261,6 +261,7 @@ class Sim:
         self.U, self.Bf = U, Bf
         flag, nfail = self.blk.con2prim(self.U, self.Bf, self.P, self.nthreads)
         self.blk.fill_ghosts(self.P, self.Bf)
+        self.flag = flag
         return flag, nfail
 
     def step(self, dt=None):

@@ -475,7 +475,7 @@ __device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &f
     fl = f2 - T(0.5) * s; fr = f2 + T(0.5) * s;
   } else {
     const T s = mc_slope(f2 - f1, f3 - f2);
-    T pr, pl, sigma;
+    T pr = T(0), pl = T(0), sigma = T(0);
     bool done = false;
 #ifndef GRMHD_OPCOUNT   // the operation count is taken on the per-face definition
     if constexpr (sizeof(T) == sizeof(double)) done = weno_pair<FV>(f0, f1, f2, f3, f4, pl, pr, sigma);

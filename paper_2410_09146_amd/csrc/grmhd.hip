@@ -36,7 +36,7 @@ struct Plan {
   std::vector<BlockInfo> blocks;
   std::vector<double> rc, rf, sc, cc, sf, cf;
   std::vector<int4> tiles[3][NSHAPE];
-  std::vector<int2> planes[3];
+  std::vector<int2> planes;       // (3 block + D, first face), 64 faces each
   std::vector<int2> ch_int, ch_ext, ch_bcc;
   std::vector<GhostP> gP;
   std::vector<GhostB> gB;
@@ -49,7 +49,7 @@ struct Plan {
   int active[3] = {1, 1, 1};
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
-  size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes[3], o_chi, o_che,
+  size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes, o_chi, o_che,
       o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_part, o_res, o_mlp,
       o_mlpw, o_mlpf, total;
   size_t o_tl[3][NSHAPE];
@@ -261,7 +261,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     for (int D = 0; D < 3; ++D) {
       const int AX = D == 0 ? 1 : 0, BX = D == 2 ? 1 : 2;
       const int np = (bi.n[AX] + 2) * (bi.n[BX] + 2);
-      for (int s = 0; s < np; s += 256) p.planes[D].push_back(make_int2(b, s));
+      for (int s = 0; s < np; s += 64) p.planes.push_back(make_int2(3 * b + D, s));
     }
     const long long ni = (long long)bi.n[0] * bi.n[1] * bi.n[2];
     for (long long s = 0; s < ni; s += 256) p.ch_int.push_back(make_int2(b, (int)s));
@@ -486,7 +486,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
   for (int D = 0; D < 3; ++D)
     for (int sh = 0; sh < NSHAPE; ++sh) p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
-  for (int D = 0; D < 3; ++D) p.o_planes[D] = take(sizeof(int2) * p.planes[D].size());
+  p.o_planes = take(sizeof(int2) * p.planes.size());
   p.o_chi = take(sizeof(int2) * p.ch_int.size());
   p.o_che = take(sizeof(int2) * p.ch_ext.size());
   p.o_chb = take(sizeof(int2) * p.ch_bcc.size());
@@ -500,7 +500,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_SB = take(sizeof(double) * (size_t)p.nsB);
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
   p.o_res = take(sizeof(double) * 32);
-  p.o_mlp = take(sizeof(float) * (size_t)p.nct);
+  p.o_mlp = take(sizeof(float) * 2 * (size_t)p.nct);   // learned mu0 and W per cell
   p.o_mlpw = take(sizeof(unsigned short) * MLPB_N);
   p.o_mlpf = take(sizeof(float) * MLPF_N);
   p.total = o;
@@ -672,14 +672,7 @@ void launch_tiles_sh(grmhd_pack *p, const KArgs &a, int sh)
 template <int MK, int D, int RC, int FV, int RS, typename T>
 void launch_flux(grmhd_pack *p, const KArgs &a)
 {
-  const Plan &pl = p->plan;
   launch_tiles_sh<MK, D, RC, FV, RS, T>(p, a, p->tune_sh >= 0 ? p->tune_sh : p->shape[D]);
-  if (p->tune_sh >= 0) return;     // autotuning times the tile kernels alone
-  if (!pl.planes[D].empty()) {
-    Prof t(p, GRMHD_PROF_FLUX_PLANE);
-    hipLaunchKernelGGL((k_flux_plane<MK, D, RC, FV, RS, T>), dim3(pl.planes[D].size()), dim3(256),
-                       0, p->stream, a, dptr<int2>(p, pl.o_planes[D]));
-  }
 }
 
 template <int MK, int RC, int FV, int RS, typename T>
@@ -688,6 +681,11 @@ void launch_flux3(grmhd_pack *p, const KArgs &a)
   if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T>(p, a);
   if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T>(p, a);
   if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T>(p, a);
+  const Plan &pl = p->plan;
+  if (p->tune_sh >= 0 || pl.planes.empty()) return;   // autotuning times the tiles alone
+  Prof t(p, GRMHD_PROF_FLUX_PLANE);
+  hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T>), dim3(pl.planes.size()), dim3(64), 0,
+                     p->stream, a, dptr<int2>(p, pl.o_planes));
 }
 
 template <int MK, int RC, int FV, typename T>
@@ -779,11 +777,10 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   hipError_t e = hipSuccess;
   if (!e) e = up(pl.o_blocks, pl.blocks.data(), sizeof(BlockInfo) * pl.blocks.size());
   if (!e) e = up(pl.o_tab, tab.data(), sizeof(double) * tab.size());
-  for (int D = 0; D < 3; ++D) {
+  for (int D = 0; D < 3; ++D)
     for (int sh = 0; sh < NSHAPE; ++sh)
       if (!e) e = up(pl.o_tl[D][sh], pl.tiles[D][sh].data(), sizeof(int4) * pl.tiles[D][sh].size());
-    if (!e) e = up(pl.o_planes[D], pl.planes[D].data(), sizeof(int2) * pl.planes[D].size());
-  }
+  if (!e) e = up(pl.o_planes, pl.planes.data(), sizeof(int2) * pl.planes.size());
   if (!e) e = up(pl.o_chi, pl.ch_int.data(), sizeof(int2) * pl.ch_int.size());
   if (!e) e = up(pl.o_che, pl.ch_ext.data(), sizeof(int2) * pl.ch_ext.size());
   if (!e) e = up(pl.o_chb, pl.ch_bcc.data(), sizeof(int2) * pl.ch_bcc.size());
@@ -902,7 +899,23 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   return GRMHD_OK;
 }
 
-int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess)
+}  // extern "C"
+
+namespace {
+
+template <int MK, int RED>
+void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch, const float *mlp,
+                double *part)
+{
+  if (guess == 0) hipLaunchKernelGGL((k_c2p<MK, 0, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+  else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK, 1, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+  else hipLaunchKernelGGL((k_c2p<MK, 2, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+}
+
+// part != nullptr: the inversion also writes the reduction partials, and the
+// final fold runs right after it (the reductions of grmhd_reductions).
+int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess,
+                  double cfl, bool reduce)
 {
   if (!p) return GRMHD_E_INVALID;
   if (int rc = check_metric(p, m)) return rc;
@@ -929,18 +942,34 @@ int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
                          a, md, ch, mu);
     LAUNCHCHK(p);
   }
+  double *part = (double *)(p->ws + pl.o_part);
+  {
   Prof t(p, GRMHD_PROF_C2P);
-  if (m->kind == GRMHD_METRIC_KS_LOGSPH) {
-    if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
-    else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK_KS, 1>), g, dim3(256), 0, p->stream, a, ch, mlp);
-    else hipLaunchKernelGGL((k_c2p<MK_KS, 2>), g, dim3(256), 0, p->stream, a, ch, mlp);
+  const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
+  if (reduce) {
+    if (ks) launch_c2p<MK_KS, 1>(p, a, guess, g, ch, mlp, part);
+    else launch_c2p<MK_MINK, 1>(p, a, guess, g, ch, mlp, part);
   } else {
-    if (guess == 0) hipLaunchKernelGGL((k_c2p<MK_MINK, 0>), g, dim3(256), 0, p->stream, a, ch, mlp);
-    else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK_MINK, 1>), g, dim3(256), 0, p->stream, a, ch, mlp);
-    else hipLaunchKernelGGL((k_c2p<MK_MINK, 2>), g, dim3(256), 0, p->stream, a, ch, mlp);
+    if (ks) launch_c2p<MK_KS, 0>(p, a, guess, g, ch, mlp, part);
+    else launch_c2p<MK_MINK, 0>(p, a, guess, g, ch, mlp, part);
+  }
+  }
+  if (reduce) {
+    Prof t(p, GRMHD_PROF_REDUCE);
+    hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(256), 0, p->stream, (const double *)part,
+                       (int)pl.ch_int.size(), cfl, pl.dxmin, (double *)(p->ws + pl.o_res));
   }
   LAUNCHCHK(p);
   return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_con2prim(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess)
+{
+  return con2prim_impl(p, m, eos, guess, 0.0, false);
 }
 
 int grmhd_prim_to_cons(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos)
@@ -1165,9 +1194,9 @@ int grmhd_step(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doubl
   if ((rc = grmhd_con2prim(p, m, eos, guess))) return rc;
   if ((rc = grmhd_fill_ghosts(p, m))) return rc;
   if ((rc = grmhd_stage(p, m, eos, dt, rk2))) return rc;
-  if ((rc = grmhd_con2prim(p, m, eos, guess))) return rc;
+  // the last inversion also produces the reductions (dt of the next step)
+  if ((rc = con2prim_impl(p, m, eos, guess, cfl, cfl > 0.0))) return rc;
   if ((rc = grmhd_fill_ghosts(p, m))) return rc;
-  if (cfl > 0.0 && (rc = grmhd_reductions(p, m, eos, cfl, nullptr))) return rc;
   return GRMHD_OK;
 }
 

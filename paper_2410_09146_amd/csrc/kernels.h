@@ -3,7 +3,7 @@
 //   k_ghost_P / k_ghost_B   gather ghost zones through precomputed maps
 //   k_bcc                   cell-centred B from the face field
 //   k_flux<D>               LDS-staged 16x16 face tiles: reconstruct -> Riemann
-//   k_flux_plane<D>         the last face plane along D (one thread per face)
+//   k_flux_planes           the last face plane of every direction (one thread per face)
 //   k_update                flux divergence + sources + CT (edge-averaged EMF)
 //                           + Runge-Kutta combination, one thread per cell
 //   k_c2p                   safeguarded Newton inversion + floors
@@ -258,7 +258,8 @@ __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo 
 {
   if (D == 1 && (j == b.pole_lo || j == b.pole_hi)) {   // sqrt(-g) = 0 on the axis
 #pragma unroll
-    for (int v = 0; v < 8; ++v) a.F[(D * 8 + v) * a.nct + c] = 0.0;
+    for (int v = 0; v < 8; ++v)
+      if (v != 5 + D) a.F[(D * 8 + v) * a.nct + c] = 0.0;
     return;
   }
   const Geo G = geo_face<MK, D>(a, b, i, j);
@@ -273,7 +274,8 @@ __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo 
   const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
   for (int v = 0; v < 8; ++v)
-    a.F[(D * 8 + v) * a.nct + c] = smg * (double)A[v] + sg * (double)B[v];
+    if (v != 5 + D)        // the flux of the normal field component vanishes identically
+      a.F[(D * 8 + v) * a.nct + c] = smg * (double)A[v] + sg * (double)B[v];
 }
 
 template <typename T>
@@ -355,15 +357,13 @@ __global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ 
   }
 }
 
-// Faces on the upper boundary plane along D (index ng + n_D), one per thread.
+// One face on the upper boundary plane along D (index ng + n_D); e indexes
+// the (n_A + 2) x (n_B + 2) faces of the plane (transverse ghosts included).
 template <int MK, int D, int RECON, int FV, int RS, typename T>
-__global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restrict__ chunks)
+__device__ __forceinline__ void plane_face(const KArgs &a, const BlockInfo &b, int e)
 {
   constexpr int AX = (D == 0) ? 1 : 0;
   constexpr int BX = (D == 2) ? 1 : 2;
-  const int2 ch = chunks[blockIdx.x];
-  const BlockInfo b = a.blocks[ch.x];
-  const int e = ch.y + threadIdx.x;
   const int na = b.n[AX] + 2, nb = b.n[BX] + 2;
   if (e >= na * nb) return;
   int idx[3];
@@ -389,6 +389,22 @@ __global__ __launch_bounds__(256) void k_flux_plane(KArgs a, const int2 *__restr
     qR[v] = l;
   }
   face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
+}
+
+// The boundary planes of all three directions in one launch of 64-thread
+// workgroups (a plane holds ~1/n of a direction's faces: small grids of
+// latency-bound work are better spread thin over the CUs):
+// chunk = (3 * block + D, first face of 64).
+template <int MK, int RECON, int FV, int RS, typename T>
+__global__ __launch_bounds__(64) void k_flux_planes(KArgs a, const int2 *__restrict__ chunks)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const int D = ch.x % 3;
+  const BlockInfo b = a.blocks[ch.x / 3];
+  const int e = ch.y + threadIdx.x;
+  if (D == 0) plane_face<MK, 0, RECON, FV, RS, T>(a, b, e);
+  else if (D == 1) plane_face<MK, 1, RECON, FV, RS, T>(a, b, e);
+  else plane_face<MK, 2, RECON, FV, RS, T>(a, b, e);
 }
 
 // ------------------------------------------------------------------ update
@@ -476,27 +492,134 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
   }
 }
 
+// ------------------------------------------------------------- reductions
+
+constexpr int NPART = 13;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax, guess fallback
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Per-cell diagnostics of the reductions: [0] sum_d max|lambda_d| / dx_d,
+// [1] |div B|, [2] max |face B|, [3..7] U dV, [8] failed inversion,
+// [9] floor hit, [10] Newton iterations, [12] learned guess rejected.
+template <int MK>
+__device__ __forceinline__ void cell_diag(const KArgs &a, const BlockInfo &b, const Geo &G,
+                                          const Prim &q, const double bf[6], const double U[5],
+                                          int fl, int iters, double val[NPART])
+{
+  const Aux A = aux_of(G, a.eos.gam, q);
+  double s = 0.0, lm, lp;
+  if (a.active[0]) { speeds_of<0>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[0]; }
+  if (a.active[1]) { speeds_of<1>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[1]; }
+  if (a.active[2]) { speeds_of<2>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[2]; }
+  val[0] = s;
+  val[1] = fabs((bf[1] - bf[0]) / b.dx[0] + (bf[3] - bf[2]) / b.dx[1] + (bf[5] - bf[4]) / b.dx[2]);
+  val[2] = fmax(fmax(fmax(fabs(bf[0]), fabs(bf[1])), fmax(fabs(bf[2]), fabs(bf[3]))),
+                fmax(fabs(bf[4]), fabs(bf[5])));
+  const double dV = b.dx[0] * b.dx[1] * b.dx[2];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) val[3 + v] = U[v] * dV;
+  val[8] = (fl & 8) ? 1.0 : 0.0;
+  val[9] = (fl & 7) ? 1.0 : 0.0;
+  val[10] = (double)iters;
+  val[11] = 0.0;
+  val[12] = (fl & 16) ? 1.0 : 0.0;
+}
+
+// Fold the 256 threads' diagnostics (wavefront shuffles, then a fixed order
+// over the 4 wavefronts) into part[blockIdx.x]; every thread must call it.
+__device__ __forceinline__ void block_diag_store(double val[NPART], double *__restrict__ part)
+{
+  __shared__ double sh[4][NPART];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double itmax = wave_max(val[10]);
+#pragma unroll
+  for (int q = 0; q < 3; ++q) val[q] = wave_max(val[q]);
+#pragma unroll
+  for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
+  val[11] = itmax;
+  val[12] = wave_sum(val[12]);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double o[NPART];
+#pragma unroll
+    for (int q = 0; q < NPART; ++q) o[q] = sh[0][q];
+    for (int w = 1; w < 4; ++w) {
+      for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], sh[w][q]);
+      for (int q = 3; q < NPART; ++q) o[q] += sh[w][q];
+    }
+    for (int q = 0; q < NPART; ++q) part[(long long)blockIdx.x * NPART + q] = o[q];
+  }
+}
+
+template <int MK>
+__global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict__ chunks,
+                                                double *__restrict__ part)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  double val[NPART];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) val[q] = 0.0;
+  if (e < b.n[0] * b.n[1] * b.n[2]) {
+    const int ng = a.ng;
+    const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+    const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+    const long long c = b.off + i + sj * j + sk * k;
+    const long long n = a.nct;
+    const Geo G = geo_center<MK>(a, b, i, j);
+    const double isg = 1.0 / G.sqrtg;
+    const double bf[6] = {a.Bf[c], a.Bf[c + 1], a.Bf[n + c], a.Bf[n + c + sj], a.Bf[2 * n + c],
+                          a.Bf[2 * n + c + sk]};
+    Prim q;
+    q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+    q.ie = a.P[4 * n + c];
+    q.B1 = 0.5 * (bf[0] + bf[1]) * isg; q.B2 = 0.5 * (bf[2] + bf[3]) * isg;
+    q.B3 = 0.5 * (bf[4] + bf[5]) * isg;
+    double U[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) U[v] = a.U[v * n + c];
+    cell_diag<MK>(a, b, G, q, bf, U, a.flags[c], a.iters[c], val);
+  }
+  block_diag_store(val, part);
+}
+
 // --------------------------------------------------------------- inversion
 
 template <int MK>
 __device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Geo &G,
-                                           const Prim &q)
+                                           const Prim &q, double Uout[5])
 {
   const Aux A = aux_of(G, a.eos.gam, q);
   double U[8];
   cons_of(G, q, A, U);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) a.U[v * a.nct + c] = G.sqrtg * U[v];
+  for (int v = 0; v < 5; ++v) {
+    Uout[v] = G.sqrtg * U[v];
+    a.U[v * a.nct + c] = Uout[v];
+  }
 }
 
-template <int MK, int GUESS>
-__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks,
-                                             const float *__restrict__ mlp_mu)
+// One cell's inversion + floors; with RED also its reduction diagnostics.
+template <int MK, int GUESS, int RED>
+__device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int e,
+                                         const float *__restrict__ mlp_mu, double val[NPART])
 {
-  const int2 ch = chunks[blockIdx.x];
-  const BlockInfo b = a.blocks[ch.x];
-  const int e = ch.y + threadIdx.x;
-  if (e >= b.n[0] * b.n[1] * b.n[2]) return;
   const int ng = a.ng;
   const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
   const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
@@ -504,12 +627,17 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
   const long long n = a.nct;
   const Geo G = geo_center<MK>(a, b, i, j);
   const double isg = 1.0 / G.sqrtg;
-  double Ud[5];
+  double Ur[5], Ud[5];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) Ud[v] = a.U[v * n + c] * isg;
-  const double B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
-  const double B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
-  const double B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
+  for (int v = 0; v < 5; ++v) {
+    Ur[v] = a.U[v * n + c];
+    Ud[v] = Ur[v] * isg;
+  }
+  const double bf[6] = {a.Bf[c], a.Bf[c + 1], a.Bf[n + c], a.Bf[n + c + sj], a.Bf[2 * n + c],
+                        a.Bf[2 * n + c + sk]};
+  const double B1 = 0.5 * (bf[0] + bf[1]) * isg;
+  const double B2 = 0.5 * (bf[2] + bf[3]) * isg;
+  const double B3 = 0.5 * (bf[4] + bf[5]) * isg;
   Prim prev;
   prev.rho = a.P[c]; prev.u1 = a.P[n + c]; prev.u2 = a.P[2 * n + c]; prev.u3 = a.P[3 * n + c];
   prev.ie = a.P[4 * n + c];
@@ -546,9 +674,20 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
         const Aux Ap = aux_of(G, gam, prev);
         mu = 1.0 / ((1.0 + gam * prev.ie / prev.rho) * Ap.W);
         if constexpr (GUESS == 2) {
-          const float g = mlp_mu[c];
-          if (g > 0.0f && g <= 1.0f) mu = (double)g;
-          else flag |= 16;                       // learned guess rejected: previous P
+          // learned guess, kept if its W(mu0) agrees with the network's own
+          // W output to 50 % (out-of-distribution check); else previous P
+          const double g = (double)mlp_mu[c];
+          bool take = g > 0.0 && g <= 1.0;
+          if (take) {
+            const double x0 = 1.0 / (1.0 + g * m.b2);
+            const double rb0 = m.r2 * x0 * x0 + g * x0 * (1.0 + x0) * m.rb * m.rb;
+            double v20 = g * g * rb0;
+            v20 = v20 > m.v2max ? m.v2max : v20;
+            const double W0 = 1.0 / sqrt(1.0 - v20);
+            take = fabs((double)mlp_mu[a.nct + c] - W0) <= 0.5 * W0;
+          }
+          if (take) mu = g;
+          else flag |= 16;
         }
       }
       if (!(mu > 0.0 && mu <= 1.0)) mu = 0.5;
@@ -601,9 +740,28 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
   }
   a.P[c] = q.rho; a.P[n + c] = q.u1; a.P[2 * n + c] = q.u2; a.P[3 * n + c] = q.u3;
   a.P[4 * n + c] = q.ie;
-  if (flag & 15) cons_store<MK>(a, c, G, q);
+  if (flag & 15) cons_store<MK>(a, c, G, q, Ur);
   a.flags[c] = (int8_t)flag;
   a.iters[c] = (uint8_t)min(iters, 255);
+  if constexpr (RED != 0) cell_diag<MK>(a, b, G, q, bf, Ur, flag, min(iters, 255), val);
+}
+
+// Inversion of every interior cell; RED = 1 also folds the reduction
+// diagnostics of the final state into part[] (the reductions pass fused into
+// the last inversion of a step).
+template <int MK, int GUESS, int RED>
+__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks,
+                                             const float *__restrict__ mlp_mu,
+                                             double *__restrict__ part)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  double val[NPART];
+#pragma unroll
+  for (int q = 0; q < NPART; ++q) val[q] = 0.0;
+  if (e < b.n[0] * b.n[1] * b.n[2]) c2p_cell<MK, GUESS, RED>(a, b, e, mlp_mu, val);
+  if constexpr (RED != 0) block_diag_store(val, part);
 }
 
 template <int MK>
@@ -626,95 +784,11 @@ __global__ __launch_bounds__(256) void k_p2c(KArgs a, const int2 *__restrict__ c
   q.B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
   q.B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
   q.B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
-  cons_store<MK>(a, c, G, q);
+  double Uo[5];
+  cons_store<MK>(a, c, G, q, Uo);
 }
 
 // -------------------------------------------------------------- reductions
-
-constexpr int NPART = 13;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax, guess fallback
-
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-template <int MK>
-__global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict__ chunks,
-                                                double *__restrict__ part)
-{
-  __shared__ double sh[4][NPART];
-  const int2 ch = chunks[blockIdx.x];
-  const BlockInfo b = a.blocks[ch.x];
-  const int e = ch.y + threadIdx.x;
-  double val[NPART];
-#pragma unroll
-  for (int q = 0; q < NPART; ++q) val[q] = 0.0;
-  const bool live = e < b.n[0] * b.n[1] * b.n[2];
-  if (live) {
-    const int ng = a.ng;
-    const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
-    const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
-    const long long c = b.off + i + sj * j + sk * k;
-    const long long n = a.nct;
-    const Geo G = geo_center<MK>(a, b, i, j);
-    const double isg = 1.0 / G.sqrtg;
-    Prim q;
-    q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
-    q.ie = a.P[4 * n + c];
-    const double b1l = a.Bf[c], b1h = a.Bf[c + 1];
-    const double b2l = a.Bf[n + c], b2h = a.Bf[n + c + sj];
-    const double b3l = a.Bf[2 * n + c], b3h = a.Bf[2 * n + c + sk];
-    q.B1 = 0.5 * (b1l + b1h) * isg; q.B2 = 0.5 * (b2l + b2h) * isg; q.B3 = 0.5 * (b3l + b3h) * isg;
-    const Aux A = aux_of(G, a.eos.gam, q);
-    double s = 0.0, lm, lp;
-    if (a.active[0]) { speeds_of<0>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[0]; }
-    if (a.active[1]) { speeds_of<1>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[1]; }
-    if (a.active[2]) { speeds_of<2>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[2]; }
-    val[0] = s;
-    val[1] = fabs((b1h - b1l) / b.dx[0] + (b2h - b2l) / b.dx[1] + (b3h - b3l) / b.dx[2]);
-    val[2] = fmax(fmax(fmax(fabs(b1l), fabs(b1h)), fmax(fabs(b2l), fabs(b2h))),
-                  fmax(fabs(b3l), fabs(b3h)));
-    const double dV = b.dx[0] * b.dx[1] * b.dx[2];
-#pragma unroll
-    for (int v = 0; v < 5; ++v) val[3 + v] = a.U[v * n + c] * dV;
-    const int fl = a.flags[c];
-    val[8] = (fl & 8) ? 1.0 : 0.0;
-    val[9] = (fl & 7) ? 1.0 : 0.0;
-    val[10] = (double)a.iters[c];
-    val[12] = (fl & 16) ? 1.0 : 0.0;
-  }
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double itmax = wave_max(val[10]);
-#pragma unroll
-  for (int q = 0; q < 3; ++q) val[q] = wave_max(val[q]);
-#pragma unroll
-  for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
-  val[11] = itmax;
-  val[12] = wave_sum(val[12]);
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double o[NPART];
-#pragma unroll
-    for (int q = 0; q < NPART; ++q) o[q] = sh[0][q];
-    for (int w = 1; w < 4; ++w) {
-      for (int q = 0; q < 3; ++q) o[q] = fmax(o[q], sh[w][q]);
-      for (int q = 3; q < NPART; ++q) o[q] += sh[w][q];
-    }
-    for (int q = 0; q < NPART; ++q) part[(long long)blockIdx.x * NPART + q] = o[q];
-  }
-}
 
 // One workgroup folds the per-workgroup partials in a fixed order.
 // res: dt, divb_rel, divb_max, tot[5], nfail, nfloor, itsum, wavemax_sum, bmax, smax
@@ -792,10 +866,13 @@ __global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
   __syncthreads();
   mlp_wave(m, X, H1, H2, out, lane);
   if (live) {
-    // mu = 1/(hW) <= 1 always: a guess above 1 (y1 slightly negative near
-    // h W = 1) is clamped; only a non-finite or non-positive one is rejected
+    // mu = 1/(hW) <= 1 always: a guess above 1 (log hW output slightly
+    // negative near h W = 1) is clamped; a non-finite or non-positive one is
+    // marked -1.  The network's own W rides along for the consistency check
+    // of the inversion kernel.
     const float mu = fminf(expf(-out[lane * 2 + 1]), 1.0f);
     mu_out[c] = (mu > 0.0f) ? mu : -1.0f;
+    mu_out[a.nct + c] = expf(out[lane * 2]);
   }
 }
 

@@ -27,3 +27,28 @@ def test_graph_replays_equal_eager():
         assert np.array_equal(a, b)
         assert np.array_equal(eager.download("Bf"), graph.download("Bf"))
         assert ra["dt"] == rb["dt"]
+
+
+def test_fused_reductions_equal_separate_pass():
+    """The C-level step folds the reductions into its last inversion; the dt
+    it leaves on the device equals the separate reduction pass's (same
+    per-cell arithmetic), so steps driven by it match steps driven by the
+    host-side dt."""
+    from paper_2410_09146_amd import grmhd as G
+    prob = I.torus(n=(32, 32, 16))
+    fused = G.Pack(prob)
+    host = G.Pack(prob)
+    for p in (fused, host):
+        p.init()
+    fused.reductions(sync=False)
+    for s in range(3):
+        dt = host.reductions()["dt"]
+        host.step(dt)
+        fused.step_c(None, cfl=prob.cfl)
+        a, b = fused.download("P"), host.download("P")
+        say("fused-reduction step", s, "dt", dt, "max |dP|", np.abs(a - b).max())
+        assert np.allclose(a, b, rtol=1e-13, atol=0.0)
+    rf, rh = fused.reductions(), host.reductions()
+    assert rf["dt"] == pytest.approx(rh["dt"], rel=1e-14)
+    for key in ("c2p_fail", "floor_hits"):
+        assert rf[key] == rh[key], key
