@@ -166,7 +166,7 @@ int grmhd_stage(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *e
  * 1/(hW)), starting from guess (COLD: mu = 1/sqrt(1 + r^2); PREV: from the
  * current P; MLP: the learned initial guess bound by grmhd_mlp_bind, used
  * where the W it implies through the master function agrees with the
- * network's own W output to 50 %, else PREV and flag GUESS_FALLBACK).
+ * network's own W output to 50 %, else COLD and flag GUESS_FALLBACK).
  * A failed inversion keeps the previous P.  Where a floor or the failure
  * acts, the hydro part of U is rewritten from the final P (Sec. 3.1
  * inversion, Sec. 3.2 floors).

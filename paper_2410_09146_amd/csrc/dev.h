@@ -62,7 +62,7 @@ template <> struct Lim<float> {
 
 template <typename T>
 struct GeoT {
-  T alpha, beta1;               // lapse, shift (x1 component only)
+  T alpha, ialpha, beta1;       // lapse, its inverse, shift (x1 component only)
   T g11, g13, g22, g33;         // gamma_ij
   T gi11, gi13, gi22, gi33;     // gamma^ij
   T sqrtg;                      // sqrt(gamma)
@@ -73,7 +73,7 @@ template <typename T = double>
 __device__ __forceinline__ GeoT<T> geo_mink()
 {
   GeoT<T> G;
-  G.alpha = T(1); G.beta1 = T(0);
+  G.alpha = T(1); G.ialpha = T(1); G.beta1 = T(0);
   G.g11 = T(1); G.g13 = T(0); G.g22 = T(1); G.g33 = T(1);
   G.gi11 = T(1); G.gi13 = T(0); G.gi22 = T(1); G.gi33 = T(1);
   G.sqrtg = T(1);
@@ -95,14 +95,20 @@ __device__ __forceinline__ GeoT<T> geo_ks(T r, T s, T c, T M, T a)
   const T opz = T(1) + z;
   const T sq = sqrt(opz);
   GeoT<T> G;
-  G.alpha = T(1) / sq;
-  const T ir = T(1) / r;
+  // 1/r, 1/sqrt(1+z) and 1/((1+z) sin^2) from one division (sin^2 = 0 only
+  // on pole faces, whose fluxes are zero and never evaluated)
+  const T s2q = s2 > T(0) ? s2 : T(1);
+  const T osq = opz * s2q;
+  const T Q = T(1) / (r * sq * osq);
+  const T ir = Q * sq * osq;
+  G.alpha = Q * r * osq;
+  G.ialpha = sq;
   G.beta1 = z * G.alpha * G.alpha * ir;
   G.g11 = r * r * opz;
   G.g13 = -a * opz * s2 * r;
   G.g22 = Sig;
   G.g33 = s2 * fma(a2 * opz, s2, Sig);
-  const T idet = iSig * ir * ir / (opz * s2);
+  const T idet = iSig * ir * ir * (Q * r * sq);
   G.gi11 = G.g33 * idet;
   G.gi13 = -G.g13 * idet;
   G.gi33 = G.g11 * idet;
@@ -140,6 +146,7 @@ using Prim = PrimT<double>;
 template <typename T>
 struct AuxT {
   T W, ut2, v1, v2, v3, vl1, vl2, vl3, Bv;
+  T iW, iW1;              // 1 / W, 1 / (W + 1)
   T uc1, uc2, uc3;        // u^i (contravariant four-velocity)
   T b0, bc1, bc2, bc3;    // b^mu
   T bl1, bl2, bl3;        // b_i
@@ -154,7 +161,11 @@ __device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T
   A.ut2 = G.g11 * q.u1 * q.u1 + T(2) * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
           G.g33 * q.u3 * q.u3;
   A.W = sqrt(T(1) + A.ut2);
-  const T iW = T(1) / A.W;
+  // 1/W and 1/(W + 1) from one division
+  const T iWW1 = T(1) / (A.W * (A.W + T(1)));
+  const T iW = (A.W + T(1)) * iWW1;
+  A.iW = iW;
+  A.iW1 = A.W * iWW1;
   A.v1 = q.u1 * iW; A.v2 = q.u2 * iW; A.v3 = q.u3 * iW;
   A.vl1 = G.g11 * A.v1 + G.g13 * A.v3;
   A.vl2 = G.g22 * A.v2;
@@ -164,7 +175,7 @@ __device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T
   const T Bl2 = G.g22 * q.B2;
   const T Bl3 = G.g13 * q.B1 + G.g33 * q.B3;
   const T BB = q.B1 * Bl1 + q.B2 * Bl2 + q.B3 * Bl3;
-  const T ia = T(1) / G.alpha;
+  const T ia = G.ialpha;
   // u^i = W v^i - W beta^i / alpha;  b^i = B^i / W + (alpha b^0 / W) u^i,
   // alpha b^0 = W (B . v)
   A.uc1 = q.u1 - A.W * G.beta1 * ia;
@@ -198,7 +209,7 @@ __device__ __forceinline__ void cons_of(const GeoT<T> &G, const PrimT<T> &q, con
   U[2] = wt * W2 * A.vl2 - ab0 * A.bl2;
   U[3] = wt * W2 * A.vl3 - ab0 * A.bl3;
   // tau with the rest-mass part rho (W^2 - W) = D ut2 / (W + 1)
-  U[4] = D * A.ut2 / (A.W + T(1)) + (q.ie + A.p + A.b2) * W2 - (A.p + T(0.5) * A.b2) - ab0 * ab0;
+  U[4] = D * A.ut2 * A.iW1 + (q.ie + A.p + A.b2) * W2 - (A.p + T(0.5) * A.b2) - ab0 * ab0;
   U[5] = q.B1; U[6] = q.B2; U[7] = q.B3;
 }
 
@@ -207,13 +218,13 @@ template <int DIR, typename T>
 __device__ __forceinline__ void flux_of(const GeoT<T> &G, const PrimT<T> &q, const AuxT<T> &A,
                                         const T U[8], T F[8])
 {
-  const T ia = T(1) / G.alpha;
+  const T ia = G.ialpha;
   const T vt1 = G.alpha * A.v1 - G.beta1, vt2 = G.alpha * A.v2, vt3 = G.alpha * A.v3;
   const T vtd = DIR == 0 ? vt1 : (DIR == 1 ? vt2 : vt3);
   const T vd = DIR == 0 ? A.v1 : (DIR == 1 ? A.v2 : A.v3);
   const T Bd = DIR == 0 ? q.B1 : (DIR == 1 ? q.B2 : q.B3);
   const T pt = A.p + T(0.5) * A.b2;
-  const T iW = T(1) / A.W;
+  const T iW = A.iW;
   const T adv = vtd * ia;
   F[0] = U[0] * adv;
   F[1] = U[1] * adv - A.bl1 * Bd * iW + (DIR == 0 ? pt : T(0));
@@ -231,18 +242,22 @@ template <int DIR, typename T>
 __device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T> &A, T &lm, T &lp)
 {
   // c^2 = cs^2 + ca^2 - cs^2 ca^2 = 1 - (1 - cs^2)(1 - ca^2), with
-  // cs^2 = gam p / w and ca^2 = b^2 / (w + b^2), is (gam p + b^2) / (w + b^2)
-  const T c2 = (gam * A.p + A.b2) / (A.w + A.b2);
-  const T ia2 = T(1) / (G.alpha * G.alpha);
-  const T u0 = A.W / G.alpha;
+  // cs^2 = gam p / w and ca^2 = b^2 / (w + b^2), is N / Dn with
+  // N = gam p + b^2, Dn = w + b^2.  The roots of the quadratic do not change
+  // when all three coefficients are multiplied by Dn > 0, so c^2 enters as
+  // (1 - c^2) Dn = Dn - N and c^2 Dn = N, with no division.
+  const T Nc = gam * A.p + A.b2;
+  const T omc = (A.w + A.b2) - Nc;
+  const T ia = G.ialpha;
+  const T ia2 = ia * ia;
+  const T u0 = A.W * ia;
   const T ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
   const T g00 = -ia2;
   const T g0d = DIR == 0 ? G.beta1 * ia2 : T(0);
   const T gdd = DIR == 0 ? G.gi11 - G.beta1 * G.beta1 * ia2 : (DIR == 1 ? G.gi22 : G.gi33);
-  const T omc = T(1) - c2;
-  const T qa = omc * u0 * u0 - c2 * g00;
-  const T qb = T(-2) * (omc * u0 * ud - c2 * g0d);
-  const T qc = omc * ud * ud - c2 * gdd;
+  const T qa = omc * u0 * u0 - Nc * g00;
+  const T qb = T(-2) * (omc * u0 * ud - Nc * g0d);
+  const T qc = omc * ud * ud - Nc * gdd;
   T disc = qb * qb - T(4) * qa * qc;
   disc = disc > T(0) ? disc : T(0);
   const T sq = sqrt(disc);
@@ -553,8 +568,8 @@ __device__ __forceinline__ void ks_sources(double r, double s, double cth, const
 __device__ __forceinline__ Sym4 tmunu(const Geo &G, const Aux &A)
 {
   const double wt = A.w + A.b2, pt = A.p + 0.5 * A.b2;
-  const double ia2 = 1.0 / (G.alpha * G.alpha);
-  const double u0 = A.W / G.alpha;
+  const double ia2 = G.ialpha * G.ialpha;
+  const double u0 = A.W * G.ialpha;
   const double gi00 = -ia2, gi01 = G.beta1 * ia2, gi11 = G.gi11 - G.beta1 * G.beta1 * ia2;
   Sym4 T;
   T.t00 = wt * u0 * u0 + pt * gi00 - A.b0 * A.b0;

@@ -244,7 +244,7 @@ template <typename T>
 __device__ __forceinline__ GeoT<T> geo_cast(const Geo &G)
 {
   GeoT<T> g;
-  g.alpha = T(G.alpha); g.beta1 = T(G.beta1);
+  g.alpha = T(G.alpha); g.ialpha = T(G.ialpha); g.beta1 = T(G.beta1);
   g.g11 = T(G.g11); g.g13 = T(G.g13); g.g22 = T(G.g22); g.g33 = T(G.g33);
   g.gi11 = T(G.gi11); g.gi13 = T(G.gi13); g.gi22 = T(G.gi22); g.gi33 = T(G.gi33);
   g.sqrtg = T(G.sqrtg);
@@ -291,14 +291,18 @@ __device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
 template <int MK, int D, int RECON, int FV, int RS, typename T, int SH>
-__global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
 {
   constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NS = TD + 5, NR = TD + 1;
   __shared__ T stg[NV * TA * NS];
-  __shared__ T sfl[NV * TA * NR];
-  __shared__ T sfr[NV * TA * NR];
+  __shared__ T sfr[NV * TA * NR];     // right-face states of cells org[D]-1 .. org[D]+TD-1
   constexpr int AX = (D == 0) ? 1 : 0;
   const int tid = threadIdx.x;
+  // this thread's face (and cell) within the tile
+  int fd, aa;
+  if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
+  else                  { aa = tid % TA; fd = tid / TA; }
 
   // persistent: the grid strides over the tile work-list (every thread of a
   // workgroup runs the same number of iterations, so the barriers match)
@@ -308,49 +312,59 @@ __global__ __launch_bounds__(256) void k_flux(KArgs a, const int4 *__restrict__ 
     const int org[3] = {t.y, t.z, t.w};
     const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
 
-    // stage P and the transverse cell-centred field: cells org[D]-3 .. org[D]+TD+1
-    for (int it = tid; it < NV * TA * NS; it += 256) {
-      int s, aa, v;
-      if constexpr (D == 0) { s = it % NS; aa = (it / NS) % TA; v = it / (NS * TA); }
-      else                  { aa = it % TA; s = (it / TA) % NS; v = it / (TA * NS); }
+    // stage P and the transverse cell-centred field of cells org[D]-3 ..
+    // org[D]+TD+1: one (column, cell) position per thread and pass, all seven
+    // variables from one address computation
+    for (int p = tid; p < TA * NS; p += 256) {
+      int s, pa;
+      if constexpr (D == 0) { s = p % NS; pa = p / NS; }
+      else                  { pa = p % TA; s = p / TA; }
       int idx[3] = {org[0], org[1], org[2]};
       idx[D] = min(max(org[D] - 3 + s, 0), b.s[D] - 1);
-      idx[AX] = min(org[AX] + aa, b.s[AX] - 1);
+      idx[AX] = min(org[AX] + pa, b.s[AX] - 1);
       const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-      double val;
-      if (v < 5) val = a.P[v * a.nct + c];
-      else val = a.Bcc[tcomp<D>(v - 5) * a.nct + c];
-      stg[(v * TA + aa) * NS + s] = T(val);
+      T *dst = &stg[pa * NS + s];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) dst[v * TA * NS] = T(a.P[v * a.nct + c]);
+      dst[5 * TA * NS] = T(a.Bcc[tcomp<D>(0) * a.nct + c]);
+      dst[6 * TA * NS] = T(a.Bcc[tcomp<D>(1) * a.nct + c]);
     }
     __syncthreads();
 
-    // reconstruct every (variable, column, cell) of cells org[D]-1 .. org[D]+TD-1
-    for (int it = tid; it < NV * TA * NR; it += 256) {
-      const int cc = it % NR, aa = (it / NR) % TA, v = it / (NR * TA);
-      const T *f = &stg[(v * TA + aa) * NS + cc];
+    // reconstruct: each thread its own cell org[D]+fd (all seven variables),
+    // keeping the left-face state for its face and publishing the right-face
+    // state; the cells org[D]-1 of the TA columns come after (right face only)
+    T qR[7];
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+      const T *f = &stg[(v * TA + aa) * NS + fd + 1];
       T l, r;
       recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
       positivity(v, f[2], l, r);
-      sfl[it] = l;
-      sfr[it] = r;
+      sfr[(v * TA + aa) * NR + fd + 1] = r;
+#pragma unroll
+      for (int w = 0; w < 7; ++w)
+        if (w == v) qR[w] = l;
+    }
+    for (int it = tid; it < NV * TA; it += 256) {
+      const int v = it / TA, ca = it % TA;
+      const T *f = &stg[(v * TA + ca) * NS];
+      T l, r;
+      recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
+      positivity(v, f[2], l, r);
+      sfr[(v * TA + ca) * NR] = r;
     }
     __syncthreads();
 
-    int fd, aa;
-    if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
-    else                  { aa = tid % TA; fd = tid / TA; }
     int idx[3] = {org[0], org[1], org[2]};
     idx[D] = org[D] + fd;
     idx[AX] = org[AX] + aa;
     const bool live = idx[D] < a.ng + b.n[D] && idx[AX] <= a.ng + b.n[AX] && idx[AX] < b.s[AX];
     if (live) {
       const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-      T qL[7], qR[7];
+      T qL[7];
 #pragma unroll
-      for (int v = 0; v < 7; ++v) {
-        qL[v] = sfr[(v * TA + aa) * NR + fd];        // right face of cell idx[D]-1
-        qR[v] = sfl[(v * TA + aa) * NR + fd + 1];    // left face of cell idx[D]
-      }
+      for (int v = 0; v < 7; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];   // cell idx[D]-1
       face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
     }
     __syncthreads();   // LDS is restaged by the next tile
@@ -668,14 +682,14 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
       ok = false;
     } else {
       double mu;
-      if constexpr (GUESS == 0) {
-        mu = 1.0 / sqrt(1.0 + m.r2);
-      } else {
+      if constexpr (GUESS == 1) {
         const Aux Ap = aux_of(G, gam, prev);
         mu = 1.0 / ((1.0 + gam * prev.ie / prev.rho) * Ap.W);
+      } else {
+        mu = 1.0 / sqrt(1.0 + m.r2);             // cold guess: no prior state
         if constexpr (GUESS == 2) {
           // learned guess, kept if its W(mu0) agrees with the network's own
-          // W output to 50 % (out-of-distribution check); else previous P
+          // W output to 50 % (out-of-distribution check); else the cold guess
           const double g = (double)mlp_mu[c];
           bool take = g > 0.0 && g <= 1.0;
           if (take) {
