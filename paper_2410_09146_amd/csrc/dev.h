@@ -60,6 +60,30 @@ template <> struct Lim<float> {
   static constexpr float rmax = 1e15f;
 };
 
+// 1/d for finite d != 0: the hardware reciprocal estimate refined by two
+// Newton-Raphson steps r <- r + r (1 - d r), each squaring the relative error
+// (within an ulp or two of the rounded quotient; not for zero, infinite or
+// subnormal d).
+__device__ __forceinline__ double rcp_nr(double d)
+{
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/x in arithmetic T: FP64 through rcp_nr (x finite, normal, nonzero);
+// FP32 through the hardware division; the operation counter sees a division.
+template <typename T>
+__device__ __forceinline__ T inv(T x)
+{
+#ifndef GRMHD_OPCOUNT
+  if constexpr (sizeof(T) == sizeof(double)) return rcp_nr(x);
+#endif
+  return T(1) / x;
+}
+
 template <typename T>
 struct GeoT {
   T alpha, ialpha, beta1;       // lapse, its inverse, shift (x1 component only)
@@ -90,7 +114,7 @@ __device__ __forceinline__ GeoT<T> geo_ks(T r, T s, T c, T M, T a)
 {
   const T a2 = a * a, s2 = s * s;
   const T Sig = fma(a2 * c, c, r * r);
-  const T iSig = T(1) / Sig;
+  const T iSig = inv(Sig);
   const T z = T(2) * M * r * iSig;
   const T opz = T(1) + z;
   const T sq = sqrt(opz);
@@ -99,7 +123,7 @@ __device__ __forceinline__ GeoT<T> geo_ks(T r, T s, T c, T M, T a)
   // on pole faces, whose fluxes are zero and never evaluated)
   const T s2q = s2 > T(0) ? s2 : T(1);
   const T osq = opz * s2q;
-  const T Q = T(1) / (r * sq * osq);
+  const T Q = inv(r * sq * osq);
   const T ir = Q * sq * osq;
   G.alpha = Q * r * osq;
   G.ialpha = sq;
@@ -162,7 +186,7 @@ __device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T
           G.g33 * q.u3 * q.u3;
   A.W = sqrt(T(1) + A.ut2);
   // 1/W and 1/(W + 1) from one division
-  const T iWW1 = T(1) / (A.W * (A.W + T(1)));
+  const T iWW1 = inv(A.W * (A.W + T(1)));
   const T iW = (A.W + T(1)) * iWW1;
   A.iW = iW;
   A.iW1 = A.W * iWW1;
@@ -261,7 +285,7 @@ __device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T>
   T disc = qb * qb - T(4) * qa * qc;
   disc = disc > T(0) ? disc : T(0);
   const T sq = sqrt(disc);
-  const T i2a = T(0.5) / qa;
+  const T i2a = T(0.5) * inv(qa);
   const T l1 = (-qb + sq) * i2a, l2 = (-qb - sq) * i2a;
   lp = fmax(l1, l2);
   lm = fmin(l1, l2);
@@ -412,8 +436,8 @@ __device__ __forceinline__ bool weno_pair(double f0, double f1, double f2, doubl
   const double ar0 = g0 * E0 * Q12, ar1 = g1 * E1 * Q02, ar2 = g2 * E2 * Q01;
   const double al0 = g0 * E2 * Q01, al1 = g1 * E1 * Q02, al2 = g2 * E0 * Q12;
   const double Sr = ar0 + ar1 + ar2, Sl = al0 + al1 + al2;
-  if (!(Sr > 0.0 && Sr <= 1.7e308 && Sl > 0.0 && Sl <= 1.7e308)) return false;
-  const double ir = 1.0 / Sr, il = 1.0 / Sl;
+  if (!(Sr > 1e-300 && Sr <= 1e300 && Sl > 1e-300 && Sl <= 1e300)) return false;
+  const double ir = rcp_nr(Sr), il = rcp_nr(Sl);
   const double wr0 = ar0 * ir, wr1 = ar1 * ir, wr2 = ar2 * ir;
   const double wl0 = al0 * il, wl1 = al1 * il, wl2 = al2 * il;
   double pr0, pr1, pr2, pl0, pl1, pl2;
@@ -436,7 +460,8 @@ __device__ __forceinline__ bool weno_pair(double f0, double f1, double f2, doubl
   pl = wl0 * pl0 + wl1 * pl1 + wl2 * pl2;
   const double Nr = 3.0 * wr0 * wr1 * wr2, Dr = g2 * wr0 * wr1 + g1 * wr0 * wr2 + g0 * wr1 * wr2;
   const double Nl = 3.0 * wl0 * wl1 * wl2, Dl = g2 * wl0 * wl1 + g1 * wl0 * wl2 + g0 * wl1 * wl2;
-  sigma = 2.0 * Nr * Nl / (Nr * Dl + Nl * Dr);
+  const double den = Nr * Dl + Nl * Dr;
+  sigma = den > 1e-300 ? 2.0 * Nr * Nl * rcp_nr(den) : 0.0;
   return true;
 }
 

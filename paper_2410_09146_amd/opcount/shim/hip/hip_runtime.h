@@ -37,5 +37,7 @@ inline cd fmin(cd a, cd b) { ++g_ops.cmp; return cd(std::fmin(a.v, b.v)); }
 inline cd fmax(cd a, cd b) { ++g_ops.cmp; return cd(std::fmax(a.v, b.v)); }
 inline cd fma(cd a, cd b, cd c) { ++g_ops.fma; return cd(std::fma(a.v, b.v, c.v)); }
 inline bool isfinite(cd a) { return std::isfinite(a.v); }
+// the hardware reciprocal estimate counts as the division it stands for
+inline cd __builtin_amdgcn_rcp(cd a) { ++g_ops.div; return cd(1.0 / a.v); }
 
 #define double cd
