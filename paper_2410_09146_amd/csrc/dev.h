@@ -617,7 +617,7 @@ struct C2P { double q, r2, b2, rb, gam, v2max; };
 // Master function f(mu) = mu - 1/(h/W + mu rbar^2) and its derivative.
 __device__ __forceinline__ double master(const C2P &m, double mu, double &df)
 {
-  const double x = 1.0 / (1.0 + mu * m.b2);
+  const double x = inv(1.0 + mu * m.b2);
   const double dx = -m.b2 * x * x;
   const double rb2 = m.rb * m.rb;
   const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * rb2;
@@ -627,16 +627,16 @@ __device__ __forceinline__ double master(const C2P &m, double mu, double &df)
   const double dqbar = -K * (mu * x * x + mu * mu * x * dx);
   double v2 = mu * mu * rbar2, dv2 = 2.0 * mu * rbar2 + mu * mu * drbar2;
   if (v2 > m.v2max) { v2 = m.v2max; dv2 = 0.0; }
-  const double W = 1.0 / sqrt(1.0 - v2);
+  const double iW = sqrt(1.0 - v2);
+  const double W = inv(iW);
   const double dW = 0.5 * W * W * W * dv2;
-  double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
+  double eps = W * (qbar - mu * rbar2) + v2 * W * W * inv(1.0 + W);
   double deps = dW * (1.0 + qbar - mu * rbar2) + W * (dqbar - rbar2 - mu * drbar2);
   if (eps < 0.0) { eps = 0.0; deps = 0.0; }
   const double hh = 1.0 + m.gam * eps, dh = m.gam * deps;
-  const double iW = 1.0 / W;
   const double nu = hh * iW, dnu = dh * iW - hh * dW * iW * iW;
   const double den = nu + mu * rbar2;
-  const double iden = 1.0 / den;
+  const double iden = inv(den);
   df = 1.0 + (dnu + rbar2 + mu * drbar2) * iden * iden;
   return mu - iden;
 }

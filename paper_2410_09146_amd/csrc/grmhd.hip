@@ -13,6 +13,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 #include <vector>
 
@@ -244,18 +245,18 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   // entry w of the list is taken from position (w % 8) * ceil(n/8) + w / 8 of
   // the natural (spatially ordered) list; each XCD then sweeps one contiguous
   // eighth of the tiles and reuses the stencil halos in its own L2.
-  for (int D = 0; D < 3; ++D)
-    for (int sh = 0; sh < NSHAPE; ++sh) {
-      std::vector<int4> &L = p.tiles[D][sh];
-      const size_t n = L.size(), q = (n + 7) / 8;
-      std::vector<int4> out;
-      out.reserve(n);
-      for (size_t w = 0; w < 8 * q; ++w) {
-        const size_t src = (w % 8) * q + w / 8;
-        if (src < n) out.push_back(L[src]);
-      }
-      L.swap(out);
+  auto xcd_order = [](auto &L) {
+    const size_t n = L.size(), q = (n + 7) / 8;
+    std::remove_reference_t<decltype(L)> out;
+    out.reserve(n);
+    for (size_t w = 0; w < 8 * q; ++w) {
+      const size_t src = (w % 8) * q + w / 8;
+      if (src < n) out.push_back(L[src]);
     }
+    L.swap(out);
+  };
+  for (int D = 0; D < 3; ++D)
+    for (int sh = 0; sh < NSHAPE; ++sh) xcd_order(p.tiles[D][sh]);
   for (int b = 0; b < p.nb; ++b) {
     const BlockInfo &bi = p.blocks[b];
     for (int D = 0; D < 3; ++D) {
@@ -270,6 +271,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     const long long nbc = (long long)(bi.s[0] - 1) * (bi.s[1] - 1) * (bi.s[2] - 1);
     for (long long s = 0; s < nbc; s += 256) p.ch_bcc.push_back(make_int2(b, (int)s));
   }
+
 
   // ghost maps.  Per axis at level l: global index -> (source global index,
   // flags); returns 0 interior, 1 mapped, -1 fixed (leave).

@@ -640,7 +640,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   const long long c = b.off + i + sj * j + sk * k;
   const long long n = a.nct;
   const Geo G = geo_center<MK>(a, b, i, j);
-  const double isg = 1.0 / G.sqrtg;
+  const double isg = inv(G.sqrtg);
   double Ur[5], Ud[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -664,7 +664,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
 #pragma unroll
   for (int v = 0; v < 5; ++v) ok = ok && isfinite(Ud[v]);
   if (ok) {
-    const double D = Ud[0], iD = 1.0 / D;
+    const double D = Ud[0], iD = inv(D);
     // S^i = gamma^ij S_j ; B_i = gamma_ij B^j
     const double Su1 = G.gi11 * Ud[1] + G.gi13 * Ud[3];
     const double Su2 = G.gi22 * Ud[2];
@@ -675,7 +675,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
     m.q = Ud[4] * iD;
     m.r2 = (Ud[1] * Su1 + Ud[2] * Su2 + Ud[3] * Su3) * iD * iD;
     m.b2 = (Bl1 * B1 + Bl2 * B2 + Bl3 * B3) * iD;
-    const double isD = 1.0 / sqrt(D);
+    const double isD = inv(sqrt(D));
     m.rb = (Ud[1] * B1 + Ud[2] * B2 + Ud[3] * B3) * iD * isD;
     m.v2max = m.r2 / (1.0 + m.r2);
     if (master_f(m, 1.0) < 0.0) {
@@ -718,15 +718,16 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
         mu = mn;
         if (dmu <= tol * mu) break;
       }
-      const double x = 1.0 / (1.0 + mu * m.b2);
+      const double x = inv(1.0 + mu * m.b2);
       const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * m.rb * m.rb;
       const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * (m.b2 * m.r2 - m.rb * m.rb);
       double v2 = mu * mu * rbar2;
       v2 = v2 > m.v2max ? m.v2max : v2;
-      const double W = 1.0 / sqrt(1.0 - v2);
-      double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
+      const double iW = sqrt(1.0 - v2);
+      const double W = inv(iW);
+      double eps = W * (qbar - mu * rbar2) + v2 * W * W * inv(1.0 + W);
       eps = eps < 0.0 ? 0.0 : eps;
-      q.rho = D / W;
+      q.rho = D * iW;
       q.ie = q.rho * eps;
       const double f1 = mu * x * W, f2 = mu * m.rb * isD;
       q.u1 = f1 * (Su1 * iD + f2 * B1);
