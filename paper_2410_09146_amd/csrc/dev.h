@@ -498,6 +498,12 @@ __device__ __forceinline__ T mp5_face(T fm2, T fm1, T f0, T fp1, T fp2)
   return f5 + minmod_slope(lo - f5, hi - f5);     // median(f5, lo, hi)
 }
 
+// WENO5-Z-AOAH without the per-face fallback: false (and nothing) where the
+// shared-divisor pair cannot be normalised (then recon5 must be used); every
+// other reconstruction is complete here.
+template <int RECON, int FV, typename T>
+__device__ __forceinline__ bool recon5_fast(T f0, T f1, T f2, T f3, T f4, T &fl, T &fr);
+
 // Left (j-1/2) and right (j+1/2) face values of cell j.
 template <int RECON, int FV, typename T>
 __device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &fr)
@@ -531,6 +537,25 @@ __device__ __forceinline__ void recon5(T f0, T f1, T f2, T f3, T f4, T &fl, T &f
     fr = sigma * pr + (T(1) - sigma) * (f2 + T(0.5) * s);
     fl = sigma * pl + (T(1) - sigma) * (f2 - T(0.5) * s);
   }
+}
+
+template <int RECON, int FV, typename T>
+__device__ __forceinline__ bool recon5_fast(T f0, T f1, T f2, T f3, T f4, T &fl, T &fr)
+{
+#ifndef GRMHD_OPCOUNT
+  if constexpr (RECON == RC_WENO && sizeof(T) == sizeof(double)) {
+    T pr, pl, sigma;
+    if (!weno_pair<FV>(f0, f1, f2, f3, f4, pl, pr, sigma)) return false;
+    const T s = mc_slope(f2 - f1, f3 - f2);
+    sigma = sigma > T(0) ? sigma : T(0);                     // also maps NaN to 0
+    sigma = sigma < T(1) ? sigma : T(1);
+    fr = sigma * pr + (T(1) - sigma) * (f2 + T(0.5) * s);
+    fl = sigma * pl + (T(1) - sigma) * (f2 - T(0.5) * s);
+    return true;
+  }
+#endif
+  recon5<RECON, FV, T>(f0, f1, f2, f3, f4, fl, fr);
+  return true;
 }
 
 // --------------------------------------------------------- sources (KS)

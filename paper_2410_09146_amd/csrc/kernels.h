@@ -335,16 +335,28 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
     // keeping the left-face state for its face and publishing the right-face
     // state; the cells org[D]-1 of the TA columns come after (right face only)
     T qR[7];
-#pragma unroll 1
+    bool redo = false;
+#pragma unroll
     for (int v = 0; v < NV; ++v) {
       const T *f = &stg[(v * TA + aa) * NS + fd + 1];
       T l, r;
-      recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
+      redo |= !recon5_fast<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
       positivity(v, f[2], l, r);
       sfr[(v * TA + aa) * NR + fd + 1] = r;
+      qR[v] = l;
+    }
+    if (redo) {           // rare: a WENO pair that could not be normalised
+#pragma unroll 1
+      for (int v = 0; v < NV; ++v) {
+        const T *f = &stg[(v * TA + aa) * NS + fd + 1];
+        T l, r;
+        recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
+        positivity(v, f[2], l, r);
+        sfr[(v * TA + aa) * NR + fd + 1] = r;
 #pragma unroll
-      for (int w = 0; w < 7; ++w)
-        if (w == v) qR[w] = l;
+        for (int w = 0; w < 7; ++w)
+          if (w == v) qR[w] = l;
+      }
     }
     for (int it = tid; it < NV * TA; it += 256) {
       const int v = it / TA, ca = it % TA;
