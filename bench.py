@@ -32,6 +32,11 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--persist", type=int, default=0,
                     help="persistent flux grid size in workgroups (0: one per tile)")
+    ap.add_argument("--workload", default="torus128",
+                    choices=["torus128", "amr640", "mixed192", "fp64_192"],
+                    help="torus128: the headline line (default); amr640: the torus at 256^3 "
+                         "effective on ~640 two-level blocks; mixed192 / fp64_192: the torus "
+                         "at 192^3 in 27 blocks of 64^3, mixed precision / FP64")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -80,6 +85,85 @@ def flux_faces(n):
     return n * (n + 2) * (n + 2)
 
 
+def timed_steps(torch, pack, cfl, steps, warmup):
+    """(ms eager, ms graph, per-family profile, reductions) of `steps` C-level
+    steps after `warmup`, HIP events on the pack's stream."""
+    for _ in range(warmup):
+        pack.step_c(None, cfl=cfl)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    pack.profile(True)
+    torch.cuda.synchronize()
+    e0.record(pack.stream)
+    for _ in range(steps):
+        pack.step_c(None, cfl=cfl)
+    e1.record(pack.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = pack.profile_read()
+    pack.profile(False)
+    red = pack.reductions()
+    pack.step_graph(0)
+    torch.cuda.synchronize()
+    e0.record(pack.stream)
+    pack.step_graph(steps)
+    e1.record(pack.stream)
+    torch.cuda.synchronize()
+    return ms, e0.elapsed_time(e1), prof, red
+
+
+def growth_workload(args, torch, G, I):
+    """One JSON line for a growth configuration (not the headline line)."""
+    import numpy as np
+    if args.workload == "amr640":
+        fine = I.torus(n=(256, 256, 256))
+        lev, nx, ll = I.amr_layout(fine, target=640, node=32, smallest=16)
+        root = I.coarse_problem(fine)
+        Ps, Bs = I.mesh_blocks(fine, lev, nx, ll)
+        del fine
+        pack = G.Pack(root, layout=(nx, ll, lev))
+        pack.init_blocks(Ps, Bs)
+        del Ps, Bs
+        desc = (f"two-level torus, 256^3 effective (level 0 = 128^3, level 1 where rho > 1e-2 "
+                f"rho_max): {len(lev)} blocks ({int(sum(lev))} at level 1) of 16^3/32^3/64^3, "
+                "FP64, WENO5-Z-AOAH + LLF")
+        cfl, prec = root.cfl, "f64"
+    else:
+        prob = I.torus(n=(192, 192, 192))
+        mixed = args.workload == "mixed192"
+        pack = G.Pack(prob, nblk=(3, 3, 3), precision=G.PREC_MIXED if mixed else G.PREC_FP64)
+        pack.init()
+        desc = ("torus 192^3 in 27 blocks of 64^3, WENO5-Z-AOAH + LLF, " +
+                ("mixed precision (FP32 staging, reconstruction, Riemann; FP64 state, "
+                 "densitization, RK, inversion)" if mixed else "FP64"))
+        cfl, prec = prob.cfl, "f32/f64" if mixed else "f64"
+    nx = pack.nx
+    ncell = int((nx[:, 0] * nx[:, 1] * nx[:, 2]).sum())
+    pack.reductions(sync=False)
+    tiles, _ = pack.autotune(reps=2)
+    pack.set_persistent(2048)
+    ms, ms_graph, prof, red = timed_steps(torch, pack, cfl, args.steps, args.warmup)
+    faces = int(sum(nx[:, 0] * (nx[:, 1] + 2) * (nx[:, 2] + 2)))      # per direction (cubes)
+    opc = json.load(open(os.path.join(ROOT, "paper_2410_09146_amd", "opcount", "opcount.json")))
+    fams = ("flux_x1", "flux_x2", "flux_x3")
+    avg = sum(prof[f][0] for f in fams) / sum(prof[f][1] for f in fams)
+    out = {"metric": "zone-cycles/s, GRMHD RK2 step (growth configuration)",
+           "value": round(ncell * args.steps / (ms * 1e-3), 1), "unit": "zone-cycles/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(ms / args.steps, 4), "higher_is_better": True,
+           "dtype": prec, "data": "synthetic",
+           "config": {"workload": desc, "cells": ncell, "blocks": int(len(nx))},
+           "graph_replay": {"ms_per_step": round(ms_graph / args.steps, 4),
+                            "value": round(ncell * args.steps / (ms_graph * 1e-3), 1)},
+           "k_flux": {"avg_launch_ms": round(avg, 4), "faces_per_launch": faces,
+                      "algorithmic_TFLOPs": round(opc["per_face_flux_ks_weno_llf"] * faces / (avg * 1e-3) / 1e12, 3)},
+           "kernels": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+           "tiling": tiles,
+           "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -96,6 +180,9 @@ def main():
     import torch
     from paper_2410_09146_amd import grmhd as G
     from paper_2410_09146_amd import inputs as I
+
+    if args.workload != "torus128":
+        return growth_workload(args, torch, G, I)
 
     n = args.n
     prob = I.torus(n=(n, n, n))
