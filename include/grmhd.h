@@ -78,9 +78,11 @@ typedef struct {
  * blocks with even sizes and offsets.  Ghost zones between levels are filled
  * by restriction (cell means of 8 children, face means of 4 child faces) and
  * prolongation (parent plus monotonized-central limited slopes; faces constant
- * across a coarse face and linear along its normal); no flux or EMF correction
- * at level boundaries (paper Sec. 1 and 3 use Parthenon's block-structured
- * refinement).  bc[6] = boundary kind at (x1 lo, x1 hi, x2 lo, x2 hi, x3 lo,
+ * across a coarse face and linear along its normal); a face between cells of
+ * different levels belongs to the finer side.  Each stage replaces the coarse
+ * hydro fluxes and edge EMFs on level boundaries by the means of the fine
+ * ones, so the totals are conserved and the field through an interface is
+ * one (paper Sec. 1 and 3 use Parthenon's block-structured refinement).  bc[6] = boundary kind at (x1 lo, x1 hi, x2 lo, x2 hi, x3 lo,
  * x3 hi).  ng must be 4.
  * recon: GRMHD_RECON_* (Sec. 3.1 list: constant, linear with minmod or MC,
  *        mp5 of Suresh & Huynh 1997, WENO5-Z-AOAH of App. B).

@@ -293,13 +293,14 @@ class Mesh:
     per-block padded arrays (nvar, s3, s2, s1) with the interiors set.
     One global dt, no flux or EMF correction at level boundaries."""
 
-    def __init__(self, root, level, nx, lloc, P_blocks, Bf_blocks, nthreads=1):
+    def __init__(self, root, level, nx, lloc, P_blocks, Bf_blocks, nthreads=1, correct=True):
         self.root = root
         self.level = np.asarray(level, dtype=np.int32)
         self.nx = np.asarray(nx, dtype=np.int32).reshape(-1, 3)
         self.lloc = np.asarray(lloc, dtype=np.int32).reshape(-1, 3)
         self.nb = len(self.level)
         self.nthreads = nthreads
+        self.correct = correct
         self.cfl = root.cfl
         self.blocks = []
         for b in range(self.nb):
@@ -322,6 +323,20 @@ class Mesh:
         self.fill_ghosts()
         self.U = [blk.prim_to_cons(P, Bf) for blk, P, Bf in zip(self.blocks, self.P, self.Bf)]
         self.t = 0.0
+
+    def _desc(self):
+        d = _MeshDesc()
+        d.nb, d.ng = self.nb, self.root.ng
+        for k in range(3):
+            d.root_nx[k] = self.root.n[k]
+        for s in range(6):
+            d.bc[s] = self.root.bc[s]
+        self._keep = (np.ascontiguousarray(self.level, dtype=np.int32),
+                      np.ascontiguousarray(self.nx.ravel(), dtype=np.int32),
+                      np.ascontiguousarray(self.lloc.ravel(), dtype=np.int32))
+        ip = ctypes.POINTER(ctypes.c_int)
+        d.level, d.nx, d.lloc = (a.ctypes.data_as(ip) for a in self._keep)
+        return d
 
     def fill_ghosts(self, P=None, Bf=None):
         P = self.P if P is None else P
@@ -366,10 +381,32 @@ class Mesh:
         return self.reductions()["dt"]
 
     def stage(self, dt, rk, U0, Bf0):
-        nfail = 0
+        """Fluxes and EMFs of every block, their correction at level
+        boundaries (orc_mesh_correct), then each block's update."""
+        L = lib()
+        F = [np.zeros((3, 8) + blk.shape) for blk in self.blocks]
+        E = [np.zeros((3,) + blk.shape) for blk in self.blocks]
         for b, blk in enumerate(self.blocks):
-            self.U[b], self.Bf[b] = blk.stage(self.P[b], self.Bf[b], U0[b], Bf0[b], self.U[b],
-                                              dt, rk, self.nthreads)
+            if L.orc_fluxes_emfs(ctypes.byref(blk.grid), ctypes.byref(blk.metric),
+                                 ctypes.byref(blk.eos), _ptr(self.P[b]), _ptr(self.Bf[b]),
+                                 _ptr(F[b]), _ptr(E[b]), ctypes.c_int(self.nthreads)) != 0:
+                raise RuntimeError("orc_fluxes_emfs failed")
+        if self.correct:
+            d = self._desc()
+            fp = (_P * self.nb)(*[_ptr(a) for a in F])
+            ep = (_P * self.nb)(*[_ptr(a) for a in E])
+            self.corrected = L.orc_mesh_correct(ctypes.byref(d), fp, ep)
+        rkc = (ctypes.c_double * 3)(*rk)
+        for b, blk in enumerate(self.blocks):
+            Uo, Bo = np.zeros_like(self.U[b]), np.zeros_like(self.Bf[b])
+            if L.orc_stage_from(ctypes.byref(blk.grid), ctypes.byref(blk.metric),
+                                ctypes.byref(blk.eos), _ptr(self.P[b]), _ptr(self.Bf[b]),
+                                _ptr(U0[b]), _ptr(Bf0[b]), _ptr(self.U[b]), ctypes.c_double(dt),
+                                rkc, _ptr(F[b]), _ptr(E[b]), _ptr(Uo), _ptr(Bo),
+                                ctypes.c_int(self.nthreads)) != 0:
+                raise RuntimeError("orc_stage_from failed")
+            self.U[b], self.Bf[b] = Uo, Bo
+        nfail = 0
         for b, blk in enumerate(self.blocks):
             nfail += blk.con2prim(self.U[b], self.Bf[b], self.P[b], self.nthreads)[1]
         self.fill_ghosts()

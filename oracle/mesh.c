@@ -32,7 +32,11 @@
  *     periodic wrap, outflow copy with inflow velocity zeroed, polar mirror
  *     with the sign of the x2 velocity (and of the x2 face field) flipped.
  *   - A face belongs to the cell on its upper side (the cell below at the
- *     upper domain edge).
+ *     upper domain edge), except that where the two cells beside it lie on
+ *     different levels the finer one owns it.
+ *   - Each stage couples the levels conservatively (orc_mesh_correct): coarse
+ *     hydro fluxes and EMFs on level boundaries are replaced by the means of
+ *     the fine ones.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -178,9 +182,24 @@ static int face_view(const ctx_t *c, int l, int cmp, const int Fin[3], double *v
   int F[3], flip[3], ofl[3];
   for (int d = 0; d < 3; ++d)
     if (bmap(m, l, d, Fin[d], d == cmp, &F[d], &flip[d], &ofl[d]) < 0) return -1;
+  /* owner: the cell above the face (below at the upper domain edge); where
+     the two cells beside the face lie on different levels, the finer one */
+  const int N = lvl_n(m, l, cmp);
   int Co[3] = {F[0], F[1], F[2]};
-  if (Co[cmp] == lvl_n(m, l, cmp)) Co[cmp] -= 1;
-  const int ob = owner(c, l, Co), lo = m->level[ob];
+  if (Co[cmp] == N) Co[cmp] -= 1;
+  int ob = owner(c, l, Co);
+  {
+    int Ca[3] = {F[0], F[1], F[2]}, alt = -1;
+    const int per = m->bc[2 * cmp] == ORC_BC_PERIODIC;
+    if (F[cmp] > 0 && F[cmp] < N) { Ca[cmp] = F[cmp] - 1; alt = F[cmp]; }
+    else if (F[cmp] == N && per) { Ca[cmp] = 0; alt = 0; }
+    else if (F[cmp] == 0 && per) { Ca[cmp] = N - 1; alt = N; }
+    if (alt >= 0) {
+      const int oa = owner(c, l, Ca);
+      if (m->level[oa] > m->level[ob]) { ob = oa; F[cmp] = alt; }
+    }
+  }
+  const int lo = m->level[ob];
   double val;
   if (lo == l) {
     int loc[3];
@@ -275,4 +294,151 @@ int orc_mesh_fill_ghosts(const orc_mesh *m, double **P, double **Bf)
   }
   free(c.own);
   return 0;
+}
+
+/*
+ * Conservative coupling of the two levels for one stage (the framework's
+ * flux correction and its constrained-transport counterpart, reading of the
+ * refinement the paper builds on).  F[b]: face fluxes [3][8][ncell] and E[b]:
+ * edge EMFs [3][ncell] of every block (orc_fluxes_emfs).  For each level-0
+ * block:
+ *   - a face on its boundary whose other side is a level-1 block takes, for
+ *     the five hydro fluxes, the mean of the 4 child faces' fluxes of that
+ *     block (the fine fluxes are authoritative);
+ *   - an edge of its own that coincides with an edge of a level-1 block (two
+ *     fine edges) takes the mean of the two fine EMFs; the first such fine
+ *     block in block order supplies them.
+ * Periodic boundaries are followed; other physical boundaries have no
+ * neighbour.  Returns the number of corrected faces + edges.
+ */
+static int wrap_axis(const orc_mesh *m, int l, int d, int g, int *out)
+{
+  const int N = lvl_n(m, l, d);
+  if (g >= 0 && g < N) { *out = g; return 1; }
+  if (m->bc[2 * d] != ORC_BC_PERIODIC) return 0;
+  *out = ((g % N) + N) % N;
+  return 1;
+}
+
+/* does fine block f own the fine edge along e at cell ie, face indices (jf, kf)
+   along (e+1)%3, (e+2)%3?  On success sets the local indices. */
+static int owns_edge(const orc_mesh *m, int f, int e, int ie, int jf, int kf, int loc[3])
+{
+  const int a = (e + 1) % 3, b = (e + 2) % 3;
+  const int *ll = &m->lloc[3 * f], *nx = &m->nx[3 * f];
+  int cand[3][3], nc[3] = {0, 0, 0};
+  const int want[3] = {ie, jf, kf}, ax[3] = {e, a, b};
+  for (int q = 0; q < 3; ++q) {
+    const int d = ax[q], N = lvl_n(m, 1, d);
+    cand[q][nc[q]++] = want[q];
+    if (m->bc[2 * d] == ORC_BC_PERIODIC) {
+      if (q > 0 && want[q] == 0) cand[q][nc[q]++] = N;     /* face N is face 0 */
+      if (q > 0 && want[q] == N) cand[q][nc[q]++] = 0;
+    }
+  }
+  for (int x = 0; x < nc[0]; ++x)
+    for (int y = 0; y < nc[1]; ++y)
+      for (int z = 0; z < nc[2]; ++z) {
+        const int v[3] = {cand[0][x], cand[1][y], cand[2][z]};
+        int ok = 1, L[3];
+        for (int q = 0; q < 3; ++q) {
+          const int d = ax[q];
+          const int lo = ll[d], hi = ll[d] + nx[d] - (q == 0 ? 1 : 0);
+          if (v[q] < lo || v[q] > hi) ok = 0;
+          L[d] = v[q] - ll[d] + m->ng;
+        }
+        if (ok) { loc[0] = L[0]; loc[1] = L[1]; loc[2] = L[2]; return 1; }
+      }
+  return 0;
+}
+
+int orc_mesh_correct(const orc_mesh *m, double **F, double **E)
+{
+  const size_t nroot = (size_t)m->root_nx[0] * m->root_nx[1] * m->root_nx[2];
+  int *own = malloc(nroot * sizeof(int));
+  for (size_t q = 0; q < nroot; ++q) own[q] = -1;
+  for (int b = 0; b < m->nb; ++b) {
+    const int l = m->level[b];
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = m->lloc[3 * b + d] >> l;
+      hi[d] = (m->lloc[3 * b + d] + m->nx[3 * b + d]) >> l;
+    }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x)
+          own[x + (size_t)m->root_nx[0] * (y + (size_t)m->root_nx[1] * z)] = b;
+  }
+  const int ng = m->ng;
+  int count = 0;
+  for (int c = 0; c < m->nb; ++c) {
+    if (m->level[c] != 0) continue;
+    const int *ll = &m->lloc[3 * c], *nx = &m->nx[3 * c];
+    const size_t ncC = blk_ncell(m, c);
+    /* faces on the block boundary */
+    for (int d = 0; d < 3; ++d) {
+      const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+      for (int side = 0; side < 2; ++side) {
+        const int fl = side ? ng + nx[d] : ng;             /* local face index */
+        const int other = side ? ll[d] + nx[d] : ll[d] - 1; /* level-0 cell across */
+        int oc;
+        if (!wrap_axis(m, 0, d, other, &oc)) continue;
+        for (int u2 = 0; u2 < nx[t2]; ++u2)
+          for (int u1 = 0; u1 < nx[t1]; ++u1) {
+            int C0[3];
+            C0[d] = oc; C0[t1] = ll[t1] + u1; C0[t2] = ll[t2] + u2;
+            const int f = own[C0[0] + (size_t)m->root_nx[0] * (C0[1] + (size_t)m->root_nx[1] * C0[2])];
+            if (m->level[f] != 1) continue;
+            /* the interface plane seen from the fine block: its face across */
+            int X[3];
+            X[d] = side ? 2 * oc : 2 * (oc + 1);
+            X[t1] = 2 * C0[t1]; X[t2] = 2 * C0[t2];
+            int Lf[3];
+            for (int q = 0; q < 3; ++q) Lf[q] = X[q] - m->lloc[3 * f + q] + ng;
+            const size_t ncF = blk_ncell(m, f);
+            const int s0 = m->nx[3 * f] + 2 * ng, s1 = m->nx[3 * f + 1] + 2 * ng;
+            const size_t str[3] = {1, (size_t)s0, (size_t)s0 * s1};
+            const size_t src = blk_idx(m, f, Lf);
+            int Lc[3];
+            Lc[d] = fl; Lc[t1] = ng + u1; Lc[t2] = ng + u2;
+            const size_t dst = blk_idx(m, c, Lc);
+            for (int v = 0; v < 5; ++v) {
+              const double *Ff = F[f] + ((size_t)d * 8 + v) * ncF;
+              double acc = 0.0;
+              for (int bb = 0; bb < 2; ++bb)
+                for (int aa = 0; aa < 2; ++aa) acc += Ff[src + aa * str[t1] + bb * str[t2]];
+              F[c][((size_t)d * 8 + v) * ncC + dst] = 0.25 * acc;
+            }
+            ++count;
+          }
+      }
+    }
+    /* own edges on the block surface */
+    for (int e = 0; e < 3; ++e) {
+      const int a = (e + 1) % 3, bx = (e + 2) % 3;
+      for (int kb = 0; kb <= nx[bx]; ++kb)
+        for (int ka = 0; ka <= nx[a]; ++ka) {
+          if (!(ka == 0 || ka == nx[a] || kb == 0 || kb == nx[bx])) continue;
+          for (int ie = 0; ie < nx[e]; ++ie) {
+            /* (complex.h owns the name I) */
+            const int fe = 2 * (ll[e] + ie), fa = 2 * (ll[a] + ka), fb = 2 * (ll[bx] + kb);
+            int f = -1, loc[3];
+            for (int q = 0; q < m->nb && f < 0; ++q)
+              if (m->level[q] == 1 && owns_edge(m, q, e, fe, fa, fb, loc)) f = q;
+            if (f < 0) continue;
+            const int s0 = m->nx[3 * f] + 2 * ng, s1 = m->nx[3 * f + 1] + 2 * ng;
+            const size_t str[3] = {1, (size_t)s0, (size_t)s0 * s1};
+            const size_t ncF = blk_ncell(m, f);
+            const size_t sa = blk_idx(m, f, loc);
+            const double *Ef = E[f] + (size_t)e * ncF;
+            int Lc[3];
+            Lc[e] = ng + ie; Lc[a] = ng + ka; Lc[bx] = ng + kb;
+            E[c][(size_t)e * ncC + blk_idx(m, c, Lc)] = 0.5 * (Ef[sa] + Ef[sa + str[e]]);
+            ++count;
+          }
+        }
+    }
+  }
+  free(own);
+  return count;
 }

@@ -252,39 +252,86 @@ static void face_fluxes(const orc_grid *g, const orc_metric *m, const orc_eos *e
  * Outputs Uout/Bfout (complete copies of U/Bf with updated entries).
  * flux_out (optional) receives F[3][8][ncell].
  */
+/* Face fluxes F[3][8][ncell] and edge EMFs E[3][ncell] of the state (P, Bf):
+   E1 at (i, j-1/2, k-1/2), E2 at (i-1/2, j, k-1/2), E3 at (i-1/2, j-1/2, k)
+   for every (i, j, k) in the box [ng, ng+n] (four-point averages of the
+   induction fluxes).  Both arrays are zeroed first. */
+static void emfs_from_fluxes(const orc_grid *g, const double *F, double *E);
+
+int orc_fluxes_emfs(const orc_grid *g, const orc_metric *m, const orc_eos *e,
+                    const double *P, const double *Bf, double *F, double *E, int nthreads)
+{
+  const size_t nc = ncell(g);
+  double *Bcc = malloc(3 * nc * sizeof(double));
+  if (!Bcc) return -1;
+  memset(F, 0, 24 * nc * sizeof(double));
+  orc_cell_B(g, m, Bf, Bcc);
+  for (int d = 0; d < 3; ++d) face_fluxes(g, m, e, P, Bf, Bcc, d, F + (size_t)d * 8 * nc, nthreads);
+  emfs_from_fluxes(g, F, E);
+  free(Bcc);
+  return 0;
+}
+
+static void emfs_from_fluxes(const orc_grid *g, const double *F, double *E)
+{
+  const size_t nc = ncell(g);
+  const int ng = g->ng;
+  const double *F1 = F, *F2 = F + 8 * nc, *F3 = F + 16 * nc;
+  memset(E, 0, 3 * nc * sizeof(double));
+#define FL(Fd, v, i, j, k) (Fd)[(size_t)(v) * nc + IDX(g, i, j, k)]
+  for (int k = ng; k <= ng + g->n[2]; ++k)
+    for (int j = ng; j <= ng + g->n[1]; ++j)
+      for (int i = ng; i <= ng + g->n[0]; ++i) {
+        const size_t c = IDX(g, i, j, k);
+        E[0 * nc + c] = 0.25 * (FL(F2, 7, i, j, k) + FL(F2, 7, i, j, k - 1)
+                              - FL(F3, 6, i, j, k) - FL(F3, 6, i, j - 1, k));
+        E[1 * nc + c] = 0.25 * (FL(F3, 5, i, j, k) + FL(F3, 5, i - 1, j, k)
+                              - FL(F1, 7, i, j, k) - FL(F1, 7, i, j, k - 1));
+        E[2 * nc + c] = 0.25 * (FL(F1, 6, i, j, k) + FL(F1, 6, i, j - 1, k)
+                              - FL(F2, 5, i, j, k) - FL(F2, 5, i - 1, j, k));
+      }
+#undef FL
+}
+
+/*
+ * One stage from given face fluxes F and edge EMFs E (as orc_fluxes_emfs
+ * returns them, possibly corrected at level boundaries): the face field by
+ * the discrete curl of E, the hydro state by the flux divergence and the
+ * geometric source of (P, Bf).
+ */
+int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
+                   const double *P, const double *Bf, const double *U0, const double *Bf0,
+                   const double *U, double dt, const double rk[3], const double *F,
+                   const double *E, double *Uout, double *Bfout, int nthreads);
+
 int orc_stage(const orc_grid *g, const orc_metric *m, const orc_eos *e,
               const double *P, const double *Bf, const double *U0, const double *Bf0,
               const double *U, double dt, const double rk[3], double *Uout,
               double *Bfout, double *flux_out, int nthreads)
 {
   const size_t nc = ncell(g);
-  const int ng = g->ng;
-  double *Bcc = malloc(3 * nc * sizeof(double));
   double *F = flux_out ? flux_out : malloc(24 * nc * sizeof(double));
   double *E = malloc(3 * nc * sizeof(double));
-  if (!Bcc || !F || !E) return -1;
-  memset(F, 0, 24 * nc * sizeof(double));
-  memset(E, 0, 3 * nc * sizeof(double));
-  orc_cell_B(g, m, Bf, Bcc);
-  for (int d = 0; d < 3; ++d) face_fluxes(g, m, e, P, Bf, Bcc, d, F + (size_t)d * 8 * nc, nthreads);
+  if (!F || !E) return -1;
+  int r = orc_fluxes_emfs(g, m, e, P, Bf, F, E, nthreads);
+  if (!r) r = orc_stage_from(g, m, e, P, Bf, U0, Bf0, U, dt, rk, F, E, Uout, Bfout, nthreads);
+  free(E);
+  if (!flux_out) free(F);
+  return r;
+}
 
+int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
+                   const double *P, const double *Bf, const double *U0, const double *Bf0,
+                   const double *U, double dt, const double rk[3], const double *F,
+                   const double *E, double *Uout, double *Bfout, int nthreads)
+{
+  const size_t nc = ncell(g);
+  const int ng = g->ng;
+  double *Bcc = malloc(3 * nc * sizeof(double));
+  if (!Bcc) return -1;
+  orc_cell_B(g, m, Bf, Bcc);
   const double *F1 = F, *F2 = F + 8 * nc, *F3 = F + 16 * nc;
 #define FL(Fd, v, i, j, k) (Fd)[(size_t)(v) * nc + IDX(g, i, j, k)]
-  /* edge EMFs over the box [ng, ng+n] in every direction */
-  for (int k = ng; k <= ng + g->n[2]; ++k)
-    for (int j = ng; j <= ng + g->n[1]; ++j)
-      for (int i = ng; i <= ng + g->n[0]; ++i) {
-        const size_t c = IDX(g, i, j, k);
-        /* E1 at (i, j-1/2, k-1/2) */
-        E[0 * nc + c] = 0.25 * (FL(F2, 7, i, j, k) + FL(F2, 7, i, j, k - 1)
-                              - FL(F3, 6, i, j, k) - FL(F3, 6, i, j - 1, k));
-        /* E2 at (i-1/2, j, k-1/2) */
-        E[1 * nc + c] = 0.25 * (FL(F3, 5, i, j, k) + FL(F3, 5, i - 1, j, k)
-                              - FL(F1, 7, i, j, k) - FL(F1, 7, i, j, k - 1));
-        /* E3 at (i-1/2, j-1/2, k) */
-        E[2 * nc + c] = 0.25 * (FL(F1, 6, i, j, k) + FL(F1, 6, i, j - 1, k)
-                              - FL(F2, 5, i, j, k) - FL(F2, 5, i - 1, j, k));
-      }
 #define EE(a, i, j, k) E[(size_t)(a) * nc + IDX(g, i, j, k)]
 
   memcpy(Uout, U, 5 * nc * sizeof(double));
@@ -354,8 +401,6 @@ int orc_stage(const orc_grid *g, const orc_metric *m, const orc_eos *e,
 #undef FL
 #undef EE
   free(Bcc);
-  free(E);
-  if (!flux_out) free(F);
   return 0;
 }
 

@@ -46,12 +46,14 @@ struct Plan {
   std::vector<GhostBR> gBR;
   std::vector<GhostBPro> gBPro;
   long long nsP = 0, nsB = 0;      // staged coarse-view cells / faces
+  std::vector<FixF> fixF;          // level-boundary corrections (two-level meshes)
+  std::vector<FixE> fixE;
   int maxlev = 0;
   int active[3] = {1, 1, 1};
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes, o_chi, o_che,
-      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_part, o_res, o_mlp,
+      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res, o_mlp,
       o_mlpw, o_mlpf, total;
   size_t o_tl[3][NSHAPE];
 };
@@ -303,10 +305,25 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     return sb.off + lin;
   };
   // owner of a level-l face (the cell above it, or below at the upper edge)
-  auto face_owner = [&](int l, int comp, const int F[3]) -> int {
+  // owner of a level-l face: the cell above it (below at the upper domain
+  // edge); where the two cells beside the face lie on different levels, the
+  // finer one, whose frame may then name the face N instead of 0 (or 0
+  // instead of N) across a periodic boundary
+  auto face_owner = [&](int l, int comp, int F[3]) -> int {
+    const int N = d->root_nx[comp] << l;
     int C[3] = {F[0], F[1], F[2]};
-    C[comp] = std::min(C[comp], (d->root_nx[comp] << l) - 1);
-    return own.at(l, C);
+    C[comp] = std::min(C[comp], N - 1);
+    int ob = own.at(l, C);
+    int A[3] = {F[0], F[1], F[2]}, alt = -1;
+    const bool per = d->bc[2 * comp] == GRMHD_BC_PERIODIC;
+    if (F[comp] > 0 && F[comp] < N) { A[comp] = F[comp] - 1; alt = F[comp]; }
+    else if (F[comp] == N && per) { A[comp] = 0; alt = 0; }
+    else if (F[comp] == 0 && per) { A[comp] = N - 1; alt = N; }
+    if (alt >= 0) {
+      const int oa = own.at(l, A);
+      if (lev_of(oa) > lev_of(ob)) { ob = oa; F[comp] = alt; }
+    }
+    return ob;
   };
   // staged level-0 views: cells keyed by (mapped index, flags), faces by
   // (component, index)
@@ -352,12 +369,13 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     r.src = lin_in(ob, X); r.n = 4; r.st1 = str[t1]; r.st2 = str[t2];
   };
   // staging row of level-0 face Q (inside the domain)
-  auto stage_face = [&](int comp, const int Q[3]) -> int {
-    const long long key = key3(0, Q) * 3 + comp;
+  auto stage_face = [&](int comp, const int Qin[3]) -> int {
+    const long long key = key3(0, Qin) * 3 + comp;
     auto it = stB.find(key);
     if (it != stB.end()) return it->second;
     const int idx = (int)p.nsB++;
     stB.emplace(key, idx);
+    int Q[3] = {Qin[0], Qin[1], Qin[2]};
     const int ob = face_owner(0, comp, Q);
     GhostBR r{};
     r.dst = idx; r.comp = comp; r.flip = 0; r.tgt = 1;
@@ -447,6 +465,107 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     }
   }
 
+  // level-boundary corrections of every level-0 block (the fine fluxes and
+  // EMFs are authoritative): faces whose other side is a level-1 block, and
+  // own edges that coincide with two edges of a level-1 block (the first such
+  // block in block order)
+  if (p.maxlev > 0) {
+    auto wrap0 = [&](int dd, int g, int &out) -> bool {
+      const int N = d->root_nx[dd];
+      if (g >= 0 && g < N) { out = g; return true; }
+      if (d->bc[2 * dd] != GRMHD_BC_PERIODIC) return false;
+      out = ((g % N) + N) % N;
+      return true;
+    };
+    auto str_of = [&](int b, int dd) -> long long {
+      return dd == 0 ? 1 : dd == 1 ? (long long)p.blocks[b].s[0]
+                                   : (long long)p.blocks[b].s[0] * p.blocks[b].s[1];
+    };
+    // does fine block f own the fine edge along e at cell fe, faces (fa, fb)?
+    // (periodic faces N and 0 are the same face)
+    auto owns_edge = [&](int f, int e, const int want[3], int X[3]) -> bool {
+      const int ax[3] = {e, (e + 1) % 3, (e + 2) % 3};
+      int cand[3][2], nc[3];
+      for (int q = 0; q < 3; ++q) {
+        const int dd = ax[q], N = d->root_nx[dd] << 1;
+        nc[q] = 1;
+        cand[q][0] = want[q];
+        if (q > 0 && d->bc[2 * dd] == GRMHD_BC_PERIODIC) {
+          if (want[q] == 0) cand[q][nc[q]++] = N;
+          else if (want[q] == N) cand[q][nc[q]++] = 0;
+        }
+      }
+      for (int x = 0; x < nc[0]; ++x)
+        for (int y = 0; y < nc[1]; ++y)
+          for (int z = 0; z < nc[2]; ++z) {
+            const int v[3] = {cand[0][x], cand[1][y], cand[2][z]};
+            bool ok = true;
+            for (int q = 0; q < 3; ++q) {
+              const int dd = ax[q], lo = d->lloc[3 * f + dd];
+              const int hi = lo + d->nx[3 * f + dd] - (q == 0 ? 1 : 0);
+              if (v[q] < lo || v[q] > hi) ok = false;
+              X[dd] = v[q];
+            }
+            if (ok) return true;
+          }
+      return false;
+    };
+    for (int c = 0; c < p.nb; ++c) {
+      if (lev_of(c) != 0) continue;
+      const int *llc = &d->lloc[3 * c], *nxc = &d->nx[3 * c];
+      for (int D = 0; D < 3; ++D) {
+        const int t1 = (D + 1) % 3, t2 = (D + 2) % 3;
+        for (int side = 0; side < 2; ++side) {
+          int oc;
+          if (!wrap0(D, side ? llc[D] + nxc[D] : llc[D] - 1, oc)) continue;
+          for (int u2 = 0; u2 < nxc[t2]; ++u2)
+            for (int u1 = 0; u1 < nxc[t1]; ++u1) {
+              int C0[3];
+              C0[D] = oc; C0[t1] = llc[t1] + u1; C0[t2] = llc[t2] + u2;
+              const int f = own.at(0, C0);
+              if (lev_of(f) != 1) continue;
+              int X[3], G[3];
+              X[D] = side ? 2 * oc : 2 * (oc + 1);
+              X[t1] = 2 * C0[t1]; X[t2] = 2 * C0[t2];
+              G[D] = llc[D] + (side ? nxc[D] : 0); G[t1] = C0[t1]; G[t2] = C0[t2];
+              p.fixF.push_back(FixF{lin_in(c, G), lin_in(f, X), str_of(f, t1), str_of(f, t2), D, 0});
+            }
+        }
+      }
+      for (int e = 0; e < 3; ++e) {
+        const int a = (e + 1) % 3, bx = (e + 2) % 3;
+        for (int kb = 0; kb <= nxc[bx]; ++kb)
+          for (int ka = 0; ka <= nxc[a]; ++ka) {
+            if (!(ka == 0 || ka == nxc[a] || kb == 0 || kb == nxc[bx])) continue;
+            for (int ie = 0; ie < nxc[e]; ++ie) {
+              const int want[3] = {2 * (llc[e] + ie), 2 * (llc[a] + ka), 2 * (llc[bx] + kb)};
+              // candidate fine blocks: owners of the fine cells beside the edge
+              int best = -1, BX[3] = {0, 0, 0};
+              for (int sa = -1; sa <= 0; ++sa)
+                for (int sb = -1; sb <= 0; ++sb) {
+                  int cell[3];
+                  cell[e] = want[0];
+                  const int ca = want[1] + sa, cb = want[2] + sb;
+                  const int Na = d->root_nx[a] << 1, Nb = d->root_nx[bx] << 1;
+                  if ((ca < 0 || ca >= Na) && d->bc[2 * a] != GRMHD_BC_PERIODIC) continue;
+                  if ((cb < 0 || cb >= Nb) && d->bc[2 * bx] != GRMHD_BC_PERIODIC) continue;
+                  cell[a] = ((ca % Na) + Na) % Na;
+                  cell[bx] = ((cb % Nb) + Nb) % Nb;
+                  const int q = own.at(1, cell);
+                  if (lev_of(q) != 1 || (best >= 0 && q >= best)) continue;
+                  int X[3];
+                  if (owns_edge(q, e, want, X)) { best = q; BX[0] = X[0]; BX[1] = X[1]; BX[2] = X[2]; }
+                }
+              if (best < 0) continue;
+              int G[3];
+              G[e] = llc[e] + ie; G[a] = llc[a] + ka; G[bx] = llc[bx] + kb;
+              p.fixE.push_back(FixE{lin_in(c, G), lin_in(best, BX), str_of(best, e), e, 0});
+            }
+          }
+      }
+    }
+  }
+
   // every gather index must stay inside the pack's planes
   for (const GhostP &g : p.gP)
     if (g.dst < 0 || g.dst >= p.nct || g.src < 0 || g.src >= p.nct)
@@ -472,6 +591,12 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
         (g.n != 1 && g.n != 4))
       return fail("internal: face restriction map out of range", GRMHD_E_SHAPE);
   }
+  for (const FixF &f : p.fixF)
+    if (f.dst < 0 || f.dst >= p.nct || f.src < 0 || f.src + f.st1 + f.st2 >= p.nct || f.D < 0 || f.D > 2)
+      return fail("internal: flux correction map out of range", GRMHD_E_SHAPE);
+  for (const FixE &f : p.fixE)
+    if (f.dst < 0 || f.dst >= p.nct || f.src < 0 || f.src + f.st >= p.nct || f.e < 0 || f.e > 2)
+      return fail("internal: EMF correction map out of range", GRMHD_E_SHAPE);
   for (const GhostBPro &g : p.gBPro)
     if (g.dst < 0 || g.dst >= p.nct || g.comp < 0 || g.comp > 2 || g.sa < 0 || g.sa >= p.nsB ||
         g.sb >= p.nsB)
@@ -500,6 +625,9 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_gBPro = take(sizeof(GhostBPro) * p.gBPro.size());
   p.o_SP = take(sizeof(double) * 5 * (size_t)p.nsP);
   p.o_SB = take(sizeof(double) * (size_t)p.nsB);
+  p.o_E = take(p.maxlev > 0 ? sizeof(double) * 3 * (size_t)p.nct : 0);
+  p.o_fixF = take(sizeof(FixF) * p.fixF.size());
+  p.o_fixE = take(sizeof(FixE) * p.fixE.size());
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
   p.o_res = take(sizeof(double) * 32);
   p.o_mlp = take(sizeof(float) * 2 * (size_t)p.nct);   // learned mu0 and W per cell
@@ -556,6 +684,7 @@ struct grmhd_pack {
     a.SP = (double *)(ws + plan.o_SP);
     a.SB = (double *)(ws + plan.o_SB);
     a.nsp = plan.nsP;
+    a.E = (double *)(ws + plan.o_E);
     return a;
   }
 };
@@ -792,6 +921,8 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   if (!e) e = up(pl.o_gPro, pl.gPro.data(), sizeof(GhostPro) * pl.gPro.size());
   if (!e) e = up(pl.o_gBR, pl.gBR.data(), sizeof(GhostBR) * pl.gBR.size());
   if (!e) e = up(pl.o_gBPro, pl.gBPro.data(), sizeof(GhostBPro) * pl.gBPro.size());
+  if (!e) e = up(pl.o_fixF, pl.fixF.data(), sizeof(FixF) * pl.fixF.size());
+  if (!e) e = up(pl.o_fixE, pl.fixE.data(), sizeof(FixE) * pl.fixE.size());
   // flags / iteration counters / flux scratch start defined
   if (!e) e = hipMemsetAsync(p->ws + pl.o_flags, 0, 2 * align_up(pl.nct), p->stream);
   if (!e) e = hipMemsetAsync(p->ws + pl.o_F, 0, sizeof(double) * 24 * (size_t)pl.nct, p->stream);
@@ -891,12 +1022,30 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   const double *dtd = dptr<double>(p, pl.o_res);
   const int save = rk[1] == 0.0;
   Prof t(p, GRMHD_PROF_UPDATE);
-  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
-    hipLaunchKernelGGL(k_update<MK_KS>, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
+  const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
+  if (pl.maxlev > 0) {
+    // two levels: the fine fluxes and EMFs replace the coarse ones on level
+    // boundaries (conservation and one interface field), then the update
+    // reads the corrected edge arrays
+    if (!pl.fixF.empty())
+      hipLaunchKernelGGL(k_flux_fix, dim3((pl.fixF.size() + 255) / 256), dim3(256), 0, p->stream,
+                         a, dptr<FixF>(p, pl.o_fixF), (int)pl.fixF.size());
+    hipLaunchKernelGGL(k_emf, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
+                       dptr<int2>(p, pl.o_che));
+    if (!pl.fixE.empty())
+      hipLaunchKernelGGL(k_emf_fix, dim3((pl.fixE.size() + 255) / 256), dim3(256), 0, p->stream,
+                         a, dptr<FixE>(p, pl.o_fixE), (int)pl.fixE.size());
+    if (ks) hipLaunchKernelGGL((k_update<MK_KS, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+    else hipLaunchKernelGGL((k_update<MK_MINK, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  } else if (ks) {
+    hipLaunchKernelGGL((k_update<MK_KS, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
-  else
-    hipLaunchKernelGGL(k_update<MK_MINK>, dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
+  } else {
+    hipLaunchKernelGGL((k_update<MK_MINK, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  }
   LAUNCHCHK(p);
   return GRMHD_OK;
 }

@@ -30,6 +30,7 @@ struct KArgs {
   int active[3];        // directions with more than one cell (CFL sum)
   double *SP, *SB;      // staged coarse-view rows of P [5][nsp] and face B [nsb]
   long long nsp;
+  double *E;            // two-level meshes: edge EMFs [3][nct] (corrected at level boundaries)
 };
 
 struct GhostP { long long dst, src; int flags, pad; };
@@ -47,6 +48,11 @@ struct GhostPro { long long dst; int s[7]; int flags, oct, pad; };
 // (sb < 0) or the mean of two.
 struct GhostBR { long long dst, src, st1, st2; int comp, flip, n, tgt; };
 struct GhostBPro { long long dst; int sa, sb, comp, flip; };
+// Level-boundary corrections of a coarse block: a face along D takes the
+// mean of the 4 fine faces src + {0, st1} + {0, st2} (hydro fluxes); an edge
+// along e the mean of the fine edges src and src + st (EMFs).
+struct FixF { long long dst, src, st1, st2; int D, pad; };
+struct FixE { long long dst, src, st; int e, pad; };
 
 // ------------------------------------------------------------------ ghosts
 
@@ -433,9 +439,57 @@ __global__ __launch_bounds__(64) void k_flux_planes(KArgs a, const int2 *__restr
   else plane_face<MK, 2, RECON, FV, RS, T>(a, b, e);
 }
 
+// ------------------------------------------------- two-level coupling
+
+// Edge EMFs of every cell of the box [ng, ng+n] (the four-point averages the
+// update forms itself on single-level packs).
+__global__ __launch_bounds__(256) void k_emf(KArgs a, const int2 *__restrict__ chunks)
+{
+  const int2 ch = chunks[blockIdx.x];
+  const BlockInfo b = a.blocks[ch.x];
+  const int e = ch.y + threadIdx.x;
+  const int m1 = b.n[0] + 1, m2 = b.n[1] + 1;
+  if (e >= m1 * m2 * (b.n[2] + 1)) return;
+  const int ng = a.ng;
+  const int i = ng + e % m1, j = ng + (e / m1) % m2, k = ng + e / (m1 * m2);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const long long q = b.off + i + sj * j + sk * k;
+  const long long n = a.nct;
+  const double *F0 = a.F, *F1 = a.F + 8 * n, *F2 = a.F + 16 * n;
+  a.E[q] = 0.25 * (F1[7 * n + q] + F1[7 * n + q - sk] - F2[6 * n + q] - F2[6 * n + q - sj]);
+  a.E[n + q] = 0.25 * (F2[5 * n + q] + F2[5 * n + q - 1] - F0[7 * n + q] - F0[7 * n + q - sk]);
+  a.E[2 * n + q] = 0.25 * (F0[6 * n + q] + F0[6 * n + q - sj] - F1[5 * n + q] - F1[5 * n + q - 1]);
+}
+
+// Coarse hydro fluxes on level boundaries <- mean of the 4 fine fluxes.
+__global__ __launch_bounds__(256) void k_flux_fix(KArgs a, const FixF *__restrict__ map, int nfix)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nfix) return;
+  const FixF f = map[e];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const double *p = a.F + (long long)(f.D * 8 + v) * a.nct + f.src;
+    double acc = 0.0;
+    for (int bb = 0; bb < 2; ++bb)
+      for (int aa = 0; aa < 2; ++aa) acc += p[aa * f.st1 + bb * f.st2];
+    a.F[(long long)(f.D * 8 + v) * a.nct + f.dst] = 0.25 * acc;
+  }
+}
+
+// Coarse EMFs on level boundaries <- mean of the 2 fine EMFs.
+__global__ __launch_bounds__(256) void k_emf_fix(KArgs a, const FixE *__restrict__ map, int nfix)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nfix) return;
+  const FixE f = map[e];
+  const double *p = a.E + (long long)f.e * a.nct;
+  a.E[(long long)f.e * a.nct + f.dst] = 0.5 * (p[f.src] + p[f.src + f.st]);
+}
+
 // ------------------------------------------------------------------ update
 
-template <int MK>
+template <int MK, int EARR>
 __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict__ chunks,
                                                 double dt_in, const double *__restrict__ dt_dev,
                                                 double c0, double c1, double cdt, int save_base)
@@ -491,13 +545,18 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
 
   // edge EMFs: E1 = Omega_23 at (i, j-1/2, k-1/2), E2 = Omega_31 at
   // (i-1/2, j, k-1/2), E3 = Omega_12 at (i-1/2, j-1/2, k); four-point averages
+  // (EARR: read from the edge arrays, which two-level meshes correct at level
+  // boundaries before the update)
   auto E1 = [&](long long q) {
+    if constexpr (EARR != 0) return a.E[q];
     return 0.25 * (F1[7 * n + q] + F1[7 * n + q - sk] - F2[6 * n + q] - F2[6 * n + q - sj]);
   };
   auto E2 = [&](long long q) {
+    if constexpr (EARR != 0) return a.E[n + q];
     return 0.25 * (F2[5 * n + q] + F2[5 * n + q - 1] - F0[7 * n + q] - F0[7 * n + q - sk]);
   };
   auto E3 = [&](long long q) {
+    if constexpr (EARR != 0) return a.E[2 * n + q];
     return 0.25 * (F0[6 * n + q] + F0[6 * n + q - sj] - F1[5 * n + q] - F1[5 * n + q - 1]);
   };
   double rb[3];

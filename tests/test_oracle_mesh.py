@@ -153,14 +153,17 @@ def test_ghost_faces_divergence_free():
                             f = [loc[e] + (up if e == c else 0) for e in range(3)]
                             if all(g <= f[e] <= g + n[e] - (0 if e == c else 1) for e in range(3)):
                                 ok = False
-                    for c in range(3):          # owner of each face: the cell above it
+                    for c in range(3):          # level owning each face of the cell
                         for up in (0, 1):
-                            C = [G[e] + (up if e == c else 0) for e in range(3)]
-                            C = [C[e] if (e == c and 0 <= C[e] <= N[e]) else C[e] % N[e]
-                                 for e in range(3)]
-                            C[c] = min(C[c], N[c] - 1)
-                            C0 = [C[e] >> L for e in range(3)]
-                            if own[C0[2], C0[1], C0[0]] == L:
+                            # the two cells beside the face (periodic box): the
+                            # finer one owns it, else the one above
+                            F = [G[e] + (up if e == c else 0) for e in range(3)]
+                            above = [F[e] % N[e] for e in range(3)]
+                            below = list(above)
+                            below[c] = (F[c] - 1) % N[c]
+                            la = own[above[2] >> L, above[1] >> L, above[0] >> L]
+                            lb = own[below[2] >> L, below[1] >> L, below[0] >> L]
+                            if max(la, lb) == L:
                                 ok = False      # a same-level copy: not an inter-level value
                     if not ok:
                         continue
@@ -243,3 +246,78 @@ def test_mesh_reductions_match_single_level():
     assert red["dt"] == pytest.approx(ref["dt"], rel=1e-15)
     assert red["divb_max"] == pytest.approx(ref["divb_max"], rel=1e-12, abs=1e-14)
     assert np.allclose(red["totals"], ref["totals"], rtol=1e-13, atol=1e-15)
+
+
+def _box_two_level(correct):
+    fine = I.random_smooth_box((32, 32, 32), seed=6, amp=0.1)
+    root = I.coarse_problem(fine)
+    ref = {(0, 0, 0), (1, 1, 0), (1, 0, 1)}
+    lev, nx, ll = I.two_level_layout(root.n, 8, lambda lo, s: tuple(x // 8 for x in lo) in ref,
+                                     p_coarse=(0.5,), p_fine=(0.6,), smallest=8, seed=2)
+    Ps, Bs = I.mesh_blocks(fine, lev, nx, ll)
+    return root, lev, oracle.Mesh(root, lev, nx, ll, Ps, Bs, nthreads=4, correct=correct)
+
+
+def test_level_coupling_conserves():
+    """Periodic two-level box: with the coarse fluxes at level boundaries
+    replaced by the mean of the fine ones, the totals of sqrt(gamma) U are
+    conserved to rounding over three steps; without, they are not."""
+    out = {}
+    for corr in (False, True):
+        root, lev, mesh = _box_two_level(corr)
+        t0 = mesh.reductions()["totals"]
+        for _ in range(3):
+            mesh.step()
+        t1 = mesh.reductions()["totals"]
+        out[corr] = np.abs(t1 - t0).max() / np.abs(t0).max()
+    assert out[True] < 1e-14, out
+    assert out[False] > 1e-8, out
+
+
+def test_level_boundary_faces_stay_restrictions():
+    """With the coarse EMFs on level boundaries replaced by the mean of the
+    fine EMFs, every coarse face on a level boundary stays the mean of its 4
+    fine faces (the composite field keeps one divergence-free flux through
+    the interface)."""
+    root, lev, mesh = _box_two_level(True)
+    for _ in range(3):
+        mesh.step()
+    g = root.ng
+    nx, ll = mesh.nx, mesh.lloc
+    N0 = root.n
+    own = np.full(N0[::-1], -1)
+    for b in range(mesh.nb):
+        lo = ll[b] >> lev[b]
+        hi = (ll[b] + nx[b]) >> lev[b]
+        own[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = b
+    worst, count = 0.0, 0
+    scale = max(np.abs(B).max() for B in mesh.Bf)
+    for c in range(mesh.nb):
+        if lev[c] != 0:
+            continue
+        for d in range(3):
+            t1, t2 = (d + 1) % 3, (d + 2) % 3
+            for side in (0, 1):
+                other = (ll[c][d] + nx[c][d]) % N0[d] if side else (ll[c][d] - 1) % N0[d]
+                for u2 in range(nx[c][t2]):
+                    for u1 in range(nx[c][t1]):
+                        C0 = [0, 0, 0]
+                        C0[d], C0[t1], C0[t2] = other, ll[c][t1] + u1, ll[c][t2] + u2
+                        f = own[C0[2], C0[1], C0[0]]
+                        if lev[f] != 1:
+                            continue
+                        Lc = [0, 0, 0]
+                        Lc[d], Lc[t1], Lc[t2] = g + (nx[c][d] if side else 0), g + u1, g + u2
+                        vc = mesh.Bf[c][d][Lc[2], Lc[1], Lc[0]]
+                        X = [0, 0, 0]
+                        X[d] = 2 * other if side else 2 * (other + 1)
+                        vals = []
+                        for a in (0, 1):
+                            for bb in (0, 1):
+                                X[t1], X[t2] = 2 * C0[t1] + a, 2 * C0[t2] + bb
+                                Lf = [X[k] - ll[f][k] + g for k in range(3)]
+                                vals.append(mesh.Bf[f][d][Lf[2], Lf[1], Lf[0]])
+                        worst = max(worst, abs(vc - np.mean(vals)) / scale)
+                        count += 1
+    assert count > 100
+    assert worst < 1e-13, worst
