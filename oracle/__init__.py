@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["metric.c", "physics.c", "recon.c", "c2p.c", "stage.c", "api.c", "mesh.c"]
+SOURCES = ["metric.c", "physics.c", "eos.c", "recon.c", "c2p.c", "stage.c", "api.c", "mesh.c"]
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
           "-std=c11", "-Wall"]
 
@@ -40,10 +40,41 @@ class Metric(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("M", ctypes.c_double), ("a", ctypes.c_double)]
 
 
+class Table(ctypes.Structure):
+    _fields_ = [("data", ctypes.POINTER(ctypes.c_double)), ("n", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
 class Eos(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("rho_flr0", ctypes.c_double),
                 ("rho_flr_pow", ctypes.c_double), ("u_flr0", ctypes.c_double),
-                ("u_flr_pow", ctypes.c_double), ("W_max", ctypes.c_double)]
+                ("u_flr_pow", ctypes.c_double), ("W_max", ctypes.c_double),
+                ("nscalar", ctypes.c_int), ("tab", ctypes.POINTER(Table))]
+
+
+def table_struct(tab):
+    """ctypes view of an inputs.EosTable (keeps a reference to its data)."""
+    data = np.ascontiguousarray(tab.data, dtype=np.float64)
+    t = Table()
+    t.data = data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for d in range(3):
+        t.n[d] = data.shape[2 - d]
+        t.lo[d] = tab.lo[d]
+        t.hi[d] = tab.hi[d]
+    t._keep = data
+    return t
+
+
+def eos_struct(prob):
+    """orc_eos of a problem: ideal gas, or its table (with the Y_e scalar)."""
+    e = Eos(prob.gamma, prob.rho_flr0, prob.rho_flr_pow, prob.u_flr0, prob.u_flr_pow,
+            prob.W_max, int(getattr(prob, "nscalar", 0)), None)
+    tab = getattr(prob, "table", None)
+    if tab is not None:
+        t = table_struct(tab)
+        e.tab = ctypes.pointer(t)
+        e._keep = t
+    return e
 
 
 _lib = None
@@ -56,6 +87,7 @@ def lib():
             build()
         _lib = ctypes.CDLL(LIB_PATH)
         _lib.orc_pt_master.restype = ctypes.c_double
+        _lib.orc_pt_master_tab.restype = ctypes.c_double
     return _lib
 
 
@@ -164,6 +196,65 @@ def weno(f, fv=0):
     return w, s.value
 
 
+# --------------------------------------------------- general EOS point API
+# eos: an Eos structure (eos_struct); primitive vectors of 9 end with Y_e,
+# conserved and flux vectors of 9 end with D Y_e and its flux.
+
+def table_eval(tab_struct, rho, eps, ye):
+    rho, eps, ye = (np.ascontiguousarray(np.broadcast_to(a, np.broadcast(rho, eps, ye).shape),
+                                         dtype=float).ravel() for a in (rho, eps, ye))
+    lnp, g1 = np.zeros_like(rho), np.zeros_like(rho)
+    lib().orc_pt_table(ctypes.byref(tab_struct), ctypes.c_long(rho.size), _ptr(rho), _ptr(eps),
+                       _ptr(ye), _ptr(lnp), _ptr(g1))
+    return lnp, g1
+
+
+def thermo(eos, rho, u, ye):
+    rho, u, ye = (np.ascontiguousarray(np.broadcast_to(a, np.broadcast(rho, u, ye).shape),
+                                       dtype=float).ravel() for a in (rho, u, ye))
+    p, gp = np.zeros_like(rho), np.zeros_like(rho)
+    lib().orc_pt_thermo(ctypes.byref(eos), ctypes.c_long(rho.size), _ptr(rho), _ptr(u), _ptr(ye),
+                        _ptr(p), _ptr(gp))
+    return p, gp
+
+
+def p2c_eos(metric, x, eos, prim9):
+    U = np.zeros(9)
+    lib().orc_pt_p2c_eos(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.byref(eos),
+                         _ptr(np.ascontiguousarray(prim9, dtype=float)), _ptr(U))
+    return U
+
+
+def riemann_eos(metric, x, eos, solver, pl, pr, d):
+    F = np.zeros(9)
+    lib().orc_pt_riemann_eos(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.byref(eos),
+                             ctypes.c_int(solver), _ptr(np.ascontiguousarray(pl, dtype=float)),
+                             _ptr(np.ascontiguousarray(pr, dtype=float)), ctypes.c_int(d), _ptr(F))
+    return F
+
+
+def speeds_eos(metric, x, eos, prim9, d):
+    out = np.zeros(2)
+    lib().orc_pt_speeds_eos(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.byref(eos),
+                            _ptr(np.ascontiguousarray(prim9, dtype=float)), ctypes.c_int(d),
+                            _ptr(out))
+    return out[0], out[1]
+
+
+def c2p_eos(metric, x, eos, Ud6, B):
+    out = np.zeros(9)
+    mu = ctypes.c_double(0.0)
+    r = lib().orc_pt_c2p_eos(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.byref(eos),
+                             _ptr(np.ascontiguousarray(Ud6, dtype=float)),
+                             _ptr(np.asarray(B, float)), _ptr(out), ctypes.byref(mu))
+    return r, out, mu.value
+
+
+def master_tab(tab_struct, D, ye, q, r2, b2, rb, mu):
+    return lib().orc_pt_master_tab(ctypes.byref(tab_struct), *(ctypes.c_double(v) for v in
+                                                                (D, ye, q, r2, b2, rb, mu)))
+
+
 # ----------------------------------------------------------------- block API
 
 class Block:
@@ -184,8 +275,8 @@ class Block:
         g.weno_fv = prob.weno_fv
         self.grid = g
         self.metric = Metric(prob.metric_kind, prob.M, prob.a)
-        self.eos = Eos(prob.gamma, prob.rho_flr0, prob.rho_flr_pow, prob.u_flr0,
-                       prob.u_flr_pow, prob.W_max)
+        self.eos = eos_struct(prob)
+        self.nv = 5 + int(getattr(prob, "nscalar", 0))
         self.shape = prob.shape
 
     def coord(self, loc, i, j, k):
@@ -195,8 +286,8 @@ class Block:
         return x
 
     def fill_ghosts(self, P, Bf):
-        lib().orc_fill_ghosts(ctypes.byref(self.grid), ctypes.byref(self.metric), _ptr(P),
-                              _ptr(Bf))
+        lib().orc_fill_ghosts_n(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                                ctypes.c_int(self.nv), _ptr(P), _ptr(Bf))
 
     def cell_B(self, Bf):
         Bcc = np.zeros((3,) + self.shape)
@@ -206,7 +297,7 @@ class Block:
 
     def prim_to_cons(self, P, Bf, U=None):
         if U is None:
-            U = np.zeros((5,) + self.shape)
+            U = np.zeros((self.nv,) + self.shape)
         lib().orc_prim_to_cons_grid(ctypes.byref(self.grid), ctypes.byref(self.metric),
                                     ctypes.byref(self.eos), _ptr(P), _ptr(Bf), _ptr(U))
         return U
@@ -233,11 +324,12 @@ class Block:
         return flag, nfail
 
     def reductions(self, P, Bf, U, cfl):
-        out = np.zeros(8)
+        out = np.zeros(9)
         lib().orc_reductions(ctypes.byref(self.grid), ctypes.byref(self.metric),
                              ctypes.byref(self.eos), _ptr(P), _ptr(Bf), _ptr(U),
                              ctypes.c_double(cfl), _ptr(out))
-        return {"dt": out[0], "divb_rel": out[1], "divb_max": out[2], "totals": out[3:8].copy()}
+        return {"dt": out[0], "divb_rel": out[1], "divb_max": out[2], "totals": out[3:8].copy(),
+                "total_scalar": out[8]}
 
 
 class Sim:
@@ -294,6 +386,8 @@ class Mesh:
     One global dt, no flux or EMF correction at level boundaries."""
 
     def __init__(self, root, level, nx, lloc, P_blocks, Bf_blocks, nthreads=1, correct=True):
+        if getattr(root, "nscalar", 0):
+            raise NotImplementedError("two-level meshes carry no passive scalar")
         self.root = root
         self.level = np.asarray(level, dtype=np.int32)
         self.nx = np.asarray(nx, dtype=np.int32).reshape(-1, 3)

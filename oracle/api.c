@@ -13,6 +13,16 @@ static void unpack(const double p[8], orc_prim *q)
   for (int i = 0; i < 3; ++i) q->ut[i] = p[1 + i];
   q->u = p[4];
   for (int i = 0; i < 3; ++i) q->B[i] = p[5 + i];
+  q->ye = 0.0;
+}
+
+/* An ideal-gas EOS object for the point entries that take gamma alone. */
+static orc_eos ideal(double gam)
+{
+  orc_eos e;
+  memset(&e, 0, sizeof e);
+  e.gamma = gam;
+  return e;
 }
 
 /* out: g[16], gi[16], alpha, beta[3], gam[9], gami[9], sqrtgam, sqrtmg (56) */
@@ -48,7 +58,10 @@ void orc_pt_p2c(const orc_metric *m, const double x[3], double gam, const double
   orc_prim q;
   orc_geom_at(m, x, &G);
   unpack(p, &q);
-  orc_prim_to_cons(&G, gam, &q, U);
+  const orc_eos e = ideal(gam);
+  double U9[9];
+  orc_prim_to_cons(&G, &e, &q, U9);
+  memcpy(U, U9, 8 * sizeof(double));
 }
 
 void orc_pt_flux(const orc_metric *m, const double x[3], double gam, const double p[8],
@@ -58,7 +71,10 @@ void orc_pt_flux(const orc_metric *m, const double x[3], double gam, const doubl
   orc_prim q;
   orc_geom_at(m, x, &G);
   unpack(p, &q);
-  orc_flux(&G, gam, &q, dir, F);
+  const orc_eos e = ideal(gam);
+  double F9[9];
+  orc_flux(&G, &e, &q, dir, F9);
+  memcpy(F, F9, 8 * sizeof(double));
 }
 
 void orc_pt_speeds(const orc_metric *m, const double x[3], double gam, const double p[8],
@@ -68,7 +84,8 @@ void orc_pt_speeds(const orc_metric *m, const double x[3], double gam, const dou
   orc_prim q;
   orc_geom_at(m, x, &G);
   unpack(p, &q);
-  orc_speeds(&G, gam, &q, dir, &out[0], &out[1]);
+  const orc_eos e = ideal(gam);
+  orc_speeds(&G, &e, &q, dir, &out[0], &out[1]);
 }
 
 void orc_pt_riemann(const orc_metric *m, const double x[3], double gam, int solver,
@@ -79,7 +96,10 @@ void orc_pt_riemann(const orc_metric *m, const double x[3], double gam, int solv
   orc_geom_at(m, x, &G);
   unpack(pl, &L);
   unpack(pr, &R);
-  orc_riemann(&G, gam, solver, &L, &R, dir, flux);
+  const orc_eos e = ideal(gam);
+  double f9[9];
+  orc_riemann(&G, &e, solver, &L, &R, dir, f9);
+  memcpy(flux, f9, 8 * sizeof(double));
 }
 
 void orc_pt_tmunu(const orc_metric *m, const double x[3], double gam, const double p[8],
@@ -90,7 +110,8 @@ void orc_pt_tmunu(const orc_metric *m, const double x[3], double gam, const doub
   double t[4][4];
   orc_geom_at(m, x, &G);
   unpack(p, &q);
-  orc_tmunu(&G, gam, &q, t);
+  const orc_eos e = ideal(gam);
+  orc_tmunu(&G, &e, &q, t);
   memcpy(T, t, sizeof t);
 }
 
@@ -100,7 +121,9 @@ int orc_pt_c2p(const orc_metric *m, const double x[3], double gam, const double 
   orc_geom G;
   orc_prim q;
   orc_geom_at(m, x, &G);
-  int r = orc_c2p_point(gam, &G, Ud, B, &q, mu);
+  const orc_eos e = ideal(gam);
+  double U6[6] = {Ud[0], Ud[1], Ud[2], Ud[3], Ud[4], 0.0};
+  int r = orc_c2p_point(&e, &G, U6, B, &q, mu);
   if (r == 0) {
     pout[0] = q.rho;
     for (int i = 0; i < 3; ++i) pout[1 + i] = q.ut[i];
@@ -116,11 +139,90 @@ void orc_p2c_batch(const orc_metric *m, const double x[3], double gam, long n,
 {
   orc_geom G;
   orc_geom_at(m, x, &G);
+  const orc_eos e = ideal(gam);
   for (long k = 0; k < n; ++k) {
     orc_prim q;
+    double U9[9];
     unpack(prims + 8 * k, &q);
-    orc_prim_to_cons(&G, gam, &q, U + 8 * k);
+    orc_prim_to_cons(&G, &e, &q, U9);
+    memcpy(U + 8 * k, U9, 8 * sizeof(double));
   }
+}
+
+/* ---- general EOS (eos points at an orc_eos with its table, if any) ----
+ * Primitive vectors of 9: (rho, ut1, ut2, ut3, u, B1, B2, B3, Y_e);
+ * conserved / flux vectors of 9 (the last is D Y_e and its flux). */
+static void unpack9(const double p[9], orc_prim *q)
+{
+  unpack(p, q);
+  q->ye = p[8];
+}
+
+void orc_pt_thermo(const orc_eos *e, long n, const double *rho, const double *u,
+                   const double *ye, double *p, double *gp)
+{
+  for (long k = 0; k < n; ++k) orc_thermo(e, rho[k], u[k], ye[k], &p[k], &gp[k]);
+}
+
+void orc_pt_table(const orc_table *t, long n, const double *rho, const double *eps,
+                  const double *ye, double *lnp, double *g1)
+{
+  for (long k = 0; k < n; ++k) orc_table_eval(t, rho[k], eps[k], ye[k], &lnp[k], &g1[k]);
+}
+
+void orc_pt_p2c_eos(const orc_metric *m, const double x[3], const orc_eos *e,
+                    const double p[9], double U[9])
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  unpack9(p, &q);
+  orc_prim_to_cons(&G, e, &q, U);
+}
+
+void orc_pt_riemann_eos(const orc_metric *m, const double x[3], const orc_eos *e, int solver,
+                        const double pl[9], const double pr[9], int dir, double flux[9])
+{
+  orc_geom G;
+  orc_prim L, R;
+  orc_geom_at(m, x, &G);
+  unpack9(pl, &L);
+  unpack9(pr, &R);
+  orc_riemann(&G, e, solver, &L, &R, dir, flux);
+}
+
+void orc_pt_speeds_eos(const orc_metric *m, const double x[3], const orc_eos *e,
+                       const double p[9], int dir, double out[2])
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  unpack9(p, &q);
+  orc_speeds(&G, e, &q, dir, &out[0], &out[1]);
+}
+
+/* Ud = undensitized (D, S_1, S_2, S_3, tau, D Y_e) -> pout[9]. */
+int orc_pt_c2p_eos(const orc_metric *m, const double x[3], const orc_eos *e, const double Ud[6],
+                   const double B[3], double pout[9], double *mu)
+{
+  orc_geom G;
+  orc_prim q;
+  orc_geom_at(m, x, &G);
+  int r = orc_c2p_point(e, &G, Ud, B, &q, mu);
+  if (r == 0) {
+    pout[0] = q.rho;
+    for (int i = 0; i < 3; ++i) pout[1 + i] = q.ut[i];
+    pout[4] = q.u;
+    for (int i = 0; i < 3; ++i) pout[5 + i] = q.B[i];
+    pout[8] = q.ye;
+  }
+  return r;
+}
+
+double orc_pt_master_tab(const orc_table *t, double D, double ye, double q, double r2, double b2,
+                         double rb, double mu)
+{
+  return orc_c2p_master_tab(t, D, ye, q, r2, b2, rb, mu, NULL, NULL);
 }
 
 double orc_pt_master(double gam, double q, double r2, double b2, double rb, double mu)

@@ -15,8 +15,12 @@
  * These follow from the conserved-vector definitions of Sec. 2.1.  The root is
  * the unique zero in (0, 1]; the oracle finds it by plain bisection (the
  * defining property of the root), not by the Newton iteration of the HIP path.
+ * With a tabulated EOS the same bisection runs on the general master
+ * function of eos.c; the passive scalar is Y_e = (D Y_e)/D, clamped into the
+ * table's range (Sec. 3.2) when a table is used.
  */
 #include <math.h>
+#include <stddef.h>
 #include "orc.h"
 
 double orc_c2p_master(double gam, double q, double r2, double b2, double rb, double mu)
@@ -35,16 +39,25 @@ double orc_c2p_master(double gam, double q, double r2, double b2, double rb, dou
 }
 
 /*
- * Ud = undensitized (D, S_1, S_2, S_3, tau); B = undensitized B^i.
+ * Ud = undensitized (D, S_1, S_2, S_3, tau, D Y_e) (the last entry is read only
+ * with a scalar); B = undensitized B^i.
  * Returns 0 on success, 1 for an invalid state, 2 if the bracket fails.
  */
-int orc_c2p_point(double gam, const orc_geom *G, const double Ud[5], const double B[3],
+int orc_c2p_point(const orc_eos *e, const orc_geom *G, const double Ud[6], const double B[3],
                   orc_prim *P, double *mu_out)
 {
   const double D = Ud[0];
-  for (int v = 0; v < 5; ++v)
+  const double gam = e->gamma;
+  const orc_table *t = e->tab;
+  const int nv = 5 + e->nscalar;
+  for (int v = 0; v < nv; ++v)
     if (!isfinite(Ud[v])) return 1;
   if (!(D > 0.0)) return 1;
+  double ye = e->nscalar ? Ud[5] / D : 0.0;
+  if (t) {
+    if (ye < t->lo[2]) ye = t->lo[2];
+    if (ye > t->hi[2]) ye = t->hi[2];
+  }
   double Su[3], Bl[3];
   for (int i = 0; i < 3; ++i) {
     Su[i] = 0.0; Bl[i] = 0.0;
@@ -64,16 +77,18 @@ int orc_c2p_point(double gam, const orc_geom *G, const double Ud[5], const doubl
   const double b2 = BB / D;
   const double rb = SB / (D * sqrt(D));
 
+#define MASTER(m) (t ? orc_c2p_master_tab(t, D, ye, q, r2, b2, rb, (m), NULL, NULL) \
+                   : orc_c2p_master(gam, q, r2, b2, rb, (m)))
   double lo = 0.0, hi = 1.0;
-  double flo = orc_c2p_master(gam, q, r2, b2, rb, lo);
-  double fhi = orc_c2p_master(gam, q, r2, b2, rb, hi);
+  double flo = MASTER(lo);
+  double fhi = MASTER(hi);
   if (!(flo < 0.0)) return 2;
   if (fhi < 0.0) return 2;
   double mu = 0.5 * (lo + hi);
   for (int it = 0; it < 200; ++it) {
     mu = 0.5 * (lo + hi);
     if (mu <= lo || mu >= hi) break;      /* bracket is two adjacent doubles */
-    const double f = orc_c2p_master(gam, q, r2, b2, rb, mu);
+    const double f = MASTER(mu);
     if (f == 0.0) { lo = hi = mu; break; }
     if (f < 0.0) lo = mu; else hi = mu;
   }
@@ -88,8 +103,15 @@ int orc_c2p_point(double gam, const orc_geom *G, const double Ud[5], const doubl
   const double W = 1.0 / sqrt(1.0 - v2);
   double eps = W * (qbar - mu * rbar2) + v2 * W * W / (1.0 + W);
   if (eps < 0.0) eps = 0.0;
+  if (t) {          /* eps clamped into the table as in the master function */
+    const double emin = exp(t->lo[1]), emax = exp(t->hi[1]);
+    if (eps < emin) eps = emin;
+    if (eps > emax) eps = emax;
+  }
+#undef MASTER
   P->rho = D / W;
   P->u = P->rho * eps;
+  P->ye = ye;
   /* v^i = mu x (r^i + mu (r.b) b^i) with r^i = S^i/D, b^i = B^i/sqrt(D) */
   const double sD = sqrt(D);
   for (int i = 0; i < 3; ++i) {

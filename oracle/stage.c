@@ -16,7 +16,11 @@
  *           T^{mu nu}(g_{nu j,mu} - Gamma^d_{nu mu} g_{dj}) for symmetric T)
  *   S_tau = alpha (T^{mu 0} d_mu ln alpha - T^{mu nu} Gamma^0_{nu mu}).
  * Floors (Sec. 3.2): rho >= rho0 r^-a, u >= u0 r^-b, W <= W_max, then the
- * hydro conserved variables are recomputed from the floored primitives.
+ * hydro conserved variables are recomputed from the floored primitives.  With
+ * a tabulated EOS the floors never go below the table (rho within its range,
+ * eps = u/rho within its range, Y_e within its range).
+ * Passive scalar (nscalar = 1): P[5] = Y_e, U[5] = sqrt(gamma) D Y_e, no
+ * source; its face flux sits in the slot 5 + d of the direction-d block.
  */
 #include <math.h>
 #include <stdint.h>
@@ -73,7 +77,7 @@ static int map_axis(const orc_grid *g, int d, int idx, int normal, int *src, int
   }
 }
 
-void orc_fill_ghosts(const orc_grid *g, const orc_metric *m, double *P, double *Bf)
+void orc_fill_ghosts_n(const orc_grid *g, const orc_metric *m, int nv, double *P, double *Bf)
 {
   (void)m;
   const size_t nc = ncell(g);
@@ -89,8 +93,8 @@ void orc_fill_ghosts(const orc_grid *g, const orc_metric *m, double *P, double *
         }
         if (!any || fixed) continue;
         const size_t s = IDX(g, src[0], src[1], src[2]), t = IDX(g, i, j, k);
-        double v[5];
-        for (int q = 0; q < 5; ++q) v[q] = P[q * nc + s];
+        double v[6];
+        for (int q = 0; q < nv; ++q) v[q] = P[q * nc + s];
         for (int d = 0; d < 3; ++d) {
           if (side[d] == 0) continue;
           const int bc = g->bc[2 * d + (side[d] < 0 ? 0 : 1)];
@@ -101,7 +105,7 @@ void orc_fill_ghosts(const orc_grid *g, const orc_metric *m, double *P, double *
           }
           if (flip[d]) v[1 + d] = -v[1 + d];
         }
-        for (int q = 0; q < 5; ++q) P[q * nc + t] = v[q];
+        for (int q = 0; q < nv; ++q) P[q * nc + t] = v[q];
       }
   /* face-centred densitized field */
   for (int c = 0; c < 3; ++c)
@@ -119,6 +123,11 @@ void orc_fill_ghosts(const orc_grid *g, const orc_metric *m, double *P, double *
           if (flip[c]) v = -v;   /* normal component reverses across the pole */
           Bf[c * nc + IDX(g, i, j, k)] = v;
         }
+}
+
+void orc_fill_ghosts(const orc_grid *g, const orc_metric *m, double *P, double *Bf)
+{
+  orc_fill_ghosts_n(g, m, 5, P, Bf);
 }
 
 /* Cell-centred undensitized B^i = (Bf_lo + Bf_hi) / (2 sqrt(gamma)). */
@@ -140,14 +149,23 @@ void orc_cell_B(const orc_grid *g, const orc_metric *m, const double *Bf, double
       }
 }
 
-static void load_prim(const orc_grid *g, const double *P, const double *Bcc, size_t c,
-                      orc_prim *q)
+static void load_prim(const orc_grid *g, const orc_eos *e, const double *P, const double *Bcc,
+                      size_t c, orc_prim *q)
 {
   const size_t nc = ncell(g);
   q->rho = P[c];
   for (int i = 0; i < 3; ++i) q->ut[i] = P[(1 + i) * nc + c];
   q->u = P[4 * nc + c];
   for (int i = 0; i < 3; ++i) q->B[i] = Bcc[i * nc + c];
+  q->ye = e->nscalar ? P[5 * nc + c] : 0.0;
+}
+
+/* The conserved planes of a cell from the undensitized vector of 9. */
+static void store_cons(const orc_eos *e, double *U, size_t nc, size_t c, double sg,
+                       const double Uc[9])
+{
+  for (int v = 0; v < 5; ++v) U[(size_t)v * nc + c] = sg * Uc[v];
+  if (e->nscalar) U[5 * nc + c] = sg * Uc[8];
 }
 
 void orc_prim_to_cons_grid(const orc_grid *g, const orc_metric *m, const orc_eos *e,
@@ -159,15 +177,15 @@ void orc_prim_to_cons_grid(const orc_grid *g, const orc_metric *m, const orc_eos
   for (int k = g->ng; k < g->ng + g->n[2]; ++k)
     for (int j = g->ng; j < g->ng + g->n[1]; ++j)
       for (int i = g->ng; i < g->ng + g->n[0]; ++i) {
-        double x[3], Uc[8];
+        double x[3], Uc[9];
         orc_geom G;
         orc_prim q;
         orc_coord(g, m, ORC_LOC_CENTER, i, j, k, x);
         orc_geom_at(m, x, &G);
         const size_t c = IDX(g, i, j, k);
-        load_prim(g, P, Bcc, c, &q);
-        orc_prim_to_cons(&G, e->gamma, &q, Uc);
-        for (int v = 0; v < 5; ++v) U[v * nc + c] = G.sqrtgam * Uc[v];
+        load_prim(g, e, P, Bcc, c, &q);
+        orc_prim_to_cons(&G, e, &q, Uc);
+        store_cons(e, U, nc, c, G.sqrtgam, Uc);
       }
   free(Bcc);
 }
@@ -182,16 +200,19 @@ static int is_pole_face(const orc_grid *g, int d, int j)
   return 0;
 }
 
-/* Reconstruct the 5 hydro primitives and the 2 transverse B of cell c along d. */
-static void recon_cell(const orc_grid *g, const double *P, const double *Bcc, int d,
-                       int i, int j, int k, double lo[8], double hi[8])
+/* Reconstruct the 5 hydro primitives, the 2 transverse B and (nscalar) Y_e
+   of cell c along d; entry 8 is Y_e. */
+static void recon_cell(const orc_grid *g, int ns, const double *P, const double *Bcc, int d,
+                       int i, int j, int k, double lo[9], double hi[9])
 {
   const size_t nc = ncell(g);
   const size_t stride = (d == 0) ? 1 : (d == 1) ? (size_t)S1(g) : (size_t)S1(g) * S2(g);
   const size_t c = IDX(g, i, j, k);
-  for (int q = 0; q < 8; ++q) {
-    if (q >= 5 && q - 5 == d) { lo[q] = hi[q] = 0.0; continue; }
-    const double *arr = (q < 5) ? P + (size_t)q * nc : Bcc + (size_t)(q - 5) * nc;
+  lo[8] = hi[8] = 0.0;
+  for (int q = 0; q < 8 + ns; ++q) {
+    if (q >= 5 && q < 8 && q - 5 == d) { lo[q] = hi[q] = 0.0; continue; }
+    const double *arr = (q < 5) ? P + (size_t)q * nc
+                      : (q < 8) ? Bcc + (size_t)(q - 5) * nc : P + 5 * nc;
     double f[5];
     for (int s = -2; s <= 2; ++s) f[s + 2] = arr[c + s * (ptrdiff_t)stride];
     orc_recon1(g->recon, g->weno_fv, f, &lo[q], &hi[q]);
@@ -218,15 +239,15 @@ static void face_fluxes(const orc_grid *g, const orc_metric *m, const orc_eos *e
     for (int j = lo[1]; j <= hi[1]; ++j)
       for (int i = lo[0]; i <= hi[0]; ++i) {
         const size_t f = IDX(g, i, j, k);
-        double fl[8];
+        double fl[9];
         if (is_pole_face(g, d, j)) {
           for (int v = 0; v < 8; ++v) F[(size_t)v * nc + f] = 0.0;
           continue;
         }
         int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
-        double lL[8], hL[8], lR[8], hR[8];
-        recon_cell(g, P, Bcc, d, im, jm, km, lL, hL);   /* left cell  */
-        recon_cell(g, P, Bcc, d, i, j, k, lR, hR);      /* right cell */
+        double lL[9], hL[9], lR[9], hR[9];
+        recon_cell(g, e->nscalar, P, Bcc, d, im, jm, km, lL, hL);   /* left cell  */
+        recon_cell(g, e->nscalar, P, Bcc, d, i, j, k, lR, hR);      /* right cell */
         double x[3];
         orc_geom G;
         orc_coord(g, m, ORC_LOC_FACE1 + d, i, j, k, x);
@@ -235,6 +256,7 @@ static void face_fluxes(const orc_grid *g, const orc_metric *m, const orc_eos *e
         L.rho = hL[0]; R.rho = lR[0];
         for (int a = 0; a < 3; ++a) { L.ut[a] = hL[1 + a]; R.ut[a] = lR[1 + a]; }
         L.u = hL[4]; R.u = lR[4];
+        L.ye = hL[8]; R.ye = lR[8];
         for (int a = 0; a < 3; ++a) {
           if (a == d) {
             L.B[a] = R.B[a] = Bf[(size_t)d * nc + f] / G.sqrtgam;
@@ -242,8 +264,9 @@ static void face_fluxes(const orc_grid *g, const orc_metric *m, const orc_eos *e
             L.B[a] = hL[5 + a]; R.B[a] = lR[5 + a];
           }
         }
-        orc_riemann(&G, e->gamma, g->riemann, &L, &R, d, fl);
+        orc_riemann(&G, e, g->riemann, &L, &R, d, fl);
         for (int v = 0; v < 8; ++v) F[(size_t)v * nc + f] = fl[v];
+        if (e->nscalar) F[(size_t)(5 + d) * nc + f] = fl[8];   /* normal-field slot */
       }
 }
 
@@ -334,7 +357,8 @@ int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
 #define FL(Fd, v, i, j, k) (Fd)[(size_t)(v) * nc + IDX(g, i, j, k)]
 #define EE(a, i, j, k) E[(size_t)(a) * nc + IDX(g, i, j, k)]
 
-  memcpy(Uout, U, 5 * nc * sizeof(double));
+  const int nv = 5 + e->nscalar;
+  memcpy(Uout, U, (size_t)nv * nc * sizeof(double));
   memcpy(Bfout, Bf, 3 * nc * sizeof(double));
   const double c0 = rk[0], c1 = rk[1], cdt = rk[2] * dt;
   const double dx1 = g->dx[0], dx2 = g->dx[1], dx3 = g->dx[2];
@@ -368,11 +392,15 @@ int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
     for (int j = ng; j < ng + g->n[1]; ++j)
       for (int i = ng; i < ng + g->n[0]; ++i) {
         const size_t c = IDX(g, i, j, k);
-        double rhs[5];
+        double rhs[6];
         for (int v = 0; v < 5; ++v)
           rhs[v] = -(FL(F1, v, i + 1, j, k) - FL(F1, v, i, j, k)) / dx1
                    - (FL(F2, v, i, j + 1, k) - FL(F2, v, i, j, k)) / dx2
                    - (FL(F3, v, i, j, k + 1) - FL(F3, v, i, j, k)) / dx3;
+        if (nv > 5)   /* scalar fluxes in the normal-field slots 5, 6, 7 */
+          rhs[5] = -(FL(F1, 5, i + 1, j, k) - FL(F1, 5, i, j, k)) / dx1
+                   - (FL(F2, 6, i, j + 1, k) - FL(F2, 6, i, j, k)) / dx2
+                   - (FL(F3, 7, i, j, k + 1) - FL(F3, 7, i, j, k)) / dx3;
         if (m->kind != ORC_MINKOWSKI) {
           double x[3], dg[4][4][4], Gam[4][4][4], dla[4], T[4][4];
           orc_geom G;
@@ -380,8 +408,8 @@ int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
           orc_coord(g, m, ORC_LOC_CENTER, i, j, k, x);
           orc_geom_at(m, x, &G);
           orc_metric_derivs(m, x, dg, Gam, dla);
-          load_prim(g, P, Bcc, c, &q);
-          orc_tmunu(&G, e->gamma, &q, T);
+          load_prim(g, e, P, Bcc, c, &q);
+          orc_tmunu(&G, e, &q, T);
           for (int jj = 1; jj <= 3; ++jj) {
             double s = 0.0;
             for (int a = 0; a < 4; ++a)
@@ -394,7 +422,7 @@ int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
             for (int b = 0; b < 4; ++b) s2 += T[a][b] * Gam[0][b][a];
           rhs[4] += G.sqrtmg * G.alpha * (s1 - s2);
         }
-        for (int v = 0; v < 5; ++v)
+        for (int v = 0; v < nv; ++v)
           Uout[(size_t)v * nc + c] = c0 * U0[(size_t)v * nc + c] + c1 * U[(size_t)v * nc + c]
                                    + cdt * rhs[v];
       }
@@ -409,10 +437,24 @@ int orc_stage_from(const orc_grid *g, const orc_metric *m, const orc_eos *e,
 static int apply_floors(const orc_eos *e, const orc_geom *G, double r, orc_prim *q)
 {
   int flag = 0;
-  const double rho_flr = e->rho_flr0 * pow(r, -e->rho_flr_pow);
-  const double u_flr = e->u_flr0 * pow(r, -e->u_flr_pow);
+  double rho_flr = e->rho_flr0 * pow(r, -e->rho_flr_pow);
+  double u_flr = e->u_flr0 * pow(r, -e->u_flr_pow);
+  if (e->tab) {
+    const double rmin = exp(e->tab->lo[0]);
+    if (rho_flr < rmin) rho_flr = rmin;
+  }
   if (q->rho < rho_flr) { q->rho = rho_flr; flag |= ORC_FLAG_RHO_FLOOR; }
+  if (e->tab) {
+    const double rmax = exp(e->tab->hi[0]);
+    if (q->rho > rmax) { q->rho = rmax; flag |= ORC_FLAG_RHO_FLOOR; }
+    const double umin = q->rho * exp(e->tab->lo[1]);
+    if (u_flr < umin) u_flr = umin;
+  }
   if (q->u < u_flr) { q->u = u_flr; flag |= ORC_FLAG_U_FLOOR; }
+  if (e->tab) {
+    const double umax = q->rho * exp(e->tab->hi[1]);
+    if (q->u > umax) { q->u = umax; flag |= ORC_FLAG_U_FLOOR; }
+  }
   double ut2 = 0.0;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) ut2 += G->gam[i][j] * q->ut[i] * q->ut[j];
@@ -443,27 +485,31 @@ int orc_con2prim(const orc_grid *g, const orc_metric *m, const orc_eos *e, doubl
     for (int j = g->ng; j < g->ng + g->n[1]; ++j)
       for (int i = g->ng; i < g->ng + g->n[0]; ++i) {
         const size_t c = IDX(g, i, j, k);
-        double x[3], Ud[5], B[3];
+        double x[3], Ud[6] = {0, 0, 0, 0, 0, 0}, B[3];
         orc_geom G;
         orc_prim q;
         orc_coord(g, m, ORC_LOC_CENTER, i, j, k, x);
         orc_geom_at(m, x, &G);
-        for (int v = 0; v < 5; ++v) Ud[v] = U[(size_t)v * nc + c] / G.sqrtgam;
+        const int nv = 5 + e->nscalar;
+        for (int v = 0; v < nv; ++v) Ud[v] = U[(size_t)v * nc + c] / G.sqrtgam;
         for (int a = 0; a < 3; ++a) B[a] = Bcc[(size_t)a * nc + c];
         int fl = 0;
-        if (orc_c2p_point(e->gamma, &G, Ud, B, &q, NULL) != 0) {
-          load_prim(g, P, Bcc, c, &q);
+        if (orc_c2p_point(e, &G, Ud, B, &q, NULL) != 0) {
+          load_prim(g, e, P, Bcc, c, &q);
           fl |= ORC_FLAG_C2P_FAIL;
           nfail += 1;
+        } else if (e->nscalar && q.ye != Ud[5] / Ud[0]) {
+          fl |= ORC_FLAG_YE_CLAMP;           /* Y_e held inside the table */
         }
         fl |= apply_floors(e, &G, orc_radius(m, x), &q);
         P[c] = q.rho;
         for (int a = 0; a < 3; ++a) P[(size_t)(1 + a) * nc + c] = q.ut[a];
         P[4 * nc + c] = q.u;
+        if (e->nscalar) P[5 * nc + c] = q.ye;
         if (fl) {
-          double Uc[8];
-          orc_prim_to_cons(&G, e->gamma, &q, Uc);
-          for (int v = 0; v < 5; ++v) U[(size_t)v * nc + c] = G.sqrtgam * Uc[v];
+          double Uc[9];
+          orc_prim_to_cons(&G, e, &q, Uc);
+          store_cons(e, U, nc, c, G.sqrtgam, Uc);
         }
         if (flag) flag[c] = (int8_t)fl;
       }
@@ -478,16 +524,17 @@ int orc_con2prim(const orc_grid *g, const orc_metric *m, const orc_eos *e, doubl
  * out[1] = max |div B| / (max |Bf| / min dx)   (or max |div B| if Bf = 0)
  * out[2] = max |div B|
  * out[3..7] = sum over interior of U_v dx1 dx2 dx3
+ * out[8] = the same sum of the scalar plane U_5 (0 without a scalar)
  */
 void orc_reductions(const orc_grid *g, const orc_metric *m, const orc_eos *e,
                     const double *P, const double *Bf, const double *U, double cfl,
-                    double out[8])
+                    double out[9])
 {
   const size_t nc = ncell(g);
   const int ng = g->ng;
   double *Bcc = malloc(3 * nc * sizeof(double));
   orc_cell_B(g, m, Bf, Bcc);
-  double smax = 0.0, dmax = 0.0, bmax = 0.0, tot[5] = {0, 0, 0, 0, 0};
+  double smax = 0.0, dmax = 0.0, bmax = 0.0, tot[6] = {0, 0, 0, 0, 0, 0};
   double dxmin = 1e300;
   for (int d = 0; d < 3; ++d)
     if (g->n[d] > 1 && g->dx[d] < dxmin) dxmin = g->dx[d];
@@ -501,12 +548,12 @@ void orc_reductions(const orc_grid *g, const orc_metric *m, const orc_eos *e,
         orc_prim q;
         orc_coord(g, m, ORC_LOC_CENTER, i, j, k, x);
         orc_geom_at(m, x, &G);
-        load_prim(g, P, Bcc, c, &q);
+        load_prim(g, e, P, Bcc, c, &q);
         double s = 0.0;
         for (int d = 0; d < 3; ++d) {
           if (g->n[d] <= 1) continue;
           double lm, lp;
-          orc_speeds(&G, e->gamma, &q, d, &lm, &lp);
+          orc_speeds(&G, e, &q, d, &lm, &lp);
           s += fmax(fabs(lm), fabs(lp)) / g->dx[d];
         }
         if (s > smax) smax = s;
@@ -518,11 +565,11 @@ void orc_reductions(const orc_grid *g, const orc_metric *m, const orc_eos *e,
           if (fabs(Bf[d * nc + up[d]]) > bmax) bmax = fabs(Bf[d * nc + up[d]]);
         }
         if (fabs(div) > dmax) dmax = fabs(div);
-        for (int v = 0; v < 5; ++v) tot[v] += U[(size_t)v * nc + c] * dV;
+        for (int v = 0; v < 5 + e->nscalar; ++v) tot[v] += U[(size_t)v * nc + c] * dV;
       }
   out[0] = (smax > 0.0) ? cfl / smax : 0.0;
   out[1] = (bmax > 0.0) ? dmax / (bmax / dxmin) : dmax;
   out[2] = dmax;
-  for (int v = 0; v < 5; ++v) out[3 + v] = tot[v];
+  for (int v = 0; v < 6; ++v) out[3 + v] = tot[v];
   free(Bcc);
 }

@@ -27,6 +27,102 @@ MINKOWSKI, KS_LOGSPH = 0, 1
 
 
 @dataclass
+class EosTable:
+    """Tabulated EOS on nodes uniform in (ln rho, ln eps, Y_e): data[k, j, i] =
+    (ln p, Gamma_1) at ln rho = lo[0] + i h0, ln eps = lo[1] + j h1,
+    Y_e = lo[2] + k h2 (h_d = (hi[d] - lo[d]) / (n_d - 1)).  Gamma_1 is the
+    adiabatic index d ln p / d ln rho at constant entropy (rho h c_s^2 =
+    Gamma_1 p).  The tables here are synthetic: sampled from closed forms."""
+    data: np.ndarray
+    lo: tuple
+    hi: tuple
+    name: str = ""
+
+    @property
+    def n(self):
+        return (self.data.shape[2], self.data.shape[1], self.data.shape[0])
+
+    def nodes(self, d):
+        return np.linspace(self.lo[d], self.hi[d], self.n[d])
+
+
+TABLE_LO = (np.log(1e-14), np.log(1e-8), 0.05)
+TABLE_HI = (np.log(1e3), np.log(1e3), 0.55)
+
+
+def ideal_table(gamma, n=(64, 64, 6), lo=TABLE_LO, hi=TABLE_HI):
+    """The ideal gas p = (gamma - 1) rho eps sampled on the table grid:
+    ln p = ln(gamma - 1) + ln rho + ln eps, Gamma_1 = gamma (independent of
+    Y_e).  Trilinear interpolation reproduces it exactly up to rounding."""
+    x = np.linspace(lo[0], hi[0], n[0])
+    y = np.linspace(lo[1], hi[1], n[1])
+    data = np.zeros((n[2], n[1], n[0], 2))
+    data[..., 0] = np.log(gamma - 1.0) + x[None, None, :] + y[None, :, None]
+    data[..., 1] = gamma
+    return EosTable(data, tuple(lo), tuple(hi), name=f"ideal gamma={gamma:.6g}")
+
+
+def synthetic_eos(rho, eps, ye, e0=0.2):
+    """Closed-form EOS behind the synthetic table: an adiabatic index that
+    falls from 5/3 to 4/3 once the specific energy exceeds a degeneracy-like
+    scale e_c = e0 (rho Y_e)^(1/3):
+        g = p / (rho eps) = 1/3 + (1/3) e_c / (e_c + eps).
+    With k = e_c eps / (3 (e_c + eps)^2):  d ln p/d ln rho|eps = 1 + k/(3 g),
+    d ln p/d ln eps|rho = 1 - k/g, and
+        Gamma_1 = d ln p/d ln rho|eps + (p/(rho eps)) d ln p/d ln eps|rho
+                = 1 + g - k (1 - 1/(3 g)).
+    Returns (p, Gamma_1)."""
+    ec = e0 * np.cbrt(rho * ye)
+    g = (1.0 + ec / (ec + eps)) / 3.0
+    k = ec * eps / (3.0 * (ec + eps) ** 2)
+    return rho * eps * g, 1.0 + g - k * (1.0 - 1.0 / (3.0 * g))
+
+
+def synthetic_table(n=(96, 96, 11), lo=TABLE_LO, hi=TABLE_HI, e0=0.2):
+    """synthetic_eos sampled on the table grid (a stand-in for a nuclear
+    table such as SFHo: p depends on all three of rho, eps and Y_e)."""
+    x = np.linspace(lo[0], hi[0], n[0])
+    y = np.linspace(lo[1], hi[1], n[1])
+    z = np.linspace(lo[2], hi[2], n[2])
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    p, g1 = synthetic_eos(np.exp(X), np.exp(Y), Z, e0)
+    data = np.stack([np.log(p), g1], axis=-1)
+    return EosTable(np.ascontiguousarray(data), tuple(lo), tuple(hi), name=f"synthetic e0={e0}")
+
+
+def with_ye(prob, ye, table=None):
+    """The problem with the Y_e passive scalar: P gains the plane P[5] = ye
+    (an array broadcast to the grid, or a function of the primitives
+    ye(P) -> array), and the EOS becomes `table` when one is given."""
+    P = prob.P
+    yv = ye(P) if callable(ye) else ye
+    prob.P = np.concatenate([P, np.broadcast_to(yv, P.shape[1:])[None]], axis=0).copy()
+    prob.nscalar = 1
+    prob.table = table
+    return prob
+
+
+def smooth_ye(prob, seed=11, base=0.3, amp=0.15):
+    """Seeded smooth Y_e field of a periodic box: base + amp * (a few Fourier
+    modes, scaled into [-1, 1])."""
+    rng = np.random.default_rng(seed)
+    x = [prob.centers(d) for d in range(3)]
+    Z, Y, X = np.meshgrid(x[2], x[1], x[0], indexing="ij")
+    f = np.zeros(X.shape)
+    for _ in range(3):
+        kv = rng.integers(-2, 3, size=3)
+        f += rng.uniform(0.5, 1.0) * np.cos(2 * np.pi * (kv[0] * X + kv[1] * Y + kv[2] * Z)
+                                           + rng.uniform(0, 2 * np.pi))
+    return base + amp * f / np.abs(f).max()
+
+
+def torus_ye(P, rho_max=1.0):
+    """Y_e of the torus: 0.5 in the atmosphere falling to 0.1 at the density
+    maximum (a neutron-rich disc)."""
+    return 0.5 - 0.4 * np.clip(P[0] / rho_max, 0.0, 1.0)
+
+
+@dataclass
 class Problem:
     n: tuple
     xmin: tuple
@@ -49,6 +145,8 @@ class Problem:
     P: np.ndarray = None
     Bf: np.ndarray = None
     meta: dict = field(default_factory=dict)
+    nscalar: int = 0              # 1: P[5] = Y_e, evolved as a passive scalar
+    table: "EosTable" = None      # tabulated EOS (needs nscalar = 1); None = ideal gas
 
     @property
     def dx(self):
