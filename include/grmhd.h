@@ -21,6 +21,9 @@
  *       Bf [3]: sqrt(gamma) B^d on the lower d-face of each cell
  *       U  [5]: sqrt(gamma) (D, S_1, S_2, S_3, tau), S_j covariant
  *       U0 [5], Bf0 [3]: Runge-Kutta base copies of U and Bf.
+ *     With the passive scalar (desc.nscalar = 1) P, U and U0 have 6 planes:
+ *       P[5] = Y_e and U[5] = sqrt(gamma) D Y_e (Sec. 2.1 advected scalars,
+ *       X = Y_e, no source term).
  *   - Coordinates: Minkowski-Cartesian, or Kerr-Schild with x1 = ln r,
  *     x2 = theta, x3 = phi (units G = c = M = 1, Heaviside-Lorentz B).
  *
@@ -38,7 +41,7 @@
 extern "C" {
 #endif
 
-#define GRMHD_ABI_VERSION 1
+#define GRMHD_ABI_VERSION 2
 
 enum { GRMHD_OK = 0, GRMHD_E_INVALID = -1, GRMHD_E_SHAPE = -2, GRMHD_E_HIP = -3,
        GRMHD_E_UNSUPPORTED = -4 };
@@ -51,7 +54,7 @@ enum { GRMHD_PREC_FP64 = 0, GRMHD_PREC_MIXED = 1 };
 enum { GRMHD_GUESS_COLD = 0, GRMHD_GUESS_PREV = 1, GRMHD_GUESS_MLP = 2 };
 /* per-cell con2prim flag bits */
 enum { GRMHD_FLAG_RHO_FLOOR = 1, GRMHD_FLAG_U_FLOOR = 2, GRMHD_FLAG_W_CAP = 4,
-       GRMHD_FLAG_C2P_FAIL = 8, GRMHD_FLAG_GUESS_FALLBACK = 16 };
+       GRMHD_FLAG_C2P_FAIL = 8, GRMHD_FLAG_GUESS_FALLBACK = 16, GRMHD_FLAG_YE_CLAMP = 32 };
 
 typedef struct grmhd_pack grmhd_pack;
 
@@ -59,14 +62,36 @@ typedef struct grmhd_pack grmhd_pack;
 typedef struct { int kind; double M, a; } grmhd_metric;
 
 /*
- * Ideal-gas EOS (Sec. 2.2) and floors (Sec. 3.2):
- *   p = (gamma - 1) u;  rho >= rho_flr0 r^-rho_flr_pow;  u >= u_flr0 r^-u_flr_pow
- *   (r = 1 in Minkowski);  W <= W_max.
+ * Tabulated EOS (Sec. 2.2 tabulated equations of state; Sec. 3.2 their
+ * bounds).  Nodes uniform in the coordinates (ln rho, ln eps, Y_e): axis d
+ * has n[d] >= 2 nodes from lo[d] to hi[d].  data is DEVICE memory owned by
+ * the caller, n[0] * n[1] * n[2] pairs of doubles (ln p, Gamma_1), node
+ * (i, j, k) at pair i + n[0] (j + n[1] k), with Gamma_1 = d ln p / d ln rho
+ * at constant entropy (rho h c_s^2 = Gamma_1 p).  Between nodes both entries
+ * are trilinear in the coordinates; a state outside the table is looked up
+ * at its clamped coordinates.  It must stay valid and unchanged while calls
+ * that use it are in flight (a captured step graph keeps the pointer).
+ */
+typedef struct {
+  const double *data;
+  int n[3];
+  double lo[3], hi[3];
+} grmhd_eos_table;
+
+/*
+ * EOS (Sec. 2.2) and floors (Sec. 3.2):
+ *   table == NULL: ideal gas p = (gamma - 1) u;
+ *   table != NULL: the tabulated EOS above (the pack needs nscalar = 1, Y_e
+ *     being its third coordinate), and gamma is unused;
+ *   rho >= rho_flr0 r^-rho_flr_pow;  u >= u_flr0 r^-u_flr_pow
+ *   (r = 1 in Minkowski);  W <= W_max; with a table also rho, u / rho and Y_e
+ *   within the table's range (flags RHO_FLOOR, U_FLOOR, YE_CLAMP).
  * c2p_tol: relative Newton tolerance on mu = 1/(hW); c2p_max_iter: cap.
  */
 typedef struct {
   double gamma, rho_flr0, rho_flr_pow, u_flr0, u_flr_pow, W_max, c2p_tol;
   int c2p_max_iter;
+  const grmhd_eos_table *table;
 } grmhd_eos;
 
 /*
@@ -88,6 +113,11 @@ typedef struct {
  *        mp5 of Suresh & Huynh 1997, WENO5-Z-AOAH of App. B).
  * weno_fv: 0 = the fifth-order candidates interpolate point values (App. B
  *          wording), 1 = cell-average reconstruction (WENO5 and MP5 alike).
+ * nscalar: 0, or 1 for the Y_e passive scalar (Sec. 2.1): P, U and U0 gain the
+ *          plane 5, reconstructed and fluxed like the hydro variables (its
+ *          conserved form D Y_e, its flux Y_e times the mass flux).  Needs
+ *          precision FP64 and a single-level pack (GRMHD_E_UNSUPPORTED
+ *          otherwise); the flux tiles then use shape 0.
  */
 typedef struct {
   int nblocks, ng;
@@ -96,6 +126,7 @@ typedef struct {
   int root_nx[3];
   double xmin[3], xmax[3];
   int bc[6];
+  int nscalar;
 } grmhd_pack_desc;
 
 /* Device pointers bound to a pack (caller-owned, see layout above). */
@@ -109,13 +140,15 @@ typedef struct { void *P, *Bf, *U, *U0, *Bf0; } grmhd_state_ptrs;
  *   totals[5]: sum over interior of U_v dx1 dx2 dx3;
  *   c2p_fail, floor_hits: flagged cells of the last con2prim;
  *   c2p_iter_mean / c2p_iter_wavemax_mean: Newton iterations per cell and the
- *   mean over 64-cell wavefronts of the per-wavefront maximum.
+ *   mean over 64-cell wavefronts of the per-wavefront maximum;
+ *   total_scalar: sum over interior of U_5 dx1 dx2 dx3 (0 without a scalar).
  */
 typedef struct {
   double dt, divb_rel, divb_max, totals[5];
   long long c2p_fail, floor_hits;
   double c2p_iter_mean, c2p_iter_wavemax_mean;
   long long guess_fallback;   /* cells whose learned guess was rejected */
+  double total_scalar;
 } grmhd_reduction_out;
 
 int grmhd_abi_version(void);
@@ -165,7 +198,9 @@ int grmhd_stage(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *e
 /*
  * Con2prim + floors on interior cells: P <- P(U, Bf) by safeguarded Newton on
  * the master function f(mu) = mu - 1/(h/W + mu rbar^2) (the unknown mu =
- * 1/(hW)), starting from guess (COLD: mu = 1/sqrt(1 + r^2); PREV: from the
+ * 1/(hW); with a table, the general-EOS form of Kastaun et al. 2021 with
+ * rho, eps clamped into the table and nu = max of its two expressions),
+ * starting from guess (COLD: mu = 1/sqrt(1 + r^2); PREV: from the
  * current P; MLP: the learned initial guess bound by grmhd_mlp_bind, used
  * where the W it implies through the master function agrees with the
  * network's own W output to 50 %, else COLD and flag GUESS_FALLBACK).

@@ -40,6 +40,18 @@ struct EosP {
   int max_iter;
 };
 
+// Tabulated EOS (Sec. 2.2 tabulated EOS, Sec. 3.2 table bounds): nodes
+// uniform in (ln rho, ln eps, Y_e), node (i, j, k) at d[i + nx (j + ny k)]
+// holding (ln p, Gamma_1), Gamma_1 = d ln p / d ln rho at constant entropy
+// (rho h c_s^2 = Gamma_1 p).  Trilinear between nodes; coordinates outside
+// the table are clamped onto it.  d == nullptr: the ideal gas of EosP.
+struct EosTab {
+  const double2 *d;
+  int nx, ny, nz;
+  double lo[3], hi[3], ih[3];            // first / last node, 1 / spacing per axis
+  double rho_min, rho_max, eps_min, eps_max;
+};
+
 // ------------------------------------------------------------------ metric
 //
 // Everything below is templated on the arithmetic type T: FP64 everywhere in
@@ -162,7 +174,7 @@ __device__ __forceinline__ GeoT<T> geo_at(const Tables &Tb, const MetricP &m, in
 
 // ------------------------------------------------------------------ physics
 
-template <typename T> struct PrimT { T rho, u1, u2, u3, ie, B1, B2, B3; };
+template <typename T> struct PrimT { T rho, u1, u2, u3, ie, B1, B2, B3, ye; };
 using Prim = PrimT<double>;
 
 // Auxiliary 4-vector quantities of a primitive state (Sec. 2.1 kinematics and
@@ -175,11 +187,13 @@ struct AuxT {
   T b0, bc1, bc2, bc3;    // b^mu
   T bl1, bl2, bl3;        // b_i
   T b2, p, w;             // b^2, pressure, rho h
+  T gp;                   // Gamma_1 p = rho h c_s^2
 };
 using Aux = AuxT<double>;
 
+// Kinematics of q with the thermodynamics (p, Gamma_1 p) supplied.
 template <typename T>
-__device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T> &q)
+__device__ __forceinline__ AuxT<T> aux_th(const GeoT<T> &G, const PrimT<T> &q, T p, T gp)
 {
   AuxT<T> A;
   A.ut2 = G.g11 * q.u1 * q.u1 + T(2) * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
@@ -214,9 +228,83 @@ __device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T
   A.bl2 = G.g22 * A.bc2;
   A.bl3 = G.g13 * (G.beta1 * A.b0 + A.bc1) + G.g33 * A.bc3;
   A.b2 = BB * iW * iW + A.Bv * A.Bv;
-  A.p = (gam - T(1)) * q.ie;
+  A.p = p;
+  A.gp = gp;
   A.w = q.rho + q.ie + A.p;
   return A;
+}
+
+// Ideal gas: p = (gam - 1) u, Gamma_1 = gam.
+template <typename T>
+__device__ __forceinline__ AuxT<T> aux_of(const GeoT<T> &G, T gam, const PrimT<T> &q)
+{
+  const T p = (gam - T(1)) * q.ie;
+  return aux_th(G, q, p, gam * p);
+}
+
+// ------------------------------------------------------------- tabulated EOS
+
+// One axis of the table lookup: cell i in [0, n-2] and weight w of x clamped
+// into [lo, hi]; inside = x strictly within (the derivative along the axis
+// is zero on the clamped part).  A NaN coordinate lands on lo (fmax / fmin
+// return the non-NaN operand), so the cell index is always in range.
+__device__ __forceinline__ void tab_axis(double x, double lo, double hi, double ih, int n, int &i,
+                                         double &w, bool &inside)
+{
+  inside = x > lo && x < hi;
+  const double t = (fmin(fmax(x, lo), hi) - lo) * ih;
+  const int k = min((int)t, n - 2);
+  i = k;
+  w = t - (double)k;
+}
+
+struct TabV { double L, G1, Lx, Ly; };   // ln p, Gamma_1, d ln p / d ln rho, d ln p / d ln eps
+
+// Trilinear lookup at (x, y, z) = (ln rho, ln eps, Y_e); with DER also the
+// two partial derivatives of the interpolant of ln p.
+template <bool DER>
+__device__ __forceinline__ TabV tab_eval(const EosTab &t, double x, double y, double z)
+{
+  int i, j, k;
+  double wx, wy, wz;
+  bool inx, iny, inz;
+  tab_axis(x, t.lo[0], t.hi[0], t.ih[0], t.nx, i, wx, inx);
+  tab_axis(y, t.lo[1], t.hi[1], t.ih[1], t.ny, j, wy, iny);
+  tab_axis(z, t.lo[2], t.hi[2], t.ih[2], t.nz, k, wz, inz);
+  const long long sy = t.nx, sz = (long long)t.nx * t.ny;
+  const double2 *b = t.d + (i + sy * j + sz * k);
+  const double2 c000 = b[0], c100 = b[1], c010 = b[sy], c110 = b[sy + 1];
+  const double2 c001 = b[sz], c101 = b[sz + 1], c011 = b[sz + sy], c111 = b[sz + sy + 1];
+  auto lerp = [](double a, double c, double w) { return fma(w, c - a, a); };
+  TabV v;
+  const double l00 = lerp(c000.x, c100.x, wx), l10 = lerp(c010.x, c110.x, wx);
+  const double l01 = lerp(c001.x, c101.x, wx), l11 = lerp(c011.x, c111.x, wx);
+  const double l0 = lerp(l00, l10, wy), l1 = lerp(l01, l11, wy);
+  v.L = lerp(l0, l1, wz);
+  const double g00 = lerp(c000.y, c100.y, wx), g10 = lerp(c010.y, c110.y, wx);
+  const double g01 = lerp(c001.y, c101.y, wx), g11 = lerp(c011.y, c111.y, wx);
+  v.G1 = lerp(lerp(g00, g10, wy), lerp(g01, g11, wy), wz);
+  v.Lx = v.Ly = 0.0;
+  if constexpr (DER) {
+    if (inx) {
+      const double d0 = lerp(c100.x - c000.x, c110.x - c010.x, wy);
+      const double d1 = lerp(c101.x - c001.x, c111.x - c011.x, wy);
+      v.Lx = lerp(d0, d1, wz) * t.ih[0];
+    }
+    if (iny) v.Ly = lerp(l10 - l00, l11 - l01, wz) * t.ih[1];
+  }
+  (void)inz;
+  return v;
+}
+
+// p and Gamma_1 p of (rho, u, Y_e) from the table (rho, u > 0).
+__device__ __forceinline__ void tab_thermo(const EosTab &t, double rho, double u, double ye,
+                                           double &p, double &gp)
+{
+  const double x = log(rho);
+  const TabV v = tab_eval<false>(t, x, log(u) - x, ye);
+  p = exp(v.L);
+  gp = v.G1 * p;
 }
 
 // Undensitized conserved vector (D, S_j, tau, B^k).
@@ -263,14 +351,14 @@ __device__ __forceinline__ void flux_of(const GeoT<T> &G, const PrimT<T> &q, con
 // Fast-wave coordinate speeds along DIR from (k.u)^2 (1 - c^2) = c^2 k.k,
 // k_mu = (-lambda, e_DIR), c^2 = cs^2 + ca^2 - cs^2 ca^2.
 template <int DIR, typename T>
-__device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T> &A, T &lm, T &lp)
+__device__ __forceinline__ void speeds_of(const GeoT<T> &G, const AuxT<T> &A, T &lm, T &lp)
 {
   // c^2 = cs^2 + ca^2 - cs^2 ca^2 = 1 - (1 - cs^2)(1 - ca^2), with
-  // cs^2 = gam p / w and ca^2 = b^2 / (w + b^2), is N / Dn with
-  // N = gam p + b^2, Dn = w + b^2.  The roots of the quadratic do not change
-  // when all three coefficients are multiplied by Dn > 0, so c^2 enters as
-  // (1 - c^2) Dn = Dn - N and c^2 Dn = N, with no division.
-  const T Nc = gam * A.p + A.b2;
+  // cs^2 = Gamma_1 p / w and ca^2 = b^2 / (w + b^2), is N / Dn with
+  // N = Gamma_1 p + b^2, Dn = w + b^2.  The roots of the quadratic do not
+  // change when all three coefficients are multiplied by Dn > 0, so c^2
+  // enters as (1 - c^2) Dn = Dn - N and c^2 Dn = N, with no division.
+  const T Nc = A.gp + A.b2;
   const T omc = (A.w + A.b2) - Nc;
   const T ia = G.ialpha;
   const T ia2 = ia * ia;
@@ -295,22 +383,28 @@ __device__ __forceinline__ void speeds_of(const GeoT<T> &G, T gam, const AuxT<T>
 // as two undensitized parts: the densitized flux is sqrt(-g) A + sqrt(gamma) B
 // (the speeds are eigenvalues of d(sqrt(-g)F)/d(sqrt(gamma)U), so the
 // dissipation B acts on sqrt(gamma) U).  The caller densitizes in FP64.
-template <int DIR, int RS, typename T>
-__device__ __forceinline__ void riemann_parts(const GeoT<T> &G, T gam, const PrimT<T> &L,
-                                              const PrimT<T> &R, T A[8], T B[8])
+// (pL, gpL), (pR, gpR): pressure and Gamma_1 p of the two states.  NSC = 1
+// adds the passive scalar as component 8: conserved D Y_e, flux Y_e F_D.
+template <int DIR, int RS, typename T, int NSC = 0>
+__device__ __forceinline__ void riemann_parts(const GeoT<T> &G, const PrimT<T> &L,
+                                              const PrimT<T> &R, T pL, T gpL, T pR, T gpR,
+                                              T A[8 + NSC], T B[8 + NSC])
 {
-  T UL[8], UR[8], FL[8], FR[8], lmL, lpL, lmR, lpR;
+  constexpr int NC = 8 + NSC;
+  T UL[NC], UR[NC], FL[NC], FR[NC], lmL, lpL, lmR, lpR;
   {
-    const AuxT<T> X = aux_of(G, gam, L);
+    const AuxT<T> X = aux_th(G, L, pL, gpL);
     cons_of(G, L, X, UL);
     flux_of<DIR>(G, L, X, UL, FL);
-    speeds_of<DIR>(G, gam, X, lmL, lpL);
+    speeds_of<DIR>(G, X, lmL, lpL);
+    if constexpr (NSC != 0) { UL[8] = UL[0] * L.ye; FL[8] = FL[0] * L.ye; }
   }
   {
-    const AuxT<T> X = aux_of(G, gam, R);
+    const AuxT<T> X = aux_th(G, R, pR, gpR);
     cons_of(G, R, X, UR);
     flux_of<DIR>(G, R, X, UR, FR);
-    speeds_of<DIR>(G, gam, X, lmR, lpR);
+    speeds_of<DIR>(G, X, lmR, lpR);
+    if constexpr (NSC != 0) { UR[8] = UR[0] * R.ye; FR[8] = FR[0] * R.ye; }
   }
   if constexpr (RS == RS_HLL) {
     const T cm = fmin(T(0), fmin(lmL, lmR));
@@ -320,26 +414,27 @@ __device__ __forceinline__ void riemann_parts(const GeoT<T> &G, T gam, const Pri
       const T id = T(1) / den;
       const T a = cp * id, b = cm * id, c = cp * cm * id;
 #pragma unroll
-      for (int v = 0; v < 8; ++v) { A[v] = a * FL[v] - b * FR[v]; B[v] = c * (UR[v] - UL[v]); }
+      for (int v = 0; v < NC; ++v) { A[v] = a * FL[v] - b * FR[v]; B[v] = c * (UR[v] - UL[v]); }
     } else {
 #pragma unroll
-      for (int v = 0; v < 8; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = T(0); }
+      for (int v = 0; v < NC; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = T(0); }
     }
   } else {
     const T c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
     const T hc = T(-0.5) * c;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = hc * (UR[v] - UL[v]); }
+    for (int v = 0; v < NC; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = hc * (UR[v] - UL[v]); }
   }
 }
 
-// FP64 densitized face flux.
+// FP64 densitized face flux, ideal gas.
 template <int DIR, int RS>
 __device__ __forceinline__ void riemann(const Geo &G, double gam, const Prim &L, const Prim &R,
                                         double out[8])
 {
   double A[8], B[8];
-  riemann_parts<DIR, RS, double>(G, gam, L, R, A, B);
+  const double pL = (gam - 1.0) * L.ie, pR = (gam - 1.0) * R.ie;
+  riemann_parts<DIR, RS, double>(G, L, R, pL, gam * pL, pR, gam * pR, A, B);
   const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
   for (int v = 0; v < 8; ++v) out[v] = smg * A[v] + sg * B[v];
@@ -670,6 +765,59 @@ __device__ __forceinline__ double master_f(const C2P &m, double mu)
 {
   double d;
   return master(m, mu, d);
+}
+
+// General-EOS master function (the inversion of Kastaun, Kalinani & Ciolfi
+// 2021 that Sec. 3.1 uses) over the table: rho = D/W and eps clamped into
+// the table, a = p / (rho (1 + eps)),
+//   nu = max((1 + a)(1 + eps)/W, (1 + a)(1 + qbar - mu rbar^2)),
+//   f(mu) = mu - 1/(nu + mu rbar^2),
+// with df/dmu from the derivatives of the trilinear interpolant.
+struct C2PT { double q, r2, b2, rb, v2max, D, ye; };
+
+__device__ __forceinline__ double master_tab(const C2PT &m, const EosTab &t, double mu,
+                                             double &df)
+{
+  const double x = inv(1.0 + mu * m.b2);
+  const double dx = -m.b2 * x * x;
+  const double rb2 = m.rb * m.rb;
+  const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * rb2;
+  const double drbar2 = 2.0 * m.r2 * x * dx + rb2 * (x * (1.0 + x) + mu * (1.0 + 2.0 * x) * dx);
+  const double K = m.b2 * m.r2 - rb2;
+  const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * K;
+  const double dqbar = -K * (mu * x * x + mu * mu * x * dx);
+  double v2 = mu * mu * rbar2, dv2 = 2.0 * mu * rbar2 + mu * mu * drbar2;
+  if (v2 > m.v2max) { v2 = m.v2max; dv2 = 0.0; }
+  const double iW = sqrt(1.0 - v2);
+  const double W = inv(iW);
+  const double dW = 0.5 * W * W * W * dv2;
+  double rho = m.D * iW, drho = -rho * iW * dW;
+  if (rho < t.rho_min) { rho = t.rho_min; drho = 0.0; }
+  if (rho > t.rho_max) { rho = t.rho_max; drho = 0.0; }
+  const double s = 1.0 + qbar - mu * rbar2, ds = dqbar - rbar2 - mu * drbar2;
+  // eps = W (qbar - mu rbar^2) + v^2 W^2/(1 + W) (= W s - 1, without its cancellation)
+  double eps = W * (qbar - mu * rbar2) + v2 * W * W * inv(1.0 + W), deps = dW * s + W * ds;
+  if (eps < t.eps_min) { eps = t.eps_min; deps = 0.0; }
+  if (eps > t.eps_max) { eps = t.eps_max; deps = 0.0; }
+  const double irho = inv(rho), iope = inv(1.0 + eps);
+  const TabV v = tab_eval<true>(t, log(rho), log(eps), m.ye);
+  const double p = exp(v.L);
+  const double dp = p * (v.Lx * drho * irho + v.Ly * deps * inv(eps));
+  const double a = p * irho * iope;
+  const double da = (dp - p * (drho * irho + deps * iope)) * irho * iope;
+  const double nuA = (1.0 + a) * (1.0 + eps) * iW;
+  const double nuB = (1.0 + a) * s;
+  double nu, dnu;
+  if (nuA > nuB) {
+    nu = nuA;
+    dnu = (da * (1.0 + eps) + (1.0 + a) * deps) * iW - nuA * dW * iW;
+  } else {
+    nu = nuB;
+    dnu = da * s + (1.0 + a) * ds;
+  }
+  const double iden = inv(nu + mu * rbar2);
+  df = 1.0 + (dnu + rbar2 + mu * drbar2) * iden * iden;
+  return mu - iden;
 }
 
 }  // namespace grmhd

@@ -73,6 +73,9 @@ int validate(const grmhd_pack_desc *d)
   if (d->riemann < 0 || d->riemann > 1) return fail("bad riemann", GRMHD_E_INVALID);
   if (d->precision != GRMHD_PREC_FP64 && d->precision != GRMHD_PREC_MIXED)
     return fail("bad precision", GRMHD_E_INVALID);
+  if (d->nscalar < 0 || d->nscalar > 1) return fail("nscalar must be 0 or 1", GRMHD_E_INVALID);
+  if (d->nscalar && d->precision != GRMHD_PREC_FP64)
+    return fail("the passive scalar needs FP64 precision", GRMHD_E_UNSUPPORTED);
   if (!d->nx || !d->lloc) return fail("null nx/lloc", GRMHD_E_INVALID);
   for (int s = 0; s < 6; ++s)
     if (d->bc[s] < 0 || d->bc[s] > 3) return fail("bad boundary kind", GRMHD_E_INVALID);
@@ -98,6 +101,8 @@ int validate(const grmhd_pack_desc *d)
       if (lev == 1 && ((n | l) & 1)) return fail("level-1 blocks need even size and offset", GRMHD_E_SHAPE);
     }
   }
+  if (maxlev > 0 && d->nscalar)
+    return fail("two-level meshes carry no passive scalar", GRMHD_E_UNSUPPORTED);
   if (maxlev > 0)
     for (int dd = 0; dd < 3; ++dd)
       if (d->root_nx[dd] < 2 * d->ng) return fail("two-level meshes need root_nx >= 2 ng", GRMHD_E_SHAPE);
@@ -659,6 +664,7 @@ struct grmhd_pack {
   double g_cfl = 0.0;
   grmhd_metric g_metric{};
   grmhd_eos g_eos{};
+  grmhd_eos_table g_tab{};
   std::vector<hipEvent_t> ev_free;
   std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> ev_rec;
   KArgs args() const
@@ -685,6 +691,8 @@ struct grmhd_pack {
     a.SB = (double *)(ws + plan.o_SB);
     a.nsp = plan.nsP;
     a.E = (double *)(ws + plan.o_E);
+    std::memset(&a.et, 0, sizeof a.et);
+    a.npv = 5 + desc.nscalar;
     return a;
   }
 };
@@ -756,13 +764,39 @@ void fill_eos(KArgs &a, const grmhd_eos *e)
   a.eos.W_max = e->W_max;
   a.eos.tol = e->c2p_tol > 0 ? e->c2p_tol : 1e-14;
   a.eos.max_iter = e->c2p_max_iter > 0 ? e->c2p_max_iter : 40;
+  std::memset(&a.et, 0, sizeof a.et);
+  if (const grmhd_eos_table *t = e->table) {
+    a.et.d = (const double2 *)t->data;
+    a.et.nx = t->n[0]; a.et.ny = t->n[1]; a.et.nz = t->n[2];
+    for (int d = 0; d < 3; ++d) {
+      a.et.lo[d] = t->lo[d];
+      a.et.hi[d] = t->hi[d];
+      a.et.ih[d] = (double)(t->n[d] - 1) / (t->hi[d] - t->lo[d]);
+    }
+    a.et.rho_min = std::exp(t->lo[0]); a.et.rho_max = std::exp(t->hi[0]);
+    a.et.eps_min = std::exp(t->lo[1]); a.et.eps_max = std::exp(t->hi[1]);
+  }
 }
 
 int check_eos(grmhd_pack *p, const grmhd_eos *e)
 {
   if (!e) return perr(p, "null eos", GRMHD_E_INVALID);
-  if (!(e->gamma > 1.0)) return perr(p, "gamma must exceed 1", GRMHD_E_INVALID);
+  if (!e->table && !(e->gamma > 1.0)) return perr(p, "gamma must exceed 1", GRMHD_E_INVALID);
   if (!(e->W_max > 1.0)) return perr(p, "W_max must exceed 1", GRMHD_E_INVALID);
+  if (const grmhd_eos_table *t = e->table) {
+    if (!p->desc.nscalar) return perr(p, "a table needs the Y_e scalar (nscalar = 1)", GRMHD_E_INVALID);
+    if (!t->data) return perr(p, "null table data", GRMHD_E_INVALID);
+    for (int d = 0; d < 3; ++d) {
+      if (t->n[d] < 2 || t->n[d] > (1 << 16)) return perr(p, "table axes need 2..65536 nodes", GRMHD_E_SHAPE);
+      if (!std::isfinite(t->lo[d]) || !std::isfinite(t->hi[d]) || !(t->hi[d] > t->lo[d]))
+        return perr(p, "table axis needs finite lo < hi", GRMHD_E_INVALID);
+    }
+    if ((long long)t->n[0] * t->n[1] * t->n[2] > (1LL << 30))
+      return perr(p, "table too large", GRMHD_E_SHAPE);
+    if (!(std::exp(t->lo[0]) > 0.0) || !(std::exp(t->lo[1]) > 0.0) ||
+        !std::isfinite(std::exp(t->hi[0])) || !std::isfinite(std::exp(t->hi[1])))
+      return perr(p, "table density / energy range out of double range", GRMHD_E_INVALID);
+  }
   return 0;
 }
 
@@ -771,7 +805,7 @@ const T *dptr(const grmhd_pack *p, size_t off) { return (const T *)(p->ws + off)
 
 // ---- templated launch helpers (host dispatch over compile-time options)
 
-template <int MK, int D, int RC, int FV, int RS, typename T, int SH>
+template <int MK, int D, int RC, int FV, int RS, typename T, int SH, int NSC>
 void launch_tiles(grmhd_pack *p, const KArgs &a)
 {
   const Plan &pl = p->plan;
@@ -779,75 +813,77 @@ void launch_tiles(grmhd_pack *p, const KArgs &a)
   Prof t(p, GRMHD_PROF_FLUX_X1 + D);
   const int nt = (int)pl.tiles[D][SH].size();
   const int grid = p->persist > 0 ? std::min(nt, p->persist) : nt;
-  hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH>), dim3(grid), dim3(256), 0, p->stream, a,
-                     dptr<int4>(p, pl.o_tl[D][SH]), nt);
+  hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, NSC>), dim3(grid), dim3(256), 0, p->stream,
+                     a, dptr<int4>(p, pl.o_tl[D][SH]), nt);
 }
 
 // Every shape is instantiated for the WENO5-Z-AOAH point-value path (the
-// production reconstruction); the other reconstructions use 16 x 16 tiles.
-template <int MK, int D, int RC, int FV, int RS, typename T>
+// production reconstruction); the other reconstructions, and every pack with
+// the passive scalar, use 16 x 16 tiles.
+template <int MK, int D, int RC, int FV, int RS, typename T, int NSC>
 void launch_tiles_sh(grmhd_pack *p, const KArgs &a, int sh)
 {
-  if constexpr (RC == RC_WENO && FV == 0) {
+  if constexpr (RC == RC_WENO && FV == 0 && NSC == 0) {
     switch (sh) {
-      case 1: launch_tiles<MK, D, RC, FV, RS, T, 1>(p, a); return;
-      case 2: launch_tiles<MK, D, RC, FV, RS, T, 2>(p, a); return;
-      case 3: launch_tiles<MK, D, RC, FV, RS, T, 3>(p, a); return;
-      case 4: launch_tiles<MK, D, RC, FV, RS, T, 4>(p, a); return;
+      case 1: launch_tiles<MK, D, RC, FV, RS, T, 1, NSC>(p, a); return;
+      case 2: launch_tiles<MK, D, RC, FV, RS, T, 2, NSC>(p, a); return;
+      case 3: launch_tiles<MK, D, RC, FV, RS, T, 3, NSC>(p, a); return;
+      case 4: launch_tiles<MK, D, RC, FV, RS, T, 4, NSC>(p, a); return;
       default: break;
     }
   }
-  launch_tiles<MK, D, RC, FV, RS, T, 0>(p, a);
+  launch_tiles<MK, D, RC, FV, RS, T, 0, NSC>(p, a);
 }
 
-template <int MK, int D, int RC, int FV, int RS, typename T>
+template <int MK, int D, int RC, int FV, int RS, typename T, int NSC>
 void launch_flux(grmhd_pack *p, const KArgs &a)
 {
-  launch_tiles_sh<MK, D, RC, FV, RS, T>(p, a, p->tune_sh >= 0 ? p->tune_sh : p->shape[D]);
+  launch_tiles_sh<MK, D, RC, FV, RS, T, NSC>(p, a, p->tune_sh >= 0 ? p->tune_sh : p->shape[D]);
 }
 
-template <int MK, int RC, int FV, int RS, typename T>
+template <int MK, int RC, int FV, int RS, typename T, int NSC>
 void launch_flux3(grmhd_pack *p, const KArgs &a)
 {
-  if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T>(p, a);
-  if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T>(p, a);
-  if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T, NSC>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T, NSC>(p, a);
+  if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T, NSC>(p, a);
   const Plan &pl = p->plan;
   if (p->tune_sh >= 0 || pl.planes.empty()) return;   // autotuning times the tiles alone
   Prof t(p, GRMHD_PROF_FLUX_PLANE);
-  hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T>), dim3(pl.planes.size()), dim3(64), 0,
+  hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T, NSC>), dim3(pl.planes.size()), dim3(64), 0,
                      p->stream, a, dptr<int2>(p, pl.o_planes));
 }
 
-template <int MK, int RC, int FV, typename T>
+template <int MK, int RC, int FV, typename T, int NSC>
 void launch_flux_rs(grmhd_pack *p, const KArgs &a, int rs)
 {
-  if (rs == RS_HLL) launch_flux3<MK, RC, FV, RS_HLL, T>(p, a);
-  else launch_flux3<MK, RC, FV, RS_LLF, T>(p, a);
+  if (rs == RS_HLL) launch_flux3<MK, RC, FV, RS_HLL, T, NSC>(p, a);
+  else launch_flux3<MK, RC, FV, RS_LLF, T, NSC>(p, a);
 }
 
-template <int MK, typename T>
+template <int MK, typename T, int NSC>
 void launch_flux_rc(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs)
 {
   switch (rc) {
-    case RC_CONST: launch_flux_rs<MK, RC_CONST, 0, T>(p, a, rs); break;
-    case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0, T>(p, a, rs); break;
-    case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0, T>(p, a, rs); break;
+    case RC_CONST: launch_flux_rs<MK, RC_CONST, 0, T, NSC>(p, a, rs); break;
+    case RC_PLM_MC: launch_flux_rs<MK, RC_PLM_MC, 0, T, NSC>(p, a, rs); break;
+    case RC_PLM_MINMOD: launch_flux_rs<MK, RC_PLM_MINMOD, 0, T, NSC>(p, a, rs); break;
     case RC_MP5:
-      if (fv) launch_flux_rs<MK, RC_MP5, 1, T>(p, a, rs);
-      else launch_flux_rs<MK, RC_MP5, 0, T>(p, a, rs);
+      if (fv) launch_flux_rs<MK, RC_MP5, 1, T, NSC>(p, a, rs);
+      else launch_flux_rs<MK, RC_MP5, 0, T, NSC>(p, a, rs);
       break;
     default:
-      if (fv) launch_flux_rs<MK, RC_WENO, 1, T>(p, a, rs);
-      else launch_flux_rs<MK, RC_WENO, 0, T>(p, a, rs);
+      if (fv) launch_flux_rs<MK, RC_WENO, 1, T, NSC>(p, a, rs);
+      else launch_flux_rs<MK, RC_WENO, 0, T, NSC>(p, a, rs);
   }
 }
 
 template <int MK>
 void launch_flux_all(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs, int prec)
 {
-  if (prec == GRMHD_PREC_MIXED) launch_flux_rc<MK, float>(p, a, rc, fv, rs);
-  else launch_flux_rc<MK, double>(p, a, rc, fv, rs);
+  if (p->desc.nscalar) launch_flux_rc<MK, double, 1>(p, a, rc, fv, rs);
+  else if (prec == GRMHD_PREC_MIXED) launch_flux_rc<MK, float, 0>(p, a, rc, fv, rs);
+  else launch_flux_rc<MK, double, 0>(p, a, rc, fv, rs);
 }
 
 }  // namespace
@@ -1039,6 +1075,11 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
                                p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
     else hipLaunchKernelGGL((k_update<MK_MINK, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
                             p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  } else if (p->desc.nscalar) {
+    if (ks) hipLaunchKernelGGL((k_update<MK_KS, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+    else hipLaunchKernelGGL((k_update<MK_MINK, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
   } else if (ks) {
     hipLaunchKernelGGL((k_update<MK_KS, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
                        dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
@@ -1054,13 +1095,21 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
 
 namespace {
 
+template <int MK, int RED, int NSC>
+void launch_c2p_n(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch,
+                  const float *mlp, double *part)
+{
+  if (guess == 0) hipLaunchKernelGGL((k_c2p<MK, 0, RED, NSC>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+  else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK, 1, RED, NSC>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+  else hipLaunchKernelGGL((k_c2p<MK, 2, RED, NSC>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+}
+
 template <int MK, int RED>
 void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch, const float *mlp,
                 double *part)
 {
-  if (guess == 0) hipLaunchKernelGGL((k_c2p<MK, 0, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
-  else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK, 1, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
-  else hipLaunchKernelGGL((k_c2p<MK, 2, RED>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
+  if (p->desc.nscalar) launch_c2p_n<MK, RED, 1>(p, a, guess, g, ch, mlp, part);
+  else launch_c2p_n<MK, RED, 0>(p, a, guess, g, ch, mlp, part);
 }
 
 // part != nullptr: the inversion also writes the reduction partials, and the
@@ -1132,12 +1181,16 @@ int grmhd_prim_to_cons(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eo
   a.met.M = m->M; a.met.a = m->a;
   fill_eos(a, eos);
   const Plan &pl = p->plan;
-  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
-    hipLaunchKernelGGL(k_p2c<MK_KS>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_chi));
-  else
-    hipLaunchKernelGGL(k_p2c<MK_MINK>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_chi));
+  const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
+  const dim3 g(pl.ch_int.size());
+  const int2 *ch = dptr<int2>(p, pl.o_chi);
+  if (p->desc.nscalar) {
+    if (ks) hipLaunchKernelGGL((k_p2c<MK_KS, 1>), g, dim3(256), 0, p->stream, a, ch);
+    else hipLaunchKernelGGL((k_p2c<MK_MINK, 1>), g, dim3(256), 0, p->stream, a, ch);
+  } else {
+    if (ks) hipLaunchKernelGGL((k_p2c<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch);
+    else hipLaunchKernelGGL((k_p2c<MK_MINK, 0>), g, dim3(256), 0, p->stream, a, ch);
+  }
   LAUNCHCHK(p);
   return GRMHD_OK;
 }
@@ -1156,12 +1209,16 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
   double *res = (double *)(p->ws + pl.o_res);
   {
   Prof t(p, GRMHD_PROF_REDUCE);
-  if (m->kind == GRMHD_METRIC_KS_LOGSPH)
-    hipLaunchKernelGGL(k_reduce<MK_KS>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_chi), part);
-  else
-    hipLaunchKernelGGL(k_reduce<MK_MINK>, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_chi), part);
+  const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
+  const dim3 g(pl.ch_int.size());
+  const int2 *ch = dptr<int2>(p, pl.o_chi);
+  if (p->desc.nscalar) {
+    if (ks) hipLaunchKernelGGL((k_reduce<MK_KS, 1>), g, dim3(256), 0, p->stream, a, ch, part);
+    else hipLaunchKernelGGL((k_reduce<MK_MINK, 1>), g, dim3(256), 0, p->stream, a, ch, part);
+  } else {
+    if (ks) hipLaunchKernelGGL((k_reduce<MK_KS, 0>), g, dim3(256), 0, p->stream, a, ch, part);
+    else hipLaunchKernelGGL((k_reduce<MK_MINK, 0>), g, dim3(256), 0, p->stream, a, ch, part);
+  }
   hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(256), 0, p->stream, (const double *)part,
                      (int)pl.ch_int.size(), cfl, pl.dxmin, res);
   }
@@ -1188,6 +1245,7 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
       nwave += (live + 63) / 64;
     }
     out->guess_fallback = (long long)h[14];
+    out->total_scalar = h[15];
     out->c2p_iter_mean = ncell ? h[10] / ncell : 0.0;
     out->c2p_iter_wavemax_mean = nwave ? h[11] / nwave : 0.0;
   }
@@ -1358,9 +1416,12 @@ int grmhd_step_graph(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
   if (int rc = check_metric(p, m)) return rc;
   if (int rc = check_eos(p, eos)) return rc;
   if (!(cfl > 0.0) || nsteps < 0) return perr(p, "need cfl > 0 and nsteps >= 0", GRMHD_E_INVALID);
+  grmhd_eos_table tab{};
+  if (eos->table) tab = *eos->table;
   const bool same = p->gexec && p->g_guess == guess && p->g_cfl == cfl &&
                     !std::memcmp(&p->g_metric, m, sizeof *m) &&
-                    !std::memcmp(&p->g_eos, eos, sizeof *eos);
+                    !std::memcmp(&p->g_eos, eos, sizeof *eos) &&
+                    !std::memcmp(&p->g_tab, &tab, sizeof tab);
   if (!same) {
     if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
     const bool prof = p->prof;
@@ -1375,7 +1436,7 @@ int grmhd_step_graph(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
     const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return perr(p, std::string("instantiate: ") + hipGetErrorString(ei), GRMHD_E_HIP);
-    p->g_guess = guess; p->g_cfl = cfl; p->g_metric = *m; p->g_eos = *eos;
+    p->g_guess = guess; p->g_cfl = cfl; p->g_metric = *m; p->g_eos = *eos; p->g_tab = tab;
   }
   for (int s = 0; s < nsteps; ++s) HIPCHK(p, hipGraphLaunch(p->gexec, p->stream));
   return GRMHD_OK;
@@ -1418,7 +1479,7 @@ int grmhd_autotune(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
   fill_eos(a, eos);
   const int rcn = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
   const int prec = p->desc.precision;
-  const bool all = rcn == RC_WENO && fv == 0;
+  const bool all = rcn == RC_WENO && fv == 0 && !p->desc.nscalar;
   hipEvent_t e0, e1;
   HIPCHK(p, hipEventCreate(&e0));
   HIPCHK(p, hipEventCreate(&e1));

@@ -31,7 +31,30 @@ struct KArgs {
   double *SP, *SB;      // staged coarse-view rows of P [5][nsp] and face B [nsb]
   long long nsp;
   double *E;            // two-level meshes: edge EMFs [3][nct] (corrected at level boundaries)
+  EosTab et;            // tabulated EOS (et.d == nullptr: ideal gas)
+  int npv;              // primitive planes: 5, or 6 with the Y_e scalar in P[5]
 };
+
+// p and Gamma_1 p of a cell or face state: the table when one is bound (only
+// packs with the scalar, NSC = 1, can bind one), else the ideal gas.
+template <int NSC>
+__device__ __forceinline__ void thermo_of(const KArgs &a, double rho, double u, double ye,
+                                          double &p, double &gp)
+{
+  if constexpr (NSC != 0) {
+    if (a.et.d) { tab_thermo(a.et, rho, u, ye, p, gp); return; }
+  }
+  p = (a.eos.gam - 1.0) * u;
+  gp = a.eos.gam * p;
+}
+
+template <int NSC>
+__device__ __forceinline__ Aux aux_cell(const KArgs &a, const Geo &G, const Prim &q)
+{
+  double p, gp;
+  thermo_of<NSC>(a, q.rho, q.ie, q.ye, p, gp);
+  return aux_th(G, q, p, gp);
+}
 
 struct GhostP { long long dst, src; int flags, pad; };
 struct GhostB { long long dst, src; int comp, flip; };
@@ -56,21 +79,24 @@ struct FixE { long long dst, src, st; int e, pad; };
 
 // ------------------------------------------------------------------ ghosts
 
-__device__ __forceinline__ void bc_flags(int flags, double v[5]);
+__device__ __forceinline__ void bc_flags(int flags, double *v);
 
 // flags: bit d = polar mirror along d (velocity d flips); 8 << 2d / 16 << 2d
-// = low / high outflow along d (inflow velocity zeroed)
+// = low / high outflow along d (inflow velocity zeroed); the scalar plane
+// (npv = 6) is copied as it is
 __global__ __launch_bounds__(256) void k_ghost_P(KArgs a, const GhostP *__restrict__ map, int n)
 {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   const GhostP g = map[e];
-  double v[5];
+  double v[6];
 #pragma unroll
-  for (int q = 0; q < 5; ++q) v[q] = a.P[q * a.nct + g.src];
+  for (int q = 0; q < 6; ++q)
+    if (q < a.npv) v[q] = a.P[q * a.nct + g.src];
   bc_flags(g.flags, v);
 #pragma unroll
-  for (int q = 0; q < 5; ++q) a.P[q * a.nct + g.dst] = v[q];
+  for (int q = 0; q < 6; ++q)
+    if (q < a.npv) a.P[q * a.nct + g.dst] = v[q];
 }
 
 __global__ __launch_bounds__(256) void k_ghost_B(KArgs a, const GhostB *__restrict__ map, int n)
@@ -82,7 +108,7 @@ __global__ __launch_bounds__(256) void k_ghost_B(KArgs a, const GhostB *__restri
   a.Bf[g.comp * a.nct + g.dst] = g.flip ? -v : v;
 }
 
-__device__ __forceinline__ void bc_flags(int flags, double v[5])
+__device__ __forceinline__ void bc_flags(int flags, double *v)
 {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -213,7 +239,6 @@ __global__ __launch_bounds__(256) void k_bcc(KArgs a, const int2 *__restrict__ c
 
 // ------------------------------------------------------------------- fluxes
 
-constexpr int NV = 7;
 // Face-tile shapes: TD faces along the flux direction x TA columns (256 faces);
 // the columns run along x1 when the direction is x2 or x3.
 template <int SH> struct Shape;
@@ -235,14 +260,18 @@ __device__ __forceinline__ Geo geo_face(const KArgs &a, const BlockInfo &b, int 
   return geo_at<MK>(a.tab, a.met, b.tab1 + i, D == 0, b.tab2 + j, D == 1);
 }
 
-template <int D, typename T>
-__device__ __forceinline__ PrimT<T> make_prim(const T q[7], T bn)
+// Reconstructed variables along D: rho, u-tilde^1..3, u, the two transverse
+// cell-centred B, and (NSC) Y_e.
+template <int D, int NSC, typename T>
+__device__ __forceinline__ PrimT<T> make_prim(const T q[7 + NSC], T bn)
 {
   PrimT<T> p;
   p.rho = q[0]; p.u1 = q[1]; p.u2 = q[2]; p.u3 = q[3]; p.ie = q[4];
   if constexpr (D == 0) { p.B1 = bn; p.B2 = q[5]; p.B3 = q[6]; }
   if constexpr (D == 1) { p.B1 = q[5]; p.B2 = bn; p.B3 = q[6]; }
   if constexpr (D == 2) { p.B1 = q[5]; p.B2 = q[6]; p.B3 = bn; }
+  if constexpr (NSC != 0) p.ye = q[7];
+  else p.ye = T(0);
   return p;
 }
 
@@ -257,31 +286,43 @@ __device__ __forceinline__ GeoT<T> geo_cast(const Geo &G)
   return g;
 }
 
-// Riemann solve at one face in arithmetic T; densitization in FP64.
-template <int MK, int D, int RS, typename T>
+// Riemann solve at one face in arithmetic T; densitization in FP64.  The
+// flux of the normal field component vanishes identically, so its slot
+// 5 + D carries the passive-scalar flux when NSC = 1 (and is not written
+// otherwise).
+template <int MK, int D, int RS, typename T, int NSC>
 __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo &b, int i, int j,
-                                                long long c, const T qL[7], const T qR[7])
+                                                long long c, const T qL[7 + NSC],
+                                                const T qR[7 + NSC])
 {
   if (D == 1 && (j == b.pole_lo || j == b.pole_hi)) {   // sqrt(-g) = 0 on the axis
 #pragma unroll
     for (int v = 0; v < 8; ++v)
-      if (v != 5 + D) a.F[(D * 8 + v) * a.nct + c] = 0.0;
+      if (v != 5 + D || NSC) a.F[(D * 8 + v) * a.nct + c] = 0.0;
     return;
   }
   const Geo G = geo_face<MK, D>(a, b, i, j);
   const double bn = a.Bf[D * a.nct + c] / G.sqrtg;
-  const PrimT<T> L = make_prim<D>(qL, T(bn)), R = make_prim<D>(qR, T(bn));
-  T A[8], B[8];
+  const PrimT<T> L = make_prim<D, NSC>(qL, T(bn)), R = make_prim<D, NSC>(qR, T(bn));
+  T A[8 + NSC], B[8 + NSC];
   if constexpr (sizeof(T) == sizeof(double)) {
-    riemann_parts<D, RS, T>(G, a.eos.gam, L, R, A, B);
+    double pL, gpL, pR, gpR;
+    thermo_of<NSC>(a, L.rho, L.ie, L.ye, pL, gpL);
+    thermo_of<NSC>(a, R.rho, R.ie, R.ye, pR, gpR);
+    riemann_parts<D, RS, T, NSC>(G, L, R, pL, gpL, pR, gpR, A, B);
   } else {
-    riemann_parts<D, RS, T>(geo_cast<T>(G), T(a.eos.gam), L, R, A, B);
+    static_assert(NSC == 0, "the mixed-precision flux path has no scalar");
+    const T gam = T(a.eos.gam);
+    const T pL = (gam - T(1)) * L.ie, pR = (gam - T(1)) * R.ie;
+    riemann_parts<D, RS, T>(geo_cast<T>(G), L, R, pL, gam * pL, pR, gam * pR, A, B);
   }
   const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
   for (int v = 0; v < 8; ++v)
-    if (v != 5 + D)        // the flux of the normal field component vanishes identically
+    if (v != 5 + D)
       a.F[(D * 8 + v) * a.nct + c] = smg * (double)A[v] + sg * (double)B[v];
+  if constexpr (NSC != 0)
+    a.F[(D * 8 + 5 + D) * a.nct + c] = smg * (double)A[8] + sg * (double)B[8];
 }
 
 template <typename T>
@@ -296,11 +337,12 @@ __device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
-template <int MK, int D, int RECON, int FV, int RS, typename T, int SH>
+template <int MK, int D, int RECON, int FV, int RS, typename T, int SH, int NSC = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
 {
   constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NS = TD + 5, NR = TD + 1;
+  constexpr int NV = 7 + NSC;
   __shared__ T stg[NV * TA * NS];
   __shared__ T sfr[NV * TA * NR];     // right-face states of cells org[D]-1 .. org[D]+TD-1
   constexpr int AX = (D == 0) ? 1 : 0;
@@ -334,13 +376,14 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
       for (int v = 0; v < 5; ++v) dst[v * TA * NS] = T(a.P[v * a.nct + c]);
       dst[5 * TA * NS] = T(a.Bcc[tcomp<D>(0) * a.nct + c]);
       dst[6 * TA * NS] = T(a.Bcc[tcomp<D>(1) * a.nct + c]);
+      if constexpr (NSC != 0) dst[7 * TA * NS] = T(a.P[5 * a.nct + c]);
     }
     __syncthreads();
 
-    // reconstruct: each thread its own cell org[D]+fd (all seven variables),
+    // reconstruct: each thread its own cell org[D]+fd (all NV variables),
     // keeping the left-face state for its face and publishing the right-face
     // state; the cells org[D]-1 of the TA columns come after (right face only)
-    T qR[7];
+    T qR[NV];
     bool redo = false;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -360,7 +403,7 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
         positivity(v, f[2], l, r);
         sfr[(v * TA + aa) * NR + fd + 1] = r;
 #pragma unroll
-        for (int w = 0; w < 7; ++w)
+        for (int w = 0; w < NV; ++w)
           if (w == v) qR[w] = l;
       }
     }
@@ -380,10 +423,10 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
     const bool live = idx[D] < a.ng + b.n[D] && idx[AX] <= a.ng + b.n[AX] && idx[AX] < b.s[AX];
     if (live) {
       const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-      T qL[7];
+      T qL[NV];
 #pragma unroll
-      for (int v = 0; v < 7; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];   // cell idx[D]-1
-      face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
+      for (int v = 0; v < NV; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];   // cell idx[D]-1
+      face_flux_store<MK, D, RS, T, NSC>(a, b, idx[0], idx[1], c, qL, qR);
     }
     __syncthreads();   // LDS is restaged by the next tile
   }
@@ -391,9 +434,10 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
 
 // One face on the upper boundary plane along D (index ng + n_D); e indexes
 // the (n_A + 2) x (n_B + 2) faces of the plane (transverse ghosts included).
-template <int MK, int D, int RECON, int FV, int RS, typename T>
+template <int MK, int D, int RECON, int FV, int RS, typename T, int NSC>
 __device__ __forceinline__ void plane_face(const KArgs &a, const BlockInfo &b, int e)
 {
+  constexpr int NV = 7 + NSC;
   constexpr int AX = (D == 0) ? 1 : 0;
   constexpr int BX = (D == 2) ? 1 : 2;
   const int na = b.n[AX] + 2, nb = b.n[BX] + 2;
@@ -405,10 +449,11 @@ __device__ __forceinline__ void plane_face(const KArgs &a, const BlockInfo &b, i
   const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
   const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
   const long long sd = str[D];
-  T qL[7], qR[7];
+  T qL[NV], qR[NV];
 #pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    const double *arr = v < 5 ? a.P + v * a.nct : a.Bcc + tcomp<D>(v - 5) * a.nct;
+  for (int v = 0; v < NV; ++v) {
+    const double *arr = v < 5 ? a.P + v * a.nct
+                      : v < 7 ? a.Bcc + tcomp<D>(v - 5) * a.nct : a.P + 5 * a.nct;
     T f[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) f[m] = T(arr[c + (m - 3) * sd]);
@@ -420,23 +465,23 @@ __device__ __forceinline__ void plane_face(const KArgs &a, const BlockInfo &b, i
     positivity(v, f[3], l, r);
     qR[v] = l;
   }
-  face_flux_store<MK, D, RS, T>(a, b, idx[0], idx[1], c, qL, qR);
+  face_flux_store<MK, D, RS, T, NSC>(a, b, idx[0], idx[1], c, qL, qR);
 }
 
 // The boundary planes of all three directions in one launch of 64-thread
 // workgroups (a plane holds ~1/n of a direction's faces: small grids of
 // latency-bound work are better spread thin over the CUs):
 // chunk = (3 * block + D, first face of 64).
-template <int MK, int RECON, int FV, int RS, typename T>
+template <int MK, int RECON, int FV, int RS, typename T, int NSC = 0>
 __global__ __launch_bounds__(64) void k_flux_planes(KArgs a, const int2 *__restrict__ chunks)
 {
   const int2 ch = chunks[blockIdx.x];
   const int D = ch.x % 3;
   const BlockInfo b = a.blocks[ch.x / 3];
   const int e = ch.y + threadIdx.x;
-  if (D == 0) plane_face<MK, 0, RECON, FV, RS, T>(a, b, e);
-  else if (D == 1) plane_face<MK, 1, RECON, FV, RS, T>(a, b, e);
-  else plane_face<MK, 2, RECON, FV, RS, T>(a, b, e);
+  if (D == 0) plane_face<MK, 0, RECON, FV, RS, T, NSC>(a, b, e);
+  else if (D == 1) plane_face<MK, 1, RECON, FV, RS, T, NSC>(a, b, e);
+  else plane_face<MK, 2, RECON, FV, RS, T, NSC>(a, b, e);
 }
 
 // ------------------------------------------------- two-level coupling
@@ -489,7 +534,7 @@ __global__ __launch_bounds__(256) void k_emf_fix(KArgs a, const FixE *__restrict
 
 // ------------------------------------------------------------------ update
 
-template <int MK, int EARR>
+template <int MK, int EARR, int NSC = 0>
 __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict__ chunks,
                                                 double dt_in, const double *__restrict__ dt_dev,
                                                 double c0, double c1, double cdt, int save_base)
@@ -511,11 +556,14 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
   const bool in1 = i < ng + b.n[0], in2 = j < ng + b.n[1], in3 = k < ng + b.n[2];
 
   if (in1 && in2 && in3) {
-    double rhs[5];
+    double rhs[5 + NSC];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
       rhs[v] = -(F0[v * n + c + 1] - F0[v * n + c]) * i1 - (F1[v * n + c + sj] - F1[v * n + c]) * i2 -
                (F2[v * n + c + sk] - F2[v * n + c]) * i3;
+    if constexpr (NSC != 0)   // scalar fluxes in the normal-field slots 5, 6, 7
+      rhs[5] = -(F0[5 * n + c + 1] - F0[5 * n + c]) * i1 -
+               (F1[6 * n + c + sj] - F1[6 * n + c]) * i2 - (F2[7 * n + c + sk] - F2[7 * n + c]) * i3;
     if constexpr (MK == MK_KS) {
       const double r = a.tab.rc[b.tab1 + i], s = a.tab.sc[b.tab2 + j], ct = a.tab.cc[b.tab2 + j];
       const Geo G = geo_ks(r, s, ct, a.met);
@@ -523,7 +571,8 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
       q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
       q.ie = a.P[4 * n + c];
       q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
-      const Aux A = aux_of(G, a.eos.gam, q);
+      q.ye = NSC ? a.P[5 * n + c] : 0.0;
+      const Aux A = aux_cell<NSC>(a, G, q);
       const Sym4 T = tmunu(G, A);
       double S1, S2, St;
       ks_sources(r, s, ct, a.met, G, T, S1, S2, St);
@@ -532,7 +581,7 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
       rhs[4] += St;
     }
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
+    for (int v = 0; v < 5 + NSC; ++v) {
       const double u = a.U[v * n + c];
       if (save_base) {
         a.U0[v * n + c] = u;
@@ -579,7 +628,7 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
 
 // ------------------------------------------------------------- reductions
 
-constexpr int NPART = 13;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax, guess fallback
+constexpr int NPART = 14;   // smax, divmax, bmax, tot[5], nfail, nfloor, itsum, wavemax, guess fallback, scalar total
 
 __device__ __forceinline__ double wave_max(double v)
 {
@@ -596,17 +645,19 @@ __device__ __forceinline__ double wave_sum(double v)
 
 // Per-cell diagnostics of the reductions: [0] sum_d max|lambda_d| / dx_d,
 // [1] |div B|, [2] max |face B|, [3..7] U dV, [8] failed inversion,
-// [9] floor hit, [10] Newton iterations, [12] learned guess rejected.
-template <int MK>
+// [9] floor hit, [10] Newton iterations, [12] learned guess rejected,
+// [13] scalar U dV.
+template <int MK, int NSC = 0>
 __device__ __forceinline__ void cell_diag(const KArgs &a, const BlockInfo &b, const Geo &G,
-                                          const Prim &q, const double bf[6], const double U[5],
-                                          int fl, int iters, double val[NPART])
+                                          const Prim &q, const double bf[6],
+                                          const double U[5 + NSC], int fl, int iters,
+                                          double val[NPART])
 {
-  const Aux A = aux_of(G, a.eos.gam, q);
+  const Aux A = aux_cell<NSC>(a, G, q);
   double s = 0.0, lm, lp;
-  if (a.active[0]) { speeds_of<0>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[0]; }
-  if (a.active[1]) { speeds_of<1>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[1]; }
-  if (a.active[2]) { speeds_of<2>(G, a.eos.gam, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[2]; }
+  if (a.active[0]) { speeds_of<0>(G, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[0]; }
+  if (a.active[1]) { speeds_of<1>(G, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[1]; }
+  if (a.active[2]) { speeds_of<2>(G, A, lm, lp); s += fmax(fabs(lm), fabs(lp)) / b.dx[2]; }
   val[0] = s;
   val[1] = fabs((bf[1] - bf[0]) / b.dx[0] + (bf[3] - bf[2]) / b.dx[1] + (bf[5] - bf[4]) / b.dx[2]);
   val[2] = fmax(fmax(fmax(fabs(bf[0]), fabs(bf[1])), fmax(fabs(bf[2]), fabs(bf[3]))),
@@ -619,6 +670,7 @@ __device__ __forceinline__ void cell_diag(const KArgs &a, const BlockInfo &b, co
   val[10] = (double)iters;
   val[11] = 0.0;
   val[12] = (fl & 16) ? 1.0 : 0.0;
+  val[13] = NSC ? U[NSC ? 5 : 0] * dV : 0.0;
 }
 
 // Fold the 256 threads' diagnostics (wavefront shuffles, then a fixed order
@@ -634,6 +686,7 @@ __device__ __forceinline__ void block_diag_store(double val[NPART], double *__re
   for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
   val[11] = itmax;
   val[12] = wave_sum(val[12]);
+  val[13] = wave_sum(val[13]);
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
@@ -651,7 +704,7 @@ __device__ __forceinline__ void block_diag_store(double val[NPART], double *__re
   }
 }
 
-template <int MK>
+template <int MK, int NSC = 0>
 __global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict__ chunks,
                                                 double *__restrict__ part)
 {
@@ -676,21 +729,22 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict_
     q.ie = a.P[4 * n + c];
     q.B1 = 0.5 * (bf[0] + bf[1]) * isg; q.B2 = 0.5 * (bf[2] + bf[3]) * isg;
     q.B3 = 0.5 * (bf[4] + bf[5]) * isg;
-    double U[5];
+    q.ye = NSC ? a.P[5 * n + c] : 0.0;
+    double U[5 + NSC];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) U[v] = a.U[v * n + c];
-    cell_diag<MK>(a, b, G, q, bf, U, a.flags[c], a.iters[c], val);
+    for (int v = 0; v < 5 + NSC; ++v) U[v] = a.U[v * n + c];
+    cell_diag<MK, NSC>(a, b, G, q, bf, U, a.flags[c], a.iters[c], val);
   }
   block_diag_store(val, part);
 }
 
 // --------------------------------------------------------------- inversion
 
-template <int MK>
+template <int MK, int NSC = 0>
 __device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Geo &G,
-                                           const Prim &q, double Uout[5])
+                                           const Prim &q, double Uout[5 + NSC])
 {
-  const Aux A = aux_of(G, a.eos.gam, q);
+  const Aux A = aux_cell<NSC>(a, G, q);
   double U[8];
   cons_of(G, q, A, U);
 #pragma unroll
@@ -698,13 +752,21 @@ __device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Ge
     Uout[v] = G.sqrtg * U[v];
     a.U[v * a.nct + c] = Uout[v];
   }
+  if constexpr (NSC != 0) {
+    Uout[5] = G.sqrtg * (U[0] * q.ye);
+    a.U[5 * a.nct + c] = Uout[5];
+  }
 }
 
 // One cell's inversion + floors; with RED also its reduction diagnostics.
-template <int MK, int GUESS, int RED>
+// NSC = 1: the Y_e scalar (P[5], U[5] = sqrt(gamma) D Y_e) and, when a table
+// is bound, the general-EOS master function with the table's bounds
+// (Sec. 3.2: rho, eps and Y_e stay inside the table).
+template <int MK, int GUESS, int RED, int NSC = 0>
 __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int e,
                                          const float *__restrict__ mlp_mu, double val[NPART])
 {
+  constexpr int NU = 5 + NSC;
   const int ng = a.ng;
   const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
   const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
@@ -712,9 +774,9 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   const long long n = a.nct;
   const Geo G = geo_center<MK>(a, b, i, j);
   const double isg = inv(G.sqrtg);
-  double Ur[5], Ud[5];
+  double Ur[NU], Ud[NU];
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < NU; ++v) {
     Ur[v] = a.U[v * n + c];
     Ud[v] = Ur[v] * isg;
   }
@@ -727,15 +789,23 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   prev.rho = a.P[c]; prev.u1 = a.P[n + c]; prev.u2 = a.P[2 * n + c]; prev.u3 = a.P[3 * n + c];
   prev.ie = a.P[4 * n + c];
   prev.B1 = B1; prev.B2 = B2; prev.B3 = B3;
+  prev.ye = NSC ? a.P[5 * n + c] : 0.0;
+  const bool tab = NSC != 0 && a.et.d != nullptr;
 
   const double gam = a.eos.gam;
   int flag = 0, iters = 0;
   Prim q = prev;
   bool ok = Ud[0] > 0.0;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) ok = ok && isfinite(Ud[v]);
+  for (int v = 0; v < NU; ++v) ok = ok && isfinite(Ud[v]);
   if (ok) {
     const double D = Ud[0], iD = inv(D);
+    double ye = 0.0;
+    if constexpr (NSC != 0) {
+      const double yr = Ud[5] * iD;
+      ye = tab ? fmin(fmax(yr, a.et.lo[2]), a.et.hi[2]) : yr;
+      if (ye != yr) flag |= 32;            // Y_e held inside the table
+    }
     // S^i = gamma^ij S_j ; B_i = gamma_ij B^j
     const double Su1 = G.gi11 * Ud[1] + G.gi13 * Ud[3];
     const double Su2 = G.gi22 * Ud[2];
@@ -749,13 +819,28 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
     const double isD = inv(sqrt(D));
     m.rb = (Ud[1] * B1 + Ud[2] * B2 + Ud[3] * B3) * iD * isD;
     m.v2max = m.r2 / (1.0 + m.r2);
-    if (master_f(m, 1.0) < 0.0) {
+    C2PT mt;
+    mt.q = m.q; mt.r2 = m.r2; mt.b2 = m.b2; mt.rb = m.rb; mt.v2max = m.v2max;
+    mt.D = D; mt.ye = ye;
+    auto F = [&](double mu, double &df) -> double {
+      if constexpr (NSC != 0) {
+        if (tab) return master_tab(mt, a.et, mu, df);
+      }
+      return master(m, mu, df);
+    };
+    double df1;
+    if (F(1.0, df1) < 0.0) {
       ok = false;
     } else {
       double mu;
-      if constexpr (GUESS == 1) {
+      if constexpr (GUESS == 1 && NSC == 0) {
         const Aux Ap = aux_of(G, gam, prev);
         mu = 1.0 / ((1.0 + gam * prev.ie / prev.rho) * Ap.W);
+      } else if constexpr (GUESS == 1) {
+        double pp, gpp;
+        thermo_of<NSC>(a, prev.rho, prev.ie, prev.ye, pp, gpp);
+        const Aux Ap = aux_th(G, prev, pp, gpp);
+        mu = 1.0 / ((1.0 + (prev.ie + pp) / prev.rho) * Ap.W);
       } else {
         mu = 1.0 / sqrt(1.0 + m.r2);             // cold guess: no prior state
         if constexpr (GUESS == 2) {
@@ -780,7 +865,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
       const double tol = a.eos.tol;
       for (iters = 1; iters <= a.eos.max_iter; ++iters) {
         double df;
-        const double f = master(m, mu, df);
+        const double f = F(mu, df);
         if (f == 0.0) break;
         if (f < 0.0) lo = mu; else hi = mu;
         double mn = mu - f / df;
@@ -798,8 +883,10 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
       const double W = inv(iW);
       double eps = W * (qbar - mu * rbar2) + v2 * W * W * inv(1.0 + W);
       eps = eps < 0.0 ? 0.0 : eps;
+      if (tab) eps = fmin(fmax(eps, a.et.eps_min), a.et.eps_max);
       q.rho = D * iW;
       q.ie = q.rho * eps;
+      q.ye = ye;
       const double f1 = mu * x * W, f2 = mu * m.rb * isD;
       q.u1 = f1 * (Su1 * iD + f2 * B1);
       q.u2 = f1 * (Su2 * iD + f2 * B2);
@@ -808,15 +895,21 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   }
   if (!ok) {
     q = prev;
-    flag |= 8;
+    flag = (flag & 16) | 8;
   }
-  // floors (Sec. 3.2)
+  // floors (Sec. 3.2), never below the table
   double r = 1.0;
   if constexpr (MK == MK_KS) r = a.tab.rc[b.tab1 + i];
-  const double rflr = a.eos.rho_flr0 * pow(r, -a.eos.rho_flr_pow);
-  const double uflr = a.eos.u_flr0 * pow(r, -a.eos.u_flr_pow);
+  double rflr = a.eos.rho_flr0 * pow(r, -a.eos.rho_flr_pow);
+  double uflr = a.eos.u_flr0 * pow(r, -a.eos.u_flr_pow);
+  if (tab) rflr = fmax(rflr, a.et.rho_min);
   if (q.rho < rflr) { q.rho = rflr; flag |= 1; }
+  if (tab) {
+    if (q.rho > a.et.rho_max) { q.rho = a.et.rho_max; flag |= 1; }
+    uflr = fmax(uflr, q.rho * a.et.eps_min);
+  }
   if (q.ie < uflr) { q.ie = uflr; flag |= 2; }
+  if (tab && q.ie > q.rho * a.et.eps_max) { q.ie = q.rho * a.et.eps_max; flag |= 2; }
   const double ut2 = G.g11 * q.u1 * q.u1 + 2.0 * G.g13 * q.u1 * q.u3 + G.g22 * q.u2 * q.u2 +
                      G.g33 * q.u3 * q.u3;
   if (sqrt(1.0 + ut2) > a.eos.W_max) {
@@ -826,16 +919,17 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   }
   a.P[c] = q.rho; a.P[n + c] = q.u1; a.P[2 * n + c] = q.u2; a.P[3 * n + c] = q.u3;
   a.P[4 * n + c] = q.ie;
-  if (flag & 15) cons_store<MK>(a, c, G, q, Ur);
+  if constexpr (NSC != 0) a.P[5 * n + c] = q.ye;
+  if (flag & 47) cons_store<MK, NSC>(a, c, G, q, Ur);
   a.flags[c] = (int8_t)flag;
   a.iters[c] = (uint8_t)min(iters, 255);
-  if constexpr (RED != 0) cell_diag<MK>(a, b, G, q, bf, Ur, flag, min(iters, 255), val);
+  if constexpr (RED != 0) cell_diag<MK, NSC>(a, b, G, q, bf, Ur, flag, min(iters, 255), val);
 }
 
 // Inversion of every interior cell; RED = 1 also folds the reduction
 // diagnostics of the final state into part[] (the reductions pass fused into
 // the last inversion of a step).
-template <int MK, int GUESS, int RED>
+template <int MK, int GUESS, int RED, int NSC = 0>
 __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks,
                                              const float *__restrict__ mlp_mu,
                                              double *__restrict__ part)
@@ -846,11 +940,11 @@ __global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ c
   double val[NPART];
 #pragma unroll
   for (int q = 0; q < NPART; ++q) val[q] = 0.0;
-  if (e < b.n[0] * b.n[1] * b.n[2]) c2p_cell<MK, GUESS, RED>(a, b, e, mlp_mu, val);
+  if (e < b.n[0] * b.n[1] * b.n[2]) c2p_cell<MK, GUESS, RED, NSC>(a, b, e, mlp_mu, val);
   if constexpr (RED != 0) block_diag_store(val, part);
 }
 
-template <int MK>
+template <int MK, int NSC = 0>
 __global__ __launch_bounds__(256) void k_p2c(KArgs a, const int2 *__restrict__ chunks)
 {
   const int2 ch = chunks[blockIdx.x];
@@ -870,8 +964,9 @@ __global__ __launch_bounds__(256) void k_p2c(KArgs a, const int2 *__restrict__ c
   q.B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
   q.B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
   q.B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
-  double Uo[5];
-  cons_store<MK>(a, c, G, q, Uo);
+  q.ye = NSC ? a.P[5 * n + c] : 0.0;
+  double Uo[5 + NSC];
+  cons_store<MK, NSC>(a, c, G, q, Uo);
 }
 
 // -------------------------------------------------------------- reductions
@@ -907,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_reduce_fin(const double *__restrict__ p
     res[2] = o[1];
     for (int v = 0; v < 5; ++v) res[3 + v] = o[3 + v];
     res[8] = o[8]; res[9] = o[9]; res[10] = o[10]; res[11] = o[11];
-    res[12] = o[2]; res[13] = o[0]; res[14] = o[12];
+    res[12] = o[2]; res[13] = o[0]; res[14] = o[12]; res[15] = o[13];
   }
 }
 

@@ -25,7 +25,7 @@ class PackDesc(ctypes.Structure):
                 ("riemann", ctypes.c_int), ("precision", ctypes.c_int), ("weno_fv", ctypes.c_int),
                 ("nx", _cint_p), ("level", _cint_p), ("lloc", _cint_p),
                 ("root_nx", ctypes.c_int * 3), ("xmin", ctypes.c_double * 3),
-                ("xmax", ctypes.c_double * 3), ("bc", ctypes.c_int * 6)]
+                ("xmax", ctypes.c_double * 3), ("bc", ctypes.c_int * 6), ("nscalar", ctypes.c_int)]
 
 
 class StatePtrs(ctypes.Structure):
@@ -37,11 +37,17 @@ class Metric(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("M", ctypes.c_double), ("a", ctypes.c_double)]
 
 
+class EosTable(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3)]
+
+
 class Eos(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("rho_flr0", ctypes.c_double),
                 ("rho_flr_pow", ctypes.c_double), ("u_flr0", ctypes.c_double),
                 ("u_flr_pow", ctypes.c_double), ("W_max", ctypes.c_double),
-                ("c2p_tol", ctypes.c_double), ("c2p_max_iter", ctypes.c_int)]
+                ("c2p_tol", ctypes.c_double), ("c2p_max_iter", ctypes.c_int),
+                ("table", ctypes.POINTER(EosTable))]
 
 
 class ReductionOut(ctypes.Structure):
@@ -49,7 +55,7 @@ class ReductionOut(ctypes.Structure):
                 ("divb_max", ctypes.c_double), ("totals", ctypes.c_double * 5),
                 ("c2p_fail", ctypes.c_longlong), ("floor_hits", ctypes.c_longlong),
                 ("c2p_iter_mean", ctypes.c_double), ("c2p_iter_wavemax_mean", ctypes.c_double),
-                ("guess_fallback", ctypes.c_longlong)]
+                ("guess_fallback", ctypes.c_longlong), ("total_scalar", ctypes.c_double)]
 
 
 EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
@@ -189,6 +195,9 @@ class Pack:
             d.xmax[k] = prob.xmax[k]
         for s in range(6):
             d.bc[s] = prob.bc[s]
+        self.nscalar = int(getattr(prob, "nscalar", 0))
+        d.nscalar = self.nscalar
+        self.npv = 5 + self.nscalar
         self.desc = d
         L = lib()
         offs = (ctypes.c_longlong * self.nb)()
@@ -200,10 +209,10 @@ class Pack:
         if wsb == 0:
             _check(-1)
         f64 = dict(dtype=torch.float64, device=self.device)
-        self.P = torch.zeros((5, self.nct), **f64)
+        self.P = torch.zeros((self.npv, self.nct), **f64)
         self.Bf = torch.zeros((3, self.nct), **f64)
-        self.U = torch.zeros((5, self.nct), **f64)
-        self.U0 = torch.zeros((5, self.nct), **f64)
+        self.U = torch.zeros((self.npv, self.nct), **f64)
+        self.U0 = torch.zeros((self.npv, self.nct), **f64)
         self.Bf0 = torch.zeros((3, self.nct), **f64)
         self.ws = torch.zeros(wsb + 256, dtype=torch.uint8, device=self.device)
         ws_ptr = (self.ws.data_ptr() + 255) // 256 * 256
@@ -220,9 +229,30 @@ class Pack:
         self.h = h
         self.metric = Metric(prob.metric_kind, prob.M, prob.a)
         self.eos = Eos(prob.gamma, prob.rho_flr0, prob.rho_flr_pow, prob.u_flr0, prob.u_flr_pow,
-                       prob.W_max, c2p_tol, c2p_max_iter)
+                       prob.W_max, c2p_tol, c2p_max_iter, None)
+        if getattr(prob, "table", None) is not None:
+            self.set_table(prob.table)
         self.cfl = prob.cfl
         self.t = 0.0
+
+    def set_table(self, tab):
+        """Bind a tabulated EOS (inputs.EosTable): its nodes are copied to the
+        device once; None restores the ideal gas."""
+        if tab is None:
+            self.eos.table = None
+            self._tab = None
+            return
+        t = self.torch
+        data = t.from_numpy(np.ascontiguousarray(tab.data, dtype=np.float64)).to(self.device)
+        et = EosTable()
+        et.data = data.data_ptr()
+        n = tab.n
+        for d in range(3):
+            et.n[d] = int(n[d])
+            et.lo[d] = float(tab.lo[d])
+            et.hi[d] = float(tab.hi[d])
+        self._tab = (data, et)
+        self.eos.table = ctypes.pointer(et)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -386,7 +416,7 @@ class Pack:
                 "totals": np.array(out.totals[:]), "c2p_fail": out.c2p_fail,
                 "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
                 "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean,
-                "guess_fallback": out.guess_fallback}
+                "guess_fallback": out.guess_fallback, "total_scalar": out.total_scalar}
 
     def mlp_bind(self, params, mean, std):
         """params: float32 device tensor [MLP_NPARAM]; mean/std: float32 device [5]."""

@@ -50,10 +50,16 @@ TABLE_LO = (np.log(1e-14), np.log(1e-8), 0.05)
 TABLE_HI = (np.log(1e3), np.log(1e3), 0.55)
 
 
-def ideal_table(gamma, n=(64, 64, 6), lo=TABLE_LO, hi=TABLE_HI):
+IDEAL_LO = (np.log(1e-30), np.log(1e-30), 0.05)
+IDEAL_HI = (np.log(1e10), np.log(1e10), 0.55)
+
+
+def ideal_table(gamma, n=(64, 64, 6), lo=IDEAL_LO, hi=IDEAL_HI):
     """The ideal gas p = (gamma - 1) rho eps sampled on the table grid:
     ln p = ln(gamma - 1) + ln rho + ln eps, Gamma_1 = gamma (independent of
-    Y_e).  Trilinear interpolation reproduces it exactly up to rounding."""
+    Y_e).  Trilinear interpolation reproduces it exactly up to rounding; the
+    default range is wide enough that no state of the test problems is
+    clamped, so the table path must reproduce the ideal-gas path."""
     x = np.linspace(lo[0], hi[0], n[0])
     y = np.linspace(lo[1], hi[1], n[1])
     data = np.zeros((n[2], n[1], n[0], 2))

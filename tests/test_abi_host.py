@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(G.EXPORTS)
-    assert L.grmhd_abi_version() == 1
+    assert L.grmhd_abi_version() == 2
 
 
 def _desc(prob, nblk=(1, 1, 1), **over):
@@ -68,7 +68,7 @@ def test_layout_alignment(L):
 
 
 @pytest.mark.parametrize("field,value", [("ng", 3), ("recon", 9), ("riemann", 5),
-                                         ("precision", 7), ("nblocks", 0)])
+                                         ("precision", 7), ("nblocks", 0), ("nscalar", 2)])
 def test_invalid_descriptor_rejected(L, field, value):
     prob = I.linear_wave((16, 16, 16))
     d, keep = _desc(prob, **{field: value})
@@ -139,3 +139,22 @@ def test_two_level_plan_builds_and_checks_maps(L):
     # two blocks over the same cells
     d, keep = _desc_layout(root, nx + nx[:3], ll + ll[:3], lev + lev[:1])
     assert L.grmhd_pack_workspace_bytes(ctypes.byref(d)) == 0
+
+
+def test_scalar_descriptor_rules(L):
+    """The Y_e scalar needs FP64 and a single level; it does not change the
+    workspace (its face flux uses the normal-field slot of the flux array)."""
+    prob = I.linear_wave((16, 16, 16))
+    d0, keep0 = _desc(prob)
+    d1, keep1 = _desc(prob, nscalar=1)
+    w0 = L.grmhd_pack_workspace_bytes(ctypes.byref(d0))
+    assert w0 > 0 and L.grmhd_pack_workspace_bytes(ctypes.byref(d1)) == w0
+    d2, keep2 = _desc(prob, nscalar=1, precision=1)
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d2)) == 0
+    assert b"FP64" in L.grmhd_last_error(None)
+    fine = I.torus(n=(64, 64, 32))
+    lev, nx, ll = I.amr_layout(fine, target=60, node=8, smallest=8)
+    d3, keep3 = _desc_layout(I.coarse_problem(fine), nx, ll, lev)
+    d3.nscalar = 1
+    assert L.grmhd_pack_workspace_bytes(ctypes.byref(d3)) == 0
+    assert b"scalar" in L.grmhd_last_error(None)
