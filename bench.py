@@ -33,10 +33,12 @@ def parse():
     ap.add_argument("--persist", type=int, default=0,
                     help="persistent flux grid size in workgroups (0: one per tile)")
     ap.add_argument("--workload", default="torus128",
-                    choices=["torus128", "amr640", "mixed192", "fp64_192"],
+                    choices=["torus128", "amr640", "mixed192", "fp64_192", "table128", "scalar128"],
                     help="torus128: the headline line (default); amr640: the torus at 256^3 "
                          "effective on ~640 two-level blocks; mixed192 / fp64_192: the torus "
-                         "at 192^3 in 27 blocks of 64^3, mixed precision / FP64")
+                         "at 192^3 in 27 blocks of 64^3, mixed precision / FP64; table128: "
+                         "the 128^3 torus with the synthetic tabulated EOS and the Y_e scalar; "
+                         "scalar128: the same with the ideal gas (scalar cost alone)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -129,6 +131,16 @@ def growth_workload(args, torch, G, I):
                 f"rho_max): {len(lev)} blocks ({int(sum(lev))} at level 1) of 16^3/32^3/64^3, "
                 "FP64, WENO5-Z-AOAH + LLF")
         cfl, prec = root.cfl, "f64"
+    elif args.workload in ("table128", "scalar128"):
+        prob = I.torus(n=(128, 128, 128))
+        tab = I.synthetic_table() if args.workload == "table128" else None
+        prob = I.with_ye(prob, I.torus_ye, tab)
+        pack = G.Pack(prob)
+        pack.init()
+        desc = ("torus 128^3 (one block), WENO5-Z-AOAH + LLF, FP64, Y_e passive scalar, " +
+                (f"tabulated EOS ({tab.n[0]}x{tab.n[1]}x{tab.n[2]} nodes in ln rho, ln eps, Y_e; "
+                 "synthetic)" if tab is not None else "ideal gas"))
+        cfl, prec = prob.cfl, "f64"
     else:
         prob = I.torus(n=(192, 192, 192))
         mixed = args.workload == "mixed192"
@@ -156,11 +168,13 @@ def growth_workload(args, torch, G, I):
            "config": {"workload": desc, "cells": ncell, "blocks": int(len(nx))},
            "graph_replay": {"ms_per_step": round(ms_graph / args.steps, 4),
                             "value": round(ncell * args.steps / (ms_graph * 1e-3), 1)},
-           "k_flux": {"avg_launch_ms": round(avg, 4), "faces_per_launch": faces,
-                      "algorithmic_TFLOPs": round(opc["per_face_flux_ks_weno_llf"] * faces / (avg * 1e-3) / 1e12, 3)},
+           "k_flux": {"avg_launch_ms": round(avg, 4), "faces_per_launch": faces},
            "kernels": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
            "tiling": tiles,
            "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"]}}
+    if args.workload not in ("table128", "scalar128"):     # the operation count is the ideal path's
+        out["k_flux"]["algorithmic_TFLOPs"] = round(
+            opc["per_face_flux_ks_weno_llf"] * faces / (avg * 1e-3) / 1e12, 3)
     print(json.dumps(out), flush=True)
 
 

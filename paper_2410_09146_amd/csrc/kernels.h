@@ -337,8 +337,10 @@ __device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
+// Occupancy target: 4 waves per SIMD (128 VGPRs) for the hydro variables;
+// with the scalar and the table lookups 3 (up to 168 VGPRs, no spills).
 template <int MK, int D, int RECON, int FV, int RS, typename T, int SH, int NSC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4 - NSC)))
 void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
 {
   constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NS = TD + 5, NR = TD + 1;
