@@ -13,7 +13,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = ["metric.c", "physics.c", "eos.c", "recon.c", "c2p.c", "stage.c", "api.c", "mesh.c"]
+SOURCES = ["metric.c", "physics.c", "eos.c", "recon.c", "c2p.c", "stage.c", "api.c", "mesh.c",
+           "m1.c"]
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
           "-std=c11", "-Wall"]
 
@@ -88,6 +89,8 @@ def lib():
         _lib = ctypes.CDLL(LIB_PATH)
         _lib.orc_pt_master.restype = ctypes.c_double
         _lib.orc_pt_master_tab.restype = ctypes.c_double
+        _lib.orc_m1_chi.restype = ctypes.c_double
+        _lib.orc_m1_chi.argtypes = [ctypes.c_double]
     return _lib
 
 
@@ -95,6 +98,8 @@ _P = ctypes.POINTER(ctypes.c_double)
 
 
 def _ptr(a):
+    if a.dtype == np.float64 and a.ndim == 1 and not a.flags["C_CONTIGUOUS"] and a.size <= 16:
+        a = np.ascontiguousarray(a)       # small point vectors (views) are copied
     if not (a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
         raise TypeError("oracle arrays must be C-contiguous float64")
     return a.ctypes.data_as(_P)
@@ -255,6 +260,52 @@ def master_tab(tab_struct, D, ye, q, r2, b2, rb, mu):
                                                                 (D, ye, q, r2, b2, rb, mu)))
 
 
+# ------------------------------------------------------------ gray M1 moments
+# X = (E, F_1, F_2, F_3) undensitized Eulerian moments of one species, ut the
+# fluid's u-tilde^i, op = (kappa_J, kappa_H, J_eq).
+
+def _geom_struct(metric, x):
+    class _G(ctypes.Structure):
+        _fields_ = [("g", ctypes.c_double * 16), ("gi", ctypes.c_double * 16),
+                    ("alpha", ctypes.c_double), ("beta", ctypes.c_double * 3),
+                    ("gam", ctypes.c_double * 9), ("gami", ctypes.c_double * 9),
+                    ("sqrtgam", ctypes.c_double), ("sqrtmg", ctypes.c_double)]
+    G = _G()
+    lib().orc_geom_at(ctypes.byref(metric), _ptr(np.asarray(x, float)), ctypes.byref(G))
+    return G
+
+
+def m1_chi(f):
+    return lib().orc_m1_chi(float(f))
+
+
+def m1_closure(metric, x, ut, E, F):
+    G = _geom_struct(metric, x)
+    P = np.zeros((3, 3))
+    lib().orc_m1_closure(ctypes.byref(G), _ptr(np.asarray(ut, float)), ctypes.c_double(E),
+                         _ptr(np.asarray(F, float)), _ptr(P))
+    return P
+
+
+def m1_sources(metric, x, ut, X, op):
+    G = _geom_struct(metric, x)
+    S = np.zeros(4)
+    J = ctypes.c_double(0.0)
+    lib().orc_m1_sources(ctypes.byref(G), _ptr(np.asarray(ut, float)),
+                         _ptr(np.asarray(X, float)), _ptr(np.asarray(op, float)),
+                         ctypes.byref(J), _ptr(S))
+    return J.value, S
+
+
+def m1_implicit(metric, x, ut, Xs, op, dt):
+    G = _geom_struct(metric, x)
+    X = np.zeros(4)
+    it = lib().orc_m1_implicit(ctypes.byref(G), _ptr(np.asarray(ut, float)),
+                               _ptr(np.asarray(Xs, float)), _ptr(np.asarray(op, float)),
+                               ctypes.c_double(dt), _ptr(X))
+    return it, X
+
+
 # ----------------------------------------------------------------- block API
 
 class Block:
@@ -322,6 +373,17 @@ class Block:
                                    flag.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)),
                                    ctypes.c_int(nthreads))
         return flag, nfail
+
+    def m1_update(self, P, R, kap, dt, nthreads=1):
+        """Implicit gray-M1 collision update of R [nsp, 4, s3, s2, s1] (in place)."""
+        nsp = R.shape[0]
+        it = np.zeros(self.shape, dtype=np.int32)
+        bad = lib().orc_m1_update_grid(ctypes.byref(self.grid), ctypes.byref(self.metric),
+                                       ctypes.c_int(nsp), _ptr(P), _ptr(R), _ptr(kap),
+                                       ctypes.c_double(dt),
+                                       it.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       ctypes.c_int(nthreads))
+        return it, bad
 
     def reductions(self, P, Bf, U, cfl):
         out = np.zeros(9)

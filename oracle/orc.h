@@ -115,6 +115,16 @@ void orc_thermo(const orc_eos *e, double rho, double u, double ye, double *p, do
 double orc_c2p_master_tab(const orc_table *t, double D, double ye, double q, double r2,
                           double b2, double rb, double mu, double *rho_out, double *eps_out);
 
+/* m1.c (gray M1 moments of one species: X = (E, F_1, F_2, F_3), op = (kappa_J,
+   kappa_H, J_eq)) */
+double orc_m1_chi(double f);
+void orc_m1_closure(const orc_geom *G, const double ut[3], double E, const double Fl[3],
+                    double P[3][3]);
+void orc_m1_sources(const orc_geom *G, const double ut[3], const double X[4],
+                    const double op[3], double *J_out, double S[4]);
+int orc_m1_implicit(const orc_geom *G, const double ut[3], const double Xs[4],
+                    const double op[3], double dt, double X[4]);
+
 /* recon.c */
 void orc_recon1(int method, int weno_fv, const double f[5], double *fl, double *fr);
 void orc_weno_weights(int weno_fv, const double f[5], double w[3]);

@@ -865,3 +865,68 @@ def mesh_blocks(prob_fine, level, nx, lloc):
         Ps.append(P)
         Bs.append(Bf)
     return Ps, Bs
+
+
+# ---------------------------------------------------------------------------
+# Gray M1 radiation fields and opacities (synthetic)
+# ---------------------------------------------------------------------------
+
+M1_SPECIES = ("nu_e", "nu_e_bar", "nu_x")
+
+
+def m1_fields(prob, seed=21, e0=(1e-3, 7e-4, 4e-4), fmax=0.9, a_abs=(10.0, 30.0, 100.0),
+              a_scat=(5.0, 5.0, 20.0), c_eq=(0.3, 0.2, 0.1)):
+    """Seeded radiation moments and opacities of three species on a problem's
+    grid (ghosts included).  Returns (R, kap):
+      R[s] = sqrt(gamma) (E, F_1, F_2, F_3) with E = e0_s (1 + 0.5 xi) and a
+      flux F_i = f E nhat_i of flux factor f = fmax xi' (|F| measured with
+      gamma^ij), nhat a seeded direction per cell;
+      kap[s] = (kappa_J, kappa_H, J_eq) = (a_abs_s rho, (a_abs_s + a_scat_s) rho,
+      c_eq_s u): constant opacities per unit density (absorption plus elastic
+      scattering for kappa_H) and an equilibrium energy density proportional
+      to the gas energy.
+    The geometry (gamma_ij, sqrt(gamma)) comes from `geometry(prob)`."""
+    P = prob.P
+    shp = P.shape[1:]
+    gam, gami, sg = geometry(prob)
+    nsp = len(e0)
+    R = np.zeros((nsp, 4) + shp)
+    kap = np.zeros((nsp, 3) + shp)
+    cell = np.arange(int(np.prod(shp)), dtype=np.uint64).reshape(shp)
+    for s in range(nsp):
+        xi = uniform01(seed + 101 * s, cell)
+        xf = uniform01(seed + 101 * s + 1, cell)
+        th = np.arccos(1.0 - 2.0 * uniform01(seed + 101 * s + 2, cell))
+        ph = 2.0 * np.pi * uniform01(seed + 101 * s + 3, cell)
+        dirc = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+        E = e0[s] * (1.0 + 0.5 * xi)
+        norm = np.sqrt(np.einsum("i...,ij...,j...->...", dirc, gami, dirc))
+        F = (fmax * xf * E / norm)[None] * dirc
+        R[s, 0] = sg * E
+        R[s, 1:] = sg[None] * F
+        kap[s, 0] = a_abs[s] * P[0]
+        kap[s, 1] = (a_abs[s] + a_scat[s]) * P[0]
+        kap[s, 2] = c_eq[s] * P[4]
+    return R, kap
+
+
+def geometry(prob):
+    """gamma_ij, gamma^ij [3, 3, s3, s2, s1] and sqrt(gamma) at cell centres
+    (Minkowski or Kerr-Schild in x1 = ln r), for laying down input fields."""
+    shp = prob.shape
+    gam = np.zeros((3, 3) + shp)
+    if prob.metric_kind == MINKOWSKI:
+        for i in range(3):
+            gam[i, i] = 1.0
+    else:
+        r = np.exp(prob.centers(0))[None, None, :]
+        th = prob.centers(1)[None, :, None]
+        g11, g13, g22, g33 = _ks_gamma_ij(r, th, prob.a, prob.M)
+        gam[0, 0] = g11 + 0 * gam[0, 0]
+        gam[0, 2] = gam[2, 0] = g13 + 0 * gam[0, 0]
+        gam[1, 1] = g22 + 0 * gam[0, 0]
+        gam[2, 2] = g33 + 0 * gam[0, 0]
+    g = np.moveaxis(gam, (0, 1), (-2, -1))
+    gi = np.moveaxis(np.linalg.inv(g), (-2, -1), (0, 1))
+    sg = np.sqrt(np.abs(np.linalg.det(g)))
+    return gam, gi, sg
