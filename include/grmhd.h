@@ -274,7 +274,7 @@ int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
 enum { GRMHD_PROF_FLUX_X1 = 0, GRMHD_PROF_FLUX_X2 = 1, GRMHD_PROF_FLUX_X3 = 2,
        GRMHD_PROF_FLUX_PLANE = 3, GRMHD_PROF_UPDATE = 4, GRMHD_PROF_C2P = 5,
        GRMHD_PROF_GHOST = 6, GRMHD_PROF_BCC = 7, GRMHD_PROF_REDUCE = 8,
-       GRMHD_PROF_MLP = 9, GRMHD_PROF_NFAM = 10 };
+       GRMHD_PROF_MLP = 9, GRMHD_PROF_M1 = 10, GRMHD_PROF_NFAM = 11 };
 int grmhd_profile(grmhd_pack *pack, int enable);
 int grmhd_profile_read(grmhd_pack *pack, double *ms, long long *count);
 
@@ -308,6 +308,33 @@ int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const floa
 int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *feat_std,
                     const float *X, float *Y, int n, void *scratch, size_t scratch_bytes,
                     void *hip_stream);
+
+/*
+ * Gray M1 moments (Sec. 2.4): the implicit (backward-Euler) update of the
+ * collision sources of every interior cell, for nspecies neutrino species
+ * (1..8; the paper evolves three).  Per species and cell the Eulerian
+ * moments X = (E, F_1, F_2, F_3) solve
+ *   X - X* = dt S(X),  S_E = alpha^2 G^0,  S_Fi = alpha g_{i nu} G^nu,
+ *   G^nu = kappa_J u^nu (J_eq - J) - kappa_H H^nu,
+ * with J, H the fluid-frame energy and flux of the M1 stress tensor and the
+ * closure P^ij = (3 chi - 1)/2 P_thin + 3 (1 - chi)/2 P_thick, chi = (1 - 2f +
+ * 4f^2)/3 (maximum-entropy Fermi-Dirac at maximum packing), f = |F|/E; the
+ * opacities and J_eq are held fixed.  Newton's method with the exact
+ * Jacobian, |dX| <= tol (|X*| + |X|) (tol <= 0: 1e-13), at most max_iter
+ * (1..254) iterations.  The fluid velocity comes from the bound P.
+ *   R      device, [nspecies][4][ncell_total]: sqrt(gamma) (E, F_1, F_2, F_3)
+ *          (F_i covariant); X* on entry, the update on return (in place).
+ *   kappa  device, [nspecies][3][ncell_total]: kappa_J, kappa_H, J_eq.
+ *   couple 1: the fluid's U[4] (tau) and U[1..3] (S_i) take the opposite of
+ *          the exchanged energy and momentum (run grmhd_con2prim after).
+ *   iters  device uint8 [ncell_total] or NULL: the largest Newton count over
+ *          the species (255: a species did not converge; its moments are the
+ *          last iterate).
+ * Asynchronous on the pack's stream.
+ */
+int grmhd_m1_source(grmhd_pack *pack, const grmhd_metric *metric, double dt, int nspecies,
+                    void *R, const void *kappa, int couple, double tol, int max_iter,
+                    void *iters);
 
 const char *grmhd_last_error(const grmhd_pack *pack);
 

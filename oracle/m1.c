@@ -236,13 +236,17 @@ int orc_m1_implicit(const orc_geom *G, const double ut[3], const double Xs[4],
     }
     double b[4] = {-R[0], -R[1], -R[2], -R[3]}, d[4];
     if (solve4(A, b, d)) return -it;
-    double dn = 0.0;
+    double dn = 0.0, xn = 0.0;
     for (int k = 0; k < 4; ++k) {
       X[k] += d[k];
       dn += fabs(d[k]);
+      xn += fabs(X[k]);
     }
     (void)rn;
-    if (dn <= 1e-14 * scale) return it;   /* the next step is far below rounding */
+    /* the step against the larger of the input and the solution (which can
+       exceed the input by orders of magnitude where the emission dominates):
+       the next step is far below rounding */
+    if (dn <= 1e-14 * (scale + xn)) return it;
   }
   return -60;
 }

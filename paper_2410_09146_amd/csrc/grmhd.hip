@@ -19,6 +19,7 @@
 
 #include "../../include/grmhd.h"
 #include "kernels.h"
+#include "m1.h"
 
 using namespace grmhd;
 
@@ -1382,6 +1383,28 @@ int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *fe
   hipLaunchKernelGGL(k_mlp_infer, dim3((n + 63) / 64), dim3(64), 0, st, md, X, Y, n);
   hipError_t e = hipGetLastError();
   if (e) return fail(std::string("mlp infer: ") + hipGetErrorString(e), GRMHD_E_HIP);
+  return GRMHD_OK;
+}
+
+int grmhd_m1_source(grmhd_pack *p, const grmhd_metric *m, double dt, int nspecies, void *R,
+                    const void *kappa, int couple, double tol, int max_iter, void *iters)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (int rc = check_metric(p, m)) return rc;
+  if (!R || !kappa) return perr(p, "null moments or opacities", GRMHD_E_INVALID);
+  if (nspecies < 1 || nspecies > 8) return perr(p, "nspecies must be 1..8", GRMHD_E_INVALID);
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return perr(p, "dt must be finite and >= 0", GRMHD_E_INVALID);
+  if (max_iter < 1 || max_iter > 254) return perr(p, "max_iter must be 1..254", GRMHD_E_INVALID);
+  if (!(tol > 0.0)) tol = 1e-13;
+  KArgs a = p->args();
+  a.met.M = m->M; a.met.a = m->a;
+  const Plan &pl = p->plan;
+  Prof t(p, GRMHD_PROF_M1);
+  hipLaunchKernelGGL(k_m1_source, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                     dptr<int2>(p, pl.o_chi), nspecies, (double *)R, (const double *)kappa, dt,
+                     tol, max_iter, couple ? 1 : 0, (uint8_t *)iters,
+                     m->kind == GRMHD_METRIC_KS_LOGSPH ? (int)MK_KS : (int)MK_MINK);
+  LAUNCHCHK(p);
   return GRMHD_OK;
 }
 

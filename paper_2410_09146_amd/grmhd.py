@@ -64,11 +64,12 @@ EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_mlp_bind",
            "grmhd_mlp_scratch_bytes", "grmhd_mlp_grad", "grmhd_mlp_train_step",
            "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_set_tiling",
-           "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_last_error"]
+           "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_m1_source",
+           "grmhd_last_error"]
 NSHAPE = 5
 
 PROF_FAMILIES = ["flux_x1", "flux_x2", "flux_x3", "flux_plane", "update", "con2prim",
-                 "ghost", "bcc", "reduce", "mlp"]
+                 "ghost", "bcc", "reduce", "mlp", "m1"]
 MLP_NPARAM = 8834
 
 _lib = None
@@ -120,6 +121,8 @@ def lib():
         L.grmhd_mlp_infer.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
         L.grmhd_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_longlong)]
+        L.grmhd_m1_source.argtypes = [vp, ctypes.POINTER(Metric), ctypes.c_double, ctypes.c_int,
+                                      vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
         _lib = L
     return _lib
 
@@ -417,6 +420,55 @@ class Pack:
                 "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
                 "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean,
                 "guess_fallback": out.guess_fallback, "total_scalar": out.total_scalar}
+
+    def m1_source(self, R, kap, dt, couple=False, tol=1e-13, max_iter=40, iters=None):
+        """Implicit gray-M1 collision update (grmhd_m1_source).  R: float64
+        device tensor [nsp, 4, nct] (in place); kap: [nsp, 3, nct]; iters:
+        optional uint8 device tensor [nct]."""
+        for t in (R, kap):
+            if t.dtype != self.torch.float64 or not t.is_contiguous() or t.device != self.device:
+                raise GrmhdError("M1 arrays must be contiguous float64 on the pack's device")
+        if R.shape[0] != kap.shape[0] or R.shape[1:] != (4, self.nct) or kap.shape[1:] != (3, self.nct):
+            raise GrmhdError("M1 arrays must be [nsp, 4, nct] and [nsp, 3, nct]")
+        if iters is not None and (iters.dtype != self.torch.uint8 or iters.numel() < self.nct):
+            raise GrmhdError("iters must be a uint8 tensor of nct entries")
+        self._m1_keep = (R, kap, iters)
+        self._in()
+        _check(lib().grmhd_m1_source(self.h, ctypes.byref(self.metric), ctypes.c_double(dt),
+                                     int(R.shape[0]), R.data_ptr(), kap.data_ptr(), int(couple),
+                                     ctypes.c_double(tol), int(max_iter),
+                                     iters.data_ptr() if iters is not None else None), self.h)
+
+    def to_pack_layout(self, arr):
+        """Global padded numpy array [..., s3, s2, s1] of a single-level pack ->
+        host array [..., nct] in the pack's block layout (interiors and
+        ghosts of each block copied from the global array)."""
+        lead = arr.shape[:-3]
+        out = np.zeros(lead + (self.nct,))
+        for b in range(self.nb):
+            lo, n = self.lloc[b], self.nx[b]
+            g = self.ng
+            s = n + 2 * g
+            sl = tuple(slice(lo[2 - d], lo[2 - d] + s[2 - d]) for d in range(3))
+            blk = arr[(Ellipsis,) + sl]
+            o = self.offsets[b]
+            out[..., o:o + s[0] * s[1] * s[2]] = blk.reshape(lead + (-1,))
+        return out
+
+    def from_pack_layout(self, host, shape):
+        """Inverse of to_pack_layout for the block interiors: [..., nct] ->
+        global padded [..., s3, s2, s1] (ghosts of the global array zero)."""
+        lead = host.shape[:-1]
+        out = np.zeros(lead + tuple(shape))
+        g = self.ng
+        for b in range(self.nb):
+            lo, n = self.lloc[b], self.nx[b]
+            s = n + 2 * g
+            o = self.offsets[b]
+            blk = host[..., o:o + s[0] * s[1] * s[2]].reshape(lead + (s[2], s[1], s[0]))
+            out[(Ellipsis,) + tuple(slice(lo[2 - d] + g, lo[2 - d] + g + n[2 - d]) for d in range(3))] = \
+                blk[(Ellipsis, slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))]
+        return out
 
     def mlp_bind(self, params, mean, std):
         """params: float32 device tensor [MLP_NPARAM]; mean/std: float32 device [5]."""
