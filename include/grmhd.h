@@ -336,6 +336,46 @@ int grmhd_m1_source(grmhd_pack *pack, const grmhd_metric *metric, double dt, int
                     void *R, const void *kappa, int couple, double tol, int max_iter,
                     void *iters);
 
+/*
+ * Refinement of the two-level block mesh (the paper evolves on Parthenon's
+ * adaptive block mesh, Sec. 1 and 3; the operators are not given there).
+ *
+ * grmhd_tag: per block, the largest refinement indicator of P[var] over its
+ * interior cells, max over the directions of |q(i+1) - q(i-1)| / (2 |q(i)|)
+ * (directions with one cell skipped); needs filled ghosts.  block_max: host
+ * array of nblocks.  Synchronises the stream.
+ *
+ * grmhd_regrid_layout: the next layout from the current descriptor and host
+ * tags (+1 refine, -1 derefine, 0 keep): a level-0 block with tag +1 and even
+ * sizes becomes its 8 level-1 children (the same size in level-1 cells); 8
+ * level-1 blocks of one cubic size m at base + {0, m}^3 (base a multiple of
+ * 2m) that are all tagged -1 become one level-0 block of size m; any other
+ * level-1 block tagged -1 becomes the level-0 block over its region (half its
+ * size, when that is at least ng); every other block is kept, in order
+ * (children and merged blocks take the place of their first source block).  Host only.  *nb_out gets the new count; the
+ * arrays (cap blocks) get nx[3 nb], lloc[3 nb], level[nb]; GRMHD_E_SHAPE when
+ * cap is too small.
+ *
+ * grmhd_remap: the state of src (P, U, Bf, with its ghosts filled) onto the
+ * layout of dst (same root grid and boundaries, no scalar): identical blocks
+ * are copied whole; otherwise per cell copy, restriction (mean of 8) or
+ * prolongation (U by parent + MC-limited slopes toward the octant, keeping
+ * the mean and, where a child's D or tau would not stay positive, the parent
+ * value; P likewise as the inversion's start), per face copy, mean of 4 fine
+ * faces, or for new fine faces: the existing fine neighbour's face across a
+ * coarse face, else the coarse value, and inside each coarse cell the
+ * least-squares correction of the linear interpolation that makes its 8
+ * children divergence-free.  Then run grmhd_fill_ghosts, grmhd_con2prim and
+ * grmhd_fill_ghosts on dst.  scratch: device memory (256-byte aligned) of
+ * grmhd_remap_scratch_bytes(dst, src) bytes; src must not be written while
+ * the call runs (it synchronises dst's stream before returning).
+ */
+int grmhd_tag(grmhd_pack *pack, int var, double *block_max);
+int grmhd_regrid_layout(const grmhd_pack_desc *desc, const int *tags, int cap, int *nb_out,
+                        int *nx_out, int *lloc_out, int *level_out);
+size_t grmhd_remap_scratch_bytes(const grmhd_pack *dst, const grmhd_pack *src);
+int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, void *scratch, size_t scratch_bytes);
+
 const char *grmhd_last_error(const grmhd_pack *pack);
 
 #ifdef __cplusplus

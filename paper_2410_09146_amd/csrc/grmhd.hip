@@ -20,6 +20,7 @@
 #include "../../include/grmhd.h"
 #include "kernels.h"
 #include "m1.h"
+#include "amr.h"
 
 using namespace grmhd;
 
@@ -50,6 +51,10 @@ struct Plan {
   std::vector<FixF> fixF;          // level-boundary corrections (two-level meshes)
   std::vector<FixE> fixE;
   int maxlev = 0;
+  // host copies of the layout (regrid / remap)
+  std::vector<int> lev, lloc;     // per block; lloc in cells of the block's level
+  int root_nx[3] = {0, 0, 0};
+  int bc[6] = {0, 0, 0, 0, 0, 0};
   int active[3] = {1, 1, 1};
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
@@ -188,6 +193,15 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
           o = b;
         }
   }
+
+  p.lev.resize(p.nb);
+  p.lloc.resize(3 * (size_t)p.nb);
+  for (int b = 0; b < p.nb; ++b) {
+    p.lev[b] = lev_of(b);
+    for (int dd = 0; dd < 3; ++dd) p.lloc[3 * b + dd] = d->lloc[3 * b + dd];
+  }
+  for (int dd = 0; dd < 3; ++dd) p.root_nx[dd] = d->root_nx[dd];
+  for (int q = 0; q < 6; ++q) p.bc[q] = d->bc[q];
 
   // blocks and coordinate tables
   p.blocks.resize(p.nb);
@@ -887,6 +901,238 @@ void launch_flux_all(grmhd_pack *p, const KArgs &a, int rc, int fv, int rs, int 
   else launch_flux_rc<MK, double, 0>(p, a, rc, fv, rs);
 }
 
+// ---- refinement: block lookups over a plan and the remap maps
+
+Owner owner_of(const Plan &P)
+{
+  Owner o;
+  for (int d = 0; d < 3; ++d) {
+    int g = P.root_nx[d];
+    for (int b = 0; b < P.nb; ++b)
+      g = gcd(g, gcd(P.blocks[b].n[d] >> P.lev[b], P.lloc[3 * b + d] >> P.lev[b]));
+    o.g[d] = g;
+    o.dims[d] = P.root_nx[d] / g;
+  }
+  o.id.assign((size_t)o.dims[0] * o.dims[1] * o.dims[2], -1);
+  for (int b = 0; b < P.nb; ++b) {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = (P.lloc[3 * b + d] >> P.lev[b]) / o.g[d];
+      hi[d] = ((P.lloc[3 * b + d] + P.blocks[b].n[d]) >> P.lev[b]) / o.g[d];
+    }
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) o.id[x + (size_t)o.dims[0] * (y + (size_t)o.dims[1] * z)] = b;
+  }
+  return o;
+}
+
+// cell index of the level-lev(b) cell c (global, in the block's level units) in block b
+long long cell_at(const Plan &P, int b, const int c[3])
+{
+  const BlockInfo &bi = P.blocks[b];
+  long long i[3];
+  for (int d = 0; d < 3; ++d) i[d] = c[d] - P.lloc[3 * b + d] + P.ng;
+  return bi.off + i[0] + (long long)bi.s[0] * (i[1] + (long long)bi.s[1] * i[2]);
+}
+
+long long stride_of(const Plan &P, int b, int d)
+{
+  const BlockInfo &bi = P.blocks[b];
+  return d == 0 ? 1 : d == 1 ? (long long)bi.s[0] : (long long)bi.s[0] * bi.s[1];
+}
+
+struct RemapPlan {
+  std::vector<std::pair<int, int>> copies;   // (dst block, src block) identical
+  std::vector<RemapC> cells;
+  std::vector<RemapF> faces;
+  std::vector<RemapP> parents;
+  double M[96];
+  double id[3];
+  size_t o_cells = 0, o_faces = 0, o_par = 0, o_M = 0, total = 0;
+};
+
+// Minimum-norm operator of the 8 children's divergence constraints.
+void div_operator(const double id[3], double M[96])
+{
+  double D[8][12] = {{0}};
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) {
+        const int r = a + 2 * b + 4 * c;
+        D[r][b + 2 * c] = a ? -id[0] : id[0];
+        D[r][4 + a + 2 * c] = b ? -id[1] : id[1];
+        D[r][8 + a + 2 * b] = c ? -id[2] : id[2];
+      }
+  double A[8][16];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) {
+      double s = 1.0;
+      for (int k = 0; k < 12; ++k) s += D[i][k] * D[j][k];
+      A[i][j] = s;
+      A[i][8 + j] = i == j ? 1.0 : 0.0;
+    }
+  for (int c = 0; c < 8; ++c) {            // Gauss-Jordan (A is symmetric positive definite)
+    const double piv = A[c][c];
+    for (int k = 0; k < 16; ++k) A[c][k] /= piv;
+    for (int r = 0; r < 8; ++r)
+      if (r != c) {
+        const double f = A[r][c];
+        for (int k = 0; k < 16; ++k) A[r][k] -= f * A[c][k];
+      }
+  }
+  for (int u = 0; u < 12; ++u)
+    for (int v = 0; v < 8; ++v) {
+      double s = 0.0;
+      for (int k = 0; k < 8; ++k) s += D[k][u] * A[k][8 + v];
+      M[u * 8 + v] = s;
+    }
+}
+
+int build_remap(const Plan &Dp, const Plan &Sp, RemapPlan &R)
+{
+  for (int d = 0; d < 3; ++d)
+    if (Dp.root_nx[d] != Sp.root_nx[d]) return fail("remap needs the same root grid", GRMHD_E_SHAPE);
+  for (int q = 0; q < 6; ++q)
+    if (Dp.bc[q] != Sp.bc[q]) return fail("remap needs the same boundaries", GRMHD_E_SHAPE);
+  if (Dp.ng != Sp.ng) return fail("remap needs the same ghost depth", GRMHD_E_SHAPE);
+  const Owner so = owner_of(Sp);
+  const int ng = Dp.ng;
+  auto sblk = [&](int l, const int c[3]) -> int {
+    int c0[3];
+    for (int d = 0; d < 3; ++d) {
+      if (c[d] < 0 || c[d] >= (Sp.root_nx[d] << l)) return -1;
+      c0[d] = c[d];
+    }
+    return so.at(l, c0);
+  };
+  R.id[0] = R.id[1] = R.id[2] = 0.0;
+  for (int b = 0; b < Dp.nb; ++b)
+    if (Dp.lev[b] == 1) {
+      for (int d = 0; d < 3; ++d) R.id[d] = 1.0 / Dp.blocks[b].dx[d];
+      break;
+    }
+  for (int b = 0; b < Dp.nb; ++b) {
+    const BlockInfo &bi = Dp.blocks[b];
+    const int l = Dp.lev[b];
+    const int *L = &Dp.lloc[3 * b];
+    {
+      const int bs = sblk(l, L);
+      if (bs >= 0 && Sp.lev[bs] == l && Sp.lloc[3 * bs] == L[0] && Sp.lloc[3 * bs + 1] == L[1] &&
+          Sp.lloc[3 * bs + 2] == L[2] && Sp.blocks[bs].n[0] == bi.n[0] &&
+          Sp.blocks[bs].n[1] == bi.n[1] && Sp.blocks[bs].n[2] == bi.n[2]) {
+        R.copies.emplace_back(b, bs);
+        continue;
+      }
+    }
+    // cells
+    for (int k = 0; k < bi.n[2]; ++k)
+      for (int j = 0; j < bi.n[1]; ++j)
+        for (int i = 0; i < bi.n[0]; ++i) {
+          const int c[3] = {L[0] + i, L[1] + j, L[2] + k};
+          const int bs = sblk(l, c);
+          if (bs < 0) return fail("remap: a cell has no source block", GRMHD_E_SHAPE);
+          RemapC m{};
+          m.dst = cell_at(Dp, b, c);
+          m.sj = (int)stride_of(Sp, bs, 1);
+          m.sk = (int)stride_of(Sp, bs, 2);
+          if (Sp.lev[bs] == l) {
+            m.op = 0;
+            m.src = cell_at(Sp, bs, c);
+          } else if (l == 0) {
+            const int c2[3] = {2 * c[0], 2 * c[1], 2 * c[2]};
+            m.op = 2;
+            m.src = cell_at(Sp, bs, c2);
+          } else {
+            const int pc[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+            m.op = 1;
+            m.src = cell_at(Sp, bs, pc);
+            m.oct = (c[0] & 1) | ((c[1] & 1) << 1) | ((c[2] & 1) << 2);
+            for (int d = 0; d < 3; ++d) {
+              const int li = pc[d] - Sp.lloc[3 * bs + d];       // interior position
+              if (li > 0) m.inb |= 1 << (2 * d);
+              if (li < Sp.blocks[bs].n[d] - 1) m.inb |= 1 << (2 * d + 1);
+            }
+            // the neighbours of the parent are in the source block's ghosts
+            if (m.src - m.sk < Sp.blocks[bs].off ||
+                m.src + m.sk >= Sp.blocks[bs].off + (long long)m.sk * Sp.blocks[bs].s[2])
+              return fail("remap: prolongation stencil outside its block", GRMHD_E_SHAPE);
+          }
+          R.cells.push_back(m);
+          if (l == 1 && Sp.lev[bs] == 0 && !(c[0] & 1) && !(c[1] & 1) && !(c[2] & 1))
+            R.parents.push_back(RemapP{m.dst, (int)stride_of(Dp, b, 1), (int)stride_of(Dp, b, 2)});
+        }
+    // faces: along d the lower faces of the cells and the upper boundary face
+    for (int d = 0; d < 3; ++d) {
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      const int N = Dp.root_nx[d] << l;
+      const bool per = Dp.bc[2 * d] == GRMHD_BC_PERIODIC;
+      for (int k = 0; k < bi.n[2] + (d == 2); ++k)
+        for (int j = 0; j < bi.n[1] + (d == 1); ++j)
+          for (int i = 0; i < bi.n[0] + (d == 0); ++i) {
+            int cu[3] = {L[0] + i, L[1] + j, L[2] + k};      // cell above the face
+            int cl[3] = {cu[0], cu[1], cu[2]};
+            cl[d] -= 1;                                       // cell below
+            const bool upin = cu[d] < N;
+            const int *cs = upin ? cu : cl;                   // the in-domain cell looked up
+            const int bs = sblk(l, cs);
+            if (bs < 0) return fail("remap: a face has no source block", GRMHD_E_SHAPE);
+            RemapF f{};
+            f.comp = d;
+            f.dst = upin ? cell_at(Dp, b, cu) : cell_at(Dp, b, cl) + stride_of(Dp, b, d);
+            // lower face index of (this level's) cell cu in block bb, or the
+            // upper face of cl
+            auto face_in = [&](const Plan &P, int bb, const int *cup, const int *clo, bool up) {
+              return up ? cell_at(P, bb, cup) : cell_at(P, bb, clo) + stride_of(P, bb, d);
+            };
+            if (Sp.lev[bs] == l) {
+              f.op = 0;
+              f.src = face_in(Sp, bs, cu, cl, upin);
+            } else if (l == 0) {
+              // restriction: fine face 2 cu (or above fine cell 2 cl + e_d)
+              int fu[3] = {2 * cu[0], 2 * cu[1], 2 * cu[2]};
+              int fl[3] = {2 * cl[0], 2 * cl[1], 2 * cl[2]};
+              fl[d] += 1;
+              f.op = 1;
+              f.src = face_in(Sp, bs, fu, fl, upin);
+              f.st1 = stride_of(Sp, bs, t1);
+              f.st2 = stride_of(Sp, bs, t2);
+            } else {
+              if (cu[d] & 1) continue;                        // inside a parent: k_remap_div
+              // across the face: an existing fine cell gives its face
+              int co[3] = {upin ? cl[0] : cu[0], upin ? cl[1] : cu[1], upin ? cl[2] : cu[2]};
+              bool ok = true;
+              if (co[d] < 0 || co[d] >= N) {
+                if (per) co[d] = (co[d] + N) % N;
+                else ok = false;
+              }
+              const int bo = ok ? sblk(1, co) : -1;
+              if (bo >= 0 && Sp.lev[bo] == 1) {
+                f.op = 0;
+                // co is below the face when the looked-up cell is above it
+                f.src = upin ? cell_at(Sp, bo, co) + stride_of(Sp, bo, d) : cell_at(Sp, bo, co);
+              } else {
+                const int pu[3] = {cu[0] >> 1, cu[1] >> 1, cu[2] >> 1};
+                const int pl[3] = {cl[0] >> 1, cl[1] >> 1, cl[2] >> 1};
+                f.op = 0;
+                f.src = face_in(Sp, bs, pu, pl, upin);
+              }
+            }
+            R.faces.push_back(f);
+          }
+    }
+  }
+  div_operator(R.id, R.M);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { const size_t at = o; o += align_up(bytes); return at; };
+  R.o_cells = take(sizeof(RemapC) * R.cells.size());
+  R.o_faces = take(sizeof(RemapF) * R.faces.size());
+  R.o_par = take(sizeof(RemapP) * R.parents.size());
+  R.o_M = take(sizeof(double) * 96);
+  R.total = o;
+  return GRMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1405,6 +1651,153 @@ int grmhd_m1_source(grmhd_pack *p, const grmhd_metric *m, double dt, int nspecie
                      tol, max_iter, couple ? 1 : 0, (uint8_t *)iters,
                      m->kind == GRMHD_METRIC_KS_LOGSPH ? (int)MK_KS : (int)MK_MINK);
   LAUNCHCHK(p);
+  return GRMHD_OK;
+}
+
+int grmhd_tag(grmhd_pack *p, int var, double *block_max)
+{
+  if (!p || !block_max) return GRMHD_E_INVALID;
+  if (var < 0 || var >= p->args().npv) return perr(p, "bad tag variable", GRMHD_E_INVALID);
+  const Plan &pl = p->plan;
+  KArgs a = p->args();
+  double *part = (double *)(p->ws + pl.o_part);
+  hipLaunchKernelGGL(k_tag, dim3(pl.ch_int.size()), dim3(256), 0, p->stream, a,
+                     dptr<int2>(p, pl.o_chi), var, part);
+  LAUNCHCHK(p);
+  std::vector<double> h(pl.ch_int.size());
+  HIPCHK(p, hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(p, hipStreamSynchronize(p->stream));
+  for (int b = 0; b < pl.nb; ++b) block_max[b] = 0.0;
+  for (size_t c = 0; c < h.size(); ++c)
+    block_max[pl.ch_int[c].x] = std::max(block_max[pl.ch_int[c].x], h[c]);
+  return GRMHD_OK;
+}
+
+int grmhd_regrid_layout(const grmhd_pack_desc *desc, const int *tags, int cap, int *nb_out,
+                        int *nx_out, int *lloc_out, int *level_out)
+{
+  if (!desc || !tags || !nb_out) return fail("null argument", GRMHD_E_INVALID);
+  if (int rc = validate(desc)) return rc;
+  const int nb = desc->nblocks;
+  auto lev = [&](int b) { return desc->level ? desc->level[b] : 0; };
+  std::vector<int> onx, oll, olv;
+  auto emit = [&](int l, const int *n, const int *ll) {
+    for (int d = 0; d < 3; ++d) { onx.push_back(n[d]); oll.push_back(ll[d]); }
+    olv.push_back(l);
+  };
+  // sibling groups of level-1 blocks: 8 blocks of one size m at base + {0, m}^3,
+  // base a multiple of 2m
+  std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> groups;
+  for (int b = 0; b < nb; ++b) {
+    if (lev(b) != 1) continue;
+    const int *n = desc->nx + 3 * b, *ll = desc->lloc + 3 * b;
+    if (n[0] != n[1] || n[1] != n[2]) continue;
+    const int m = n[0];
+    groups[std::make_tuple(m, ll[0] - ll[0] % (2 * m), ll[1] - ll[1] % (2 * m),
+                           ll[2] - ll[2] % (2 * m), 0, 0)].push_back(b);
+  }
+  std::vector<int> gleader(nb, -1);     // -2: merged into its group's leader
+  for (auto &kv : groups) {
+    auto &v = kv.second;
+    if (v.size() != 8) continue;
+    bool all = true;
+    for (int b : v) all = all && tags[b] < 0;
+    if (!all) continue;
+    const int lead = *std::min_element(v.begin(), v.end());
+    for (int b : v) gleader[b] = b == lead ? lead : -2;
+  }
+  for (int b = 0; b < nb; ++b) {
+    const int *n = desc->nx + 3 * b, *ll = desc->lloc + 3 * b;
+    if (lev(b) == 0 && tags[b] > 0 && !(n[0] & 1) && !(n[1] & 1) && !(n[2] & 1)) {
+      for (int z = 0; z < 2; ++z)
+        for (int y = 0; y < 2; ++y)
+          for (int x = 0; x < 2; ++x) {
+            const int cl[3] = {2 * ll[0] + x * n[0], 2 * ll[1] + y * n[1], 2 * ll[2] + z * n[2]};
+            emit(1, n, cl);
+          }
+    } else if (gleader[b] == b) {
+      const int m = n[0];
+      const int cl[3] = {(ll[0] - ll[0] % (2 * m)) / 2, (ll[1] - ll[1] % (2 * m)) / 2,
+                         (ll[2] - ll[2] % (2 * m)) / 2};
+      const int cn[3] = {m, m, m};
+      emit(0, cn, cl);
+    } else if (lev(b) == 1 && tags[b] < 0 && gleader[b] != -2 && n[0] / 2 >= desc->ng &&
+               n[1] / 2 >= desc->ng && n[2] / 2 >= desc->ng) {
+      const int cn[3] = {n[0] / 2, n[1] / 2, n[2] / 2};
+      const int cl[3] = {ll[0] / 2, ll[1] / 2, ll[2] / 2};
+      emit(0, cn, cl);
+    } else if (gleader[b] != -2) {
+      emit(lev(b), n, ll);
+    }
+  }
+  *nb_out = (int)olv.size();
+  if ((int)olv.size() > cap || !nx_out || !lloc_out || !level_out)
+    return fail("regrid: output capacity too small", GRMHD_E_SHAPE);
+  std::copy(onx.begin(), onx.end(), nx_out);
+  std::copy(oll.begin(), oll.end(), lloc_out);
+  std::copy(olv.begin(), olv.end(), level_out);
+  return GRMHD_OK;
+}
+
+size_t grmhd_remap_scratch_bytes(const grmhd_pack *dst, const grmhd_pack *src)
+{
+  if (!dst || !src) return 0;
+  RemapPlan R;
+  if (build_remap(dst->plan, src->plan, R)) return 0;
+  return R.total;
+}
+
+int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, void *scratch, size_t scratch_bytes)
+{
+  if (!dst || !src || !scratch) return perr(dst, "null argument", GRMHD_E_INVALID);
+  if (dst->desc.nscalar || src->desc.nscalar)
+    return perr(dst, "remap carries no passive scalar", GRMHD_E_UNSUPPORTED);
+  if ((uintptr_t)scratch % ALIGN) return perr(dst, "scratch must be 256-byte aligned", GRMHD_E_INVALID);
+  RemapPlan R;
+  if (int rc = build_remap(dst->plan, src->plan, R)) return perr(dst, g_err, rc);
+  if (scratch_bytes < R.total) return perr(dst, "remap scratch too small", GRMHD_E_SHAPE);
+  char *w = (char *)scratch;
+  hipStream_t st = dst->stream;
+  const Plan &Dp = dst->plan, &Sp = src->plan;
+  auto up = [&](size_t off, const void *h, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpyAsync(w + off, h, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HIPCHK(dst, up(R.o_cells, R.cells.data(), sizeof(RemapC) * R.cells.size()));
+  HIPCHK(dst, up(R.o_faces, R.faces.data(), sizeof(RemapF) * R.faces.size()));
+  HIPCHK(dst, up(R.o_par, R.parents.data(), sizeof(RemapP) * R.parents.size()));
+  HIPCHK(dst, up(R.o_M, R.M, sizeof(double) * 96));
+  RemapArgs ra;
+  ra.sP = (const double *)src->st.P; ra.sU = (const double *)src->st.U;
+  ra.sBf = (const double *)src->st.Bf;
+  ra.dP = (double *)dst->st.P; ra.dU = (double *)dst->st.U; ra.dBf = (double *)dst->st.Bf;
+  ra.snct = Sp.nct; ra.dnct = Dp.nct;
+  // identical blocks: whole padded blocks, every plane
+  for (const auto &cp : R.copies) {
+    const BlockInfo &db = Dp.blocks[cp.first], &sb = Sp.blocks[cp.second];
+    const size_t cnt = (size_t)db.s[0] * db.s[1] * db.s[2] * sizeof(double);
+    for (int q = 0; q < 5; ++q) {
+      HIPCHK(dst, hipMemcpyAsync(ra.dP + q * ra.dnct + db.off, ra.sP + q * ra.snct + sb.off, cnt,
+                                 hipMemcpyDeviceToDevice, st));
+      HIPCHK(dst, hipMemcpyAsync(ra.dU + q * ra.dnct + db.off, ra.sU + q * ra.snct + sb.off, cnt,
+                                 hipMemcpyDeviceToDevice, st));
+    }
+    for (int q = 0; q < 3; ++q)
+      HIPCHK(dst, hipMemcpyAsync(ra.dBf + q * ra.dnct + db.off, ra.sBf + q * ra.snct + sb.off, cnt,
+                                 hipMemcpyDeviceToDevice, st));
+  }
+  if (!R.cells.empty())
+    hipLaunchKernelGGL(k_remap_cells, dim3((R.cells.size() + 255) / 256), dim3(256), 0, st, ra,
+                       (const RemapC *)(w + R.o_cells), (int)R.cells.size());
+  if (!R.faces.empty())
+    hipLaunchKernelGGL(k_remap_faces, dim3((R.faces.size() + 255) / 256), dim3(256), 0, st, ra,
+                       (const RemapF *)(w + R.o_faces), (int)R.faces.size());
+  if (!R.parents.empty())
+    hipLaunchKernelGGL(k_remap_div, dim3((R.parents.size() + 255) / 256), dim3(256), 0, st, ra,
+                       (const RemapP *)(w + R.o_par), (int)R.parents.size(),
+                       (const double *)(w + R.o_M), R.id[0], R.id[1], R.id[2]);
+  LAUNCHCHK(dst);
+  // the host maps must outlive their copies
+  HIPCHK(dst, hipStreamSynchronize(st));
   return GRMHD_OK;
 }
 

@@ -65,6 +65,7 @@ EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_mlp_scratch_bytes", "grmhd_mlp_grad", "grmhd_mlp_train_step",
            "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_set_tiling",
            "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_m1_source",
+           "grmhd_tag", "grmhd_regrid_layout", "grmhd_remap_scratch_bytes", "grmhd_remap",
            "grmhd_last_error"]
 NSHAPE = 5
 
@@ -123,6 +124,12 @@ def lib():
                                          ctypes.POINTER(ctypes.c_longlong)]
         L.grmhd_m1_source.argtypes = [vp, ctypes.POINTER(Metric), ctypes.c_double, ctypes.c_int,
                                       vp, vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, vp]
+        L.grmhd_tag.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.grmhd_regrid_layout.argtypes = [ctypes.POINTER(PackDesc), ip, ctypes.c_int, ip, ip, ip, ip]
+        L.grmhd_remap_scratch_bytes.argtypes = [vp, vp]
+        L.grmhd_remap_scratch_bytes.restype = ctypes.c_size_t
+        L.grmhd_remap.argtypes = [vp, vp, vp, ctypes.c_size_t]
         _lib = L
     return _lib
 
@@ -135,6 +142,20 @@ def _check(rc, pack=None):
     if rc != OK:
         msg = lib().grmhd_last_error(pack).decode()
         raise GrmhdError(f"grmhd error {rc}: {msg}")
+
+
+def regrid_layout(pack, tags):
+    """Next (nx, lloc, level) from a pack's layout and per-block tags (+1
+    refine, -1 derefine, 0 keep), by grmhd_regrid_layout."""
+    tags = np.asarray(tags, dtype=np.int32)
+    cap = 8 * pack.nb + 8
+    ip = ctypes.c_int
+    nb = ip()
+    nx, ll, lv = (ip * (3 * cap))(), (ip * (3 * cap))(), (ip * cap)()
+    t = (ip * pack.nb)(*tags.tolist())
+    _check(lib().grmhd_regrid_layout(ctypes.byref(pack.desc), t, cap, ctypes.byref(nb), nx, ll, lv))
+    n = nb.value
+    return list(nx[:3 * n]), list(ll[:3 * n]), list(lv[:n])
 
 
 def block_split(n, nblk):
@@ -469,6 +490,36 @@ class Pack:
             out[(Ellipsis,) + tuple(slice(lo[2 - d] + g, lo[2 - d] + g + n[2 - d]) for d in range(3))] = \
                 blk[(Ellipsis, slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))]
         return out
+
+    def tag(self, var=0):
+        """Per-block refinement indicator of P[var] (grmhd_tag)."""
+        self._in()
+        out = (ctypes.c_double * self.nb)()
+        _check(lib().grmhd_tag(self.h, int(var), out), self.h)
+        return np.array(out[:])
+
+    def layout(self):
+        """(nx, lloc, level) flat lists of this pack."""
+        return (self.nx.ravel().tolist(), self.lloc.ravel().tolist(), self.level.tolist())
+
+    def remap_from(self, src, guess=GUESS_PREV):
+        """Take src's state onto this pack's layout (grmhd_remap), then fill
+        ghosts, invert and fill ghosts again."""
+        torch = self.torch
+        src._out()
+        self._out()
+        torch.cuda.synchronize(self.device)
+        L = lib()
+        nbytes = L.grmhd_remap_scratch_bytes(self.h, src.h)
+        if nbytes == 0:
+            _check(-2, None)
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (scratch.data_ptr() + 255) // 256 * 256
+        _check(L.grmhd_remap(self.h, src.h, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)), self.h)
+        del scratch
+        self.fill_ghosts()
+        self.con2prim(guess)
+        self.fill_ghosts()
 
     def mlp_bind(self, params, mean, std):
         """params: float32 device tensor [MLP_NPARAM]; mean/std: float32 device [5]."""
