@@ -358,14 +358,15 @@ int grmhd_m1_source(grmhd_pack *pack, const grmhd_metric *metric, double dt, int
  *
  * grmhd_remap: the state of src (P, U, Bf, with its ghosts filled) onto the
  * layout of dst (same root grid and boundaries, no scalar): identical blocks
- * are copied whole; otherwise per cell copy, restriction (mean of 8) or
- * prolongation (U by parent + MC-limited slopes toward the octant, keeping
- * the mean and, where a child's D or tau would not stay positive, the parent
- * value; P likewise as the inversion's start), per face copy, mean of 4 fine
- * faces, or for new fine faces: the existing fine neighbour's face across a
- * coarse face, else the coarse value, and inside each coarse cell the
- * least-squares correction of the linear interpolation that makes its 8
- * children divergence-free.  Then run grmhd_fill_ghosts, grmhd_con2prim and
+ * are copied whole; otherwise per cell copy or restriction (mean of 8) of P
+ * and U, or prolongation (P by parent + MC-limited slopes toward the octant,
+ * a non-positive rho or u keeping the parent value; U = U(P, B) of each child
+ * plus the parent's U minus the mean over its 8 children, which keeps the
+ * totals), per face copy, mean of 4 fine faces, or for new fine faces: the
+ * existing fine neighbour's face across a coarse face, else the coarse
+ * value, and inside each coarse cell the least-squares correction of the
+ * linear interpolation that makes its 8 children divergence-free.  metric
+ * and eos serve U(P, B).  Then run grmhd_fill_ghosts, grmhd_con2prim and
  * grmhd_fill_ghosts on dst.  scratch: device memory (256-byte aligned) of
  * grmhd_remap_scratch_bytes(dst, src) bytes; src must not be written while
  * the call runs (it synchronises dst's stream before returning).
@@ -374,7 +375,8 @@ int grmhd_tag(grmhd_pack *pack, int var, double *block_max);
 int grmhd_regrid_layout(const grmhd_pack_desc *desc, const int *tags, int cap, int *nb_out,
                         int *nx_out, int *lloc_out, int *level_out);
 size_t grmhd_remap_scratch_bytes(const grmhd_pack *dst, const grmhd_pack *src);
-int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, void *scratch, size_t scratch_bytes);
+int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, const grmhd_metric *metric,
+                const grmhd_eos *eos, void *scratch, size_t scratch_bytes);
 
 const char *grmhd_last_error(const grmhd_pack *pack);
 

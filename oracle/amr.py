@@ -13,11 +13,11 @@ Parthenon's refinement):
     its size, if that is at least the ghost depth); other blocks kept, in
     order, children and merged blocks at the place of their first source;
   * remap per cell: copy from the block of the same level, mean of the 8
-    children, or parent + monotonized-central slopes toward the octant (U:
-    mean-preserving, the parent value in all children where D or tau would
-    not stay positive, a neighbour outside the source block's interior
-    counting as the parent since U has no ghost zones; P from its ghosts,
-    the parent where rho or u would not stay positive);
+    children, or, for new fine cells, P by parent + monotonized-central
+    slopes toward the octant (from its ghosts; the parent where rho or u
+    would not stay positive) and U = U(P, B) of each child with the new face
+    field plus the parent's U minus the mean of its 8 children (the totals
+    are kept);
   * remap per face: copy, mean of the 4 fine faces, or (new fine faces) the
     face of an existing fine cell across a coarse face, else the coarse
     value; the 12 faces inside a coarse cell: the linear interpolation
@@ -149,6 +149,7 @@ def remap(src, level, nx, lloc):
         return src.Bf[bs][comp, ijk[2], ijk[1], ijk[0]]
 
     Ps, Us, Bs = [], [], []
+    parents = []           # (dst block, k, j, i of child (0,0,0), parent U)
     fine_dx = None
     for b in range(len(level)):
         if level[b] == 1:
@@ -177,26 +178,19 @@ def remap(src, level, nx, lloc):
                         pc = [v // 2 for v in c]
                         kk, jj, ii = loc(bs, pc, 0)
                         octv = [c[d] & 1 for d in range(3)]
-                        inner = [(pc[d] - sll[bs][d] > 0, pc[d] - sll[bs][d] < src.nx[bs][d] - 1)
-                                 for d in range(3)]
                         for q in range(5):
-                            for arr, out, isU in ((src.P[bs][q], P, False), (src.U[bs][q], U, True)):
-                                c0 = arr[kk, jj, ii]
-                                nb_ = {0: (arr[kk, jj, ii - 1], arr[kk, jj, ii + 1]),
-                                       1: (arr[kk, jj - 1, ii], arr[kk, jj + 1, ii]),
-                                       2: (arr[kk - 1, jj, ii], arr[kk + 1, jj, ii])}
-                                if isU:          # U has no ghosts: outside the interior = parent
-                                    nb_ = {d: (nb_[d][0] if inner[d][0] else c0,
-                                               nb_[d][1] if inner[d][1] else c0) for d in range(3)}
-                                sl = [mc(c0 - nb_[d][0], nb_[d][1] - c0) for d in range(3)]
-                                v = c0 + 0.25 * sum(sl[d] if octv[d] else -sl[d] for d in range(3))
-                                if q in (0, 4):
-                                    if isU:
-                                        if not (c0 - 0.25 * sum(abs(x) for x in sl) > 0.0):
-                                            v = c0
-                                    elif not (v > 0.0) or not np.isfinite(v):
-                                        v = c0
-                                out[(q, g + k, g + j, g + i)] = v
+                            arr = src.P[bs][q]
+                            c0 = arr[kk, jj, ii]
+                            nb_ = {0: (arr[kk, jj, ii - 1], arr[kk, jj, ii + 1]),
+                                   1: (arr[kk, jj - 1, ii], arr[kk, jj + 1, ii]),
+                                   2: (arr[kk - 1, jj, ii], arr[kk + 1, jj, ii])}
+                            sl = [mc(c0 - nb_[d][0], nb_[d][1] - c0) for d in range(3)]
+                            v = c0 + 0.25 * sum(sl[d] if octv[d] else -sl[d] for d in range(3))
+                            if q in (0, 4) and (not (v > 0.0) or not np.isfinite(v)):
+                                v = c0
+                            P[(q, g + k, g + j, g + i)] = v
+                        if not any(octv):
+                            parents.append((b, k, j, i, src.U[bs][:, kk, jj, ii].copy()))
         # faces
         N = [root.n[d] << l for d in range(3)]
         for d in range(3):
@@ -299,6 +293,15 @@ def remap(src, level, nx, lloc):
         Ps.append(P)
         Us.append(U)
         Bs.append(B)
+    if parents:
+        # refined cells: U(P, B) of each child plus the parent's excess over
+        # the children's mean
+        import oracle as _o
+        tmp = _o.Mesh(root, level, nx.ravel(), lloc.ravel(), Ps, Bs, correct=False)
+        for b, k, j, i, up in parents:
+            sl = (slice(None), slice(g + k, g + k + 2), slice(g + j, g + j + 2), slice(g + i, g + i + 2))
+            kids = tmp.U[b][sl]
+            Us[b][sl] = kids + (up - kids.mean(axis=(1, 2, 3)))[:, None, None, None]
     return Ps, Us, Bs
 
 

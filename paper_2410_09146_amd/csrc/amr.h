@@ -2,12 +2,12 @@
 // a state from one block layout onto another (blocks copied, refined or
 // derefined).  Included once, by grmhd.hip (after kernels.h).
 //
-// Refined cells: the conserved U by parent + monotonized-central slopes
-// toward the child's octant (the mean of the 8 children is the parent, so the
-// totals are kept; D or tau that a child would take non-positive keeps the
-// parent value in all 8; U has no ghost zones, so a neighbour outside the
-// source block's interior counts as the parent), P likewise from its filled
-// ghosts (only the inversion's starting point).
+// Refined cells: P by parent + monotonized-central slopes toward the
+// child's octant (from its filled ghosts; a non-positive rho or u keeps the
+// parent value), then U = U(P, B) of each child with the new face field,
+// plus the parent's U minus the children's mean (the same for all 8), so the
+// totals are kept and each child's U matches its field's energy and
+// momentum.
 // Refined faces: on a coarse face the fine faces copy the fine neighbour's
 // where an existing fine block lies across, else the coarse value; the 12
 // faces inside a coarse cell start from the mean of the two outer faces
@@ -24,7 +24,7 @@ namespace grmhd {
 // the source block (U is read there; P, whose ghosts are filled, always)
 struct RemapC { long long dst, src; int op, oct, sj, sk, inb, pad; };
 struct RemapF { long long dst, src, st1, st2; int comp, op; }; // op 0 copy, 1 mean of 4 faces
-struct RemapP { long long dst0; int sj, sk; };                // refined parent: child (0,0,0)
+struct RemapP { long long dst0, src; int sj, sk; };           // refined parent: child (0,0,0), source cell
 
 struct RemapArgs {
   const double *sP, *sU, *sBf;
@@ -106,7 +106,30 @@ __global__ __launch_bounds__(256) void k_remap_cells(RemapArgs r, const RemapC *
       vu = ((q == 0 || q == 4) && !(u0 - 0.25 * absu > 0.0)) ? u0 : u0 + 0.25 * sumu;
     }
     r.dP[q * r.dnct + m.dst] = vp;
-    r.dU[q * r.dnct + m.dst] = vu;
+    if (m.op != 1) r.dU[q * r.dnct + m.dst] = vu;
+  }
+}
+
+// Refined cells: U = U(P) of each child (computed by k_p2c) plus the
+// parent's excess over the children's mean, so that the 8 children keep the
+// parent's conserved content.
+__global__ __launch_bounds__(256) void k_remap_cons(RemapArgs r, const RemapP *__restrict__ map,
+                                                    int n)
+{
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const RemapP m = map[e];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    double *u = r.dU + q * r.dnct + m.dst0;
+    double acc = 0.0;
+    for (int z = 0; z < 2; ++z)
+      for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x) acc += u[x + y * (long long)m.sj + z * (long long)m.sk];
+    const double dlt = r.sU[q * r.snct + m.src] - 0.125 * acc;
+    for (int z = 0; z < 2; ++z)
+      for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x) u[x + y * (long long)m.sj + z * (long long)m.sk] += dlt;
   }
 }
 

@@ -1060,7 +1060,7 @@ int build_remap(const Plan &Dp, const Plan &Sp, RemapPlan &R)
           }
           R.cells.push_back(m);
           if (l == 1 && Sp.lev[bs] == 0 && !(c[0] & 1) && !(c[1] & 1) && !(c[2] & 1))
-            R.parents.push_back(RemapP{m.dst, (int)stride_of(Dp, b, 1), (int)stride_of(Dp, b, 2)});
+            R.parents.push_back(RemapP{m.dst, m.src, (int)stride_of(Dp, b, 1), (int)stride_of(Dp, b, 2)});
         }
     // faces: along d the lower faces of the cells and the upper boundary face
     for (int d = 0; d < 3; ++d) {
@@ -1747,9 +1747,12 @@ size_t grmhd_remap_scratch_bytes(const grmhd_pack *dst, const grmhd_pack *src)
   return R.total;
 }
 
-int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, void *scratch, size_t scratch_bytes)
+int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, const grmhd_metric *metric,
+                const grmhd_eos *eos, void *scratch, size_t scratch_bytes)
 {
   if (!dst || !src || !scratch) return perr(dst, "null argument", GRMHD_E_INVALID);
+  if (int rc = check_metric(dst, metric)) return rc;
+  if (int rc = check_eos(dst, eos)) return rc;
   if (dst->desc.nscalar || src->desc.nscalar)
     return perr(dst, "remap carries no passive scalar", GRMHD_E_UNSUPPORTED);
   if ((uintptr_t)scratch % ALIGN) return perr(dst, "scratch must be 256-byte aligned", GRMHD_E_INVALID);
@@ -1791,10 +1794,34 @@ int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, void *scratch, size_t sc
   if (!R.faces.empty())
     hipLaunchKernelGGL(k_remap_faces, dim3((R.faces.size() + 255) / 256), dim3(256), 0, st, ra,
                        (const RemapF *)(w + R.o_faces), (int)R.faces.size());
-  if (!R.parents.empty())
+  if (!R.parents.empty()) {
     hipLaunchKernelGGL(k_remap_div, dim3((R.parents.size() + 255) / 256), dim3(256), 0, st, ra,
                        (const RemapP *)(w + R.o_par), (int)R.parents.size(),
                        (const double *)(w + R.o_M), R.id[0], R.id[1], R.id[2]);
+    // refined cells: U of the new P and field, then the parents' content
+    KArgs a = dst->args();
+    a.met.M = metric->M; a.met.a = metric->a;
+    fill_eos(a, eos);
+    if (metric->kind == GRMHD_METRIC_KS_LOGSPH)
+      hipLaunchKernelGGL((k_p2c<MK_KS, 0>), dim3(Dp.ch_int.size()), dim3(256), 0, st, a,
+                         dptr<int2>(dst, Dp.o_chi));
+    else
+      hipLaunchKernelGGL((k_p2c<MK_MINK, 0>), dim3(Dp.ch_int.size()), dim3(256), 0, st, a,
+                         dptr<int2>(dst, Dp.o_chi));
+    // copied and restricted cells take their U again
+    if (!R.cells.empty())
+      hipLaunchKernelGGL(k_remap_cells, dim3((R.cells.size() + 255) / 256), dim3(256), 0, st, ra,
+                         (const RemapC *)(w + R.o_cells), (int)R.cells.size());
+    for (const auto &cp : R.copies) {
+      const BlockInfo &db = Dp.blocks[cp.first], &sb = Sp.blocks[cp.second];
+      const size_t cnt = (size_t)db.s[0] * db.s[1] * db.s[2] * sizeof(double);
+      for (int q = 0; q < 5; ++q)
+        HIPCHK(dst, hipMemcpyAsync(ra.dU + q * ra.dnct + db.off, ra.sU + q * ra.snct + sb.off, cnt,
+                                   hipMemcpyDeviceToDevice, st));
+    }
+    hipLaunchKernelGGL(k_remap_cons, dim3((R.parents.size() + 255) / 256), dim3(256), 0, st, ra,
+                       (const RemapP *)(w + R.o_par), (int)R.parents.size());
+  }
   LAUNCHCHK(dst);
   // the host maps must outlive their copies
   HIPCHK(dst, hipStreamSynchronize(st));

@@ -129,7 +129,8 @@ def lib():
         L.grmhd_regrid_layout.argtypes = [ctypes.POINTER(PackDesc), ip, ctypes.c_int, ip, ip, ip, ip]
         L.grmhd_remap_scratch_bytes.argtypes = [vp, vp]
         L.grmhd_remap_scratch_bytes.restype = ctypes.c_size_t
-        L.grmhd_remap.argtypes = [vp, vp, vp, ctypes.c_size_t]
+        L.grmhd_remap.argtypes = [vp, vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos), vp,
+                                  ctypes.c_size_t]
         _lib = L
     return _lib
 
@@ -515,7 +516,8 @@ class Pack:
             _check(-2, None)
         scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         ptr = (scratch.data_ptr() + 255) // 256 * 256
-        _check(L.grmhd_remap(self.h, src.h, ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)), self.h)
+        _check(L.grmhd_remap(self.h, src.h, ctypes.byref(self.metric), ctypes.byref(self.eos),
+                             ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes)), self.h)
         del scratch
         self.fill_ghosts()
         self.con2prim(guess)

@@ -55,7 +55,8 @@ def _raw_remap(G, dst, src):
     assert nb > 0, L.grmhd_last_error(None)
     s = torch.empty(nb + 256, dtype=torch.uint8, device=dst.device)
     ptr = (s.data_ptr() + 255) // 256 * 256
-    G._check(L.grmhd_remap(dst.h, src.h, ctypes.c_void_p(ptr), ctypes.c_size_t(nb)), dst.h)
+    G._check(L.grmhd_remap(dst.h, src.h, ctypes.byref(dst.metric), ctypes.byref(dst.eos),
+                           ctypes.c_void_p(ptr), ctypes.c_size_t(nb)), dst.h)
     torch.cuda.synchronize()
 
 
@@ -154,7 +155,8 @@ def test_regrid_cycle_matches_oracle(G):
         np.abs(r1["totals"] - r0["totals"]).max() / np.abs(r0["totals"]).max(),
         "divb", r1["divb_rel"], "c2p fail", r1["c2p_fail"], "floors", r1["floor_hits"])
     assert r1["divb_rel"] < 1e-12
-    assert r1["floor_hits"] > 0 or np.allclose(r1["totals"], r0["totals"], rtol=1e-12)
+    assert r1["floor_hits"] == 0 and r1["c2p_fail"] == 0
+    assert np.abs(r1["totals"] - r0["totals"]).max() <= 1e-13 * np.abs(r0["totals"]).max()
     for s in range(2):
         dt = mesh2.dt()
         mesh2.step(dt)

@@ -137,8 +137,9 @@ def test_refine_then_derefine_returns_the_state():
 
 
 def test_prolongation_of_linear_data_is_exact():
-    """Linear U and P: the MC slopes are the exact gradient, so the children
-    take the linear function at their centres."""
+    """Linear P: the MC slopes are the exact gradient, so the children take
+    the linear function at their centres; the children's U keep the parent's
+    U on average."""
     mesh = _box_mesh(set())
     g = 4
     h = mesh.root.dx
@@ -148,12 +149,12 @@ def test_prolongation_of_linear_data_is_exact():
         Z, Y, X = np.meshgrid(*[(np.arange(s[2 - d]) - g + mesh.lloc[b][2 - d] + 0.5) * h[2 - d]
                                 for d in range(3)], indexing="ij")
         for q in range(5):
-            lin = 2.0 + 0.3 * X - 0.2 * Y + 0.1 * Z + 0.05 * q
-            mesh.P[b][q] = lin
-            mesh.U[b][q] = lin
+            mesh.P[b][q] = 1.0 + 0.03 * X - 0.02 * Y + 0.01 * Z + (0.0 if q in (0, 4) else -0.9)
+        mesh.U[b] = mesh.blocks[b].prim_to_cons(mesh.P[b], mesh.Bf[b])
     lev, nx, ll = mesh.level.tolist(), mesh.nx.ravel().tolist(), mesh.lloc.ravel().tolist()
     nx2, ll2, lv2 = amr.regrid_layout(lev, nx, ll, [1] + [0] * (len(lev) - 1))
     P, U, B = amr.remap(mesh, lv2, nx2, ll2)
+    n0 = mesh.nx[0]
     for b, (l, n, L) in enumerate(zip(lv2, np.reshape(nx2, (-1, 3)), np.reshape(ll2, (-1, 3)))):
         if l != 1:
             continue
@@ -161,17 +162,16 @@ def test_prolongation_of_linear_data_is_exact():
         Z, Y, X = np.meshgrid(*[(np.arange(n[2 - d]) + L[2 - d] + 0.5) * hf[2 - d] for d in range(3)],
                               indexing="ij")
         it = (slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
-        # U: children of parents whose six neighbours are interior to the
-        # source block (elsewhere U's slopes are one-sided by construction)
-        par = [(np.arange(n[2 - d]) + L[2 - d]) // 2 for d in range(3)]
-        src_lo = [0, 0, 0]           # the refined block is the first coarse block
-        inner = [(p_ > src_lo[2 - d]) & (p_ < src_lo[2 - d] + mesh.nx[0][2 - d] - 1)
-                 for d, p_ in enumerate(par)]
-        mask = inner[0][:, None, None] & inner[1][None, :, None] & inner[2][None, None, :]
         for q in range(5):
-            lin = 2.0 + 0.3 * X - 0.2 * Y + 0.1 * Z + 0.05 * q
-            assert np.allclose(U[b][q][it][mask], lin[mask], rtol=1e-13)
-            assert np.allclose(P[b][q][it], lin, rtol=1e-13)
+            lin = 1.0 + 0.03 * X - 0.02 * Y + 0.01 * Z + (0.0 if q in (0, 4) else -0.9)
+            assert np.allclose(P[b][q][it], lin, rtol=1e-13, atol=1e-14)
+        for k in range(0, n[2], 2):
+            for j in range(0, n[1], 2):
+                for i in range(0, n[0], 2):
+                    pc = [(L[0] + i) // 2, (L[1] + j) // 2, (L[2] + k) // 2]
+                    kids = U[b][:, g + k:g + k + 2, g + j:g + j + 2, g + i:g + i + 2].mean(axis=(1, 2, 3))
+                    par = mesh.U[0][:, g + pc[2], g + pc[1], g + pc[0]]
+                    assert np.allclose(kids, par, rtol=1e-13, atol=1e-15)
 
 
 def test_tag_indicator():
