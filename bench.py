@@ -34,14 +34,14 @@ def parse():
                     help="persistent flux grid size in workgroups (0: one per tile)")
     ap.add_argument("--workload", default="torus128",
                     choices=["torus128", "amr640", "mixed192", "fp64_192", "table128", "scalar128",
-                             "m1_128"],
+                             "m1_128", "regrid640"],
                     help="torus128: the headline line (default); amr640: the torus at 256^3 "
                          "effective on ~640 two-level blocks; mixed192 / fp64_192: the torus "
                          "at 192^3 in 27 blocks of 64^3, mixed precision / FP64; table128: "
                          "the 128^3 torus with the synthetic tabulated EOS and the Y_e scalar; "
                          "scalar128: the same with the ideal gas (scalar cost alone); m1_128: "
                          "the implicit gray-M1 collision update of three species on the 128^3 "
-                         "torus")
+                         "torus; regrid640: tag, regrid and remap of the 631-block two-level torus")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -227,6 +227,60 @@ def m1_workload(args, torch, G, I):
     print(json.dumps(out), flush=True)
 
 
+def regrid_workload(args, torch, G, I):
+    """One JSON line for a refinement cycle of the 631-block two-level torus:
+    tag the blocks by the density indicator, refine the 8 most structured
+    level-0 blocks and derefine every complete sibling group of level-1
+    blocks whose indicator is below 0.05, remap, fill ghosts, invert."""
+    import time
+    import numpy as np
+    fine = I.torus(n=(256, 256, 256))
+    lev, nx, ll = I.amr_layout(fine, target=640, node=32, smallest=16)
+    root = I.coarse_problem(fine)
+    Ps, Bs = I.mesh_blocks(fine, lev, nx, ll)
+    del fine
+    pack = G.Pack(root, layout=(nx, ll, lev))
+    pack.init_blocks(Ps, Bs)
+    del Ps, Bs
+    pack.reductions(sync=False)
+    pack.step_c(None, cfl=root.cfl)
+    r0 = pack.reductions()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ind = pack.tag(0)
+    t1 = time.perf_counter()
+    coarse = [b for b in np.argsort(ind)[::-1] if lev[b] == 0][:8]
+    tags = [1 if b in coarse else (-1 if lev[b] == 1 and ind[b] < 0.05 else 0) for b in range(len(lev))]
+    nx2, ll2, lv2 = G.regrid_layout(pack, tags)
+    t2 = time.perf_counter()
+    new = G.Pack(root, layout=(nx2, ll2, lv2))
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    new.remap_from(pack)
+    new._out()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    r1 = new.reductions()
+    cells = int(sum(np.prod(np.reshape(nx2, (-1, 3)), axis=1)))
+    out = {"metric": "refinement cycle of the two-level torus (growth configuration)",
+           "value": round((t4 - t3) * 1e3, 2), "unit": "ms (remap + ghosts + inversion)",
+           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "two-level torus, 256^3 effective, tag by the density indicator, "
+                                  "refine the 8 most structured level-0 blocks, derefine smooth "
+                                  "sibling groups", "blocks_before": len(lev), "blocks_after": len(lv2),
+                      "cells_after": cells},
+           "ms": {"tag": round((t1 - t0) * 1e3, 2), "layout": round((t2 - t1) * 1e3, 2),
+                  "new_pack": round((t3 - t2) * 1e3, 2),
+                  "remap_ghosts_inversion": round((t4 - t3) * 1e3, 2)},
+           "checks": {"divb_rel_after": r1["divb_rel"],
+                      "totals_rel_change": float(np.abs(r1["totals"] - r0["totals"]).max()
+                                                 / np.abs(r0["totals"]).max()),
+                      "floor_hits": r1["floor_hits"], "c2p_fail": r1["c2p_fail"],
+                      "refined": int(sum(1 for t in tags if t > 0)),
+                      "derefine_tags": int(sum(1 for t in tags if t < 0))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -246,6 +300,8 @@ def main():
 
     if args.workload == "m1_128":
         return m1_workload(args, torch, G, I)
+    if args.workload == "regrid640":
+        return regrid_workload(args, torch, G, I)
     if args.workload != "torus128":
         return growth_workload(args, torch, G, I)
 
