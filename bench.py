@@ -313,13 +313,25 @@ def main():
     tiles, tune_ms = pack.autotune(reps=3) if not args.no_autotune else ([0, 0, 0], None)
     if args.persist:
         pack.set_persistent(args.persist)
-    for _ in range(args.warmup):
-        pack.step_c(None, cfl=prob.cfl)
-    torch.cuda.synchronize()
-
     stream = pack.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+
+    # the timed steps: the SSPRK2 step captured once into a HIP graph (dt
+    # stays on the device) and replayed; warm-up replays first
+    for _ in range(args.warmup):
+        pack.step_c(None, cfl=prob.cfl)
+    pack.step_graph(0)
+    pack.step_graph(args.warmup)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    pack.step_graph(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
+
+    # the same steps launched one by one from the host, with an event pair
+    # around every kernel family (the per-kernel times and the roofline)
     pack.profile(True)
     torch.cuda.synchronize()
     e0.record(stream)
@@ -332,17 +344,8 @@ def main():
     pack.profile(False)
     red = pack.reductions()
 
-    # the same steps replayed from a captured HIP graph
-    pack.step_graph(0)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    pack.step_graph(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_graph = e0.elapsed_time(e1)
-
     ncell = n ** 3
-    value = ncell * args.steps / (ms * 1e-3)
+    value = ncell * args.steps / (ms_graph * 1e-3)
 
     # dominant kernel: the face-flux tile kernel k_flux (one launch per
     # direction and stage; the three directions are one template); roofline
@@ -395,7 +398,7 @@ def main():
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "zone-cycles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 4),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_graph / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"Kerr-Schild torus {n}^3 (a=0.9375, FM r_in=6 r_max=12, "
@@ -403,8 +406,11 @@ def main():
                                "WENO5-Z-AOAH + LLF, CT, SSPRK2, FP64, one meshblock",
                    "cells": ncell, "parallelism": "single GPU"},
         "roofline": roof, "hbm_view": hbm, "kernels": kernels,
-        "graph_replay": {"ms_per_step": round(ms_graph / args.steps, 4),
-                         "value": round(ncell * args.steps / (ms_graph * 1e-3), 1)},
+        "timing": "value and ms_per_step: K graph-replayed steps (the whole SSPRK2 step "
+                  "captured once, dt on the device); eager: the same K steps launched from "
+                  "the host with an event pair around every kernel family",
+        "eager": {"ms_per_step": round(ms / args.steps, 4),
+                  "value": round(ncell * args.steps / (ms * 1e-3), 1)},
         "tiling": {"shape_per_direction": tiles,
                    "autotune_ms": None if tune_ms is None else tune_ms.round(4).tolist()},
         "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"],
