@@ -280,7 +280,7 @@ int grmhd_profile_read(grmhd_pack *pack, double *ms, long long *count);
 
 /*
  * Learned initial guess of the inversion (growth on top of the paper's
- * method; the Newton solve stays the judge).  Network 5 -> 64 -> 64 -> 64 -> 2
+ * method; the Newton solve still decides the result).  Network 5 -> 64 -> 64 -> 64 -> 2
  * with SiLU, GRMHD_MLP_NPARAM FP32 parameters laid out as W1[64][5] b1[64]
  * W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2] (W[out][in]).
  * Features of a cell's undensitized conserved state: log10 D, log(1+S^2/D^2),
