@@ -52,3 +52,36 @@ def test_fused_reductions_equal_separate_pass():
     assert rf["dt"] == pytest.approx(rh["dt"], rel=1e-14)
     for key in ("c2p_fail", "floor_hits"):
         assert rf[key] == rh[key], key
+
+
+def test_torus128_benchmark_configuration_matches_oracle():
+    """The benchmark's own workload and launch configuration: the 128^3
+    ideal-gas Kerr-Schild torus (WENO5-Z-AOAH + LLF, FP64), autotuned tile
+    shapes, SSPRK2 steps replayed from the captured graph with the
+    device-resident dt.  Two steps from the oracle's state, compared on the
+    whole grid after each (gate 1e-11), and the dt each side derives."""
+    import os
+    import torch
+    import oracle
+    from paper_2410_09146_amd import grmhd as G
+    from parity_util import rel_err, upload_all
+    prob = I.torus(n=(128, 128, 128))
+    sim = oracle.Sim(prob, min(16, os.cpu_count() or 1))
+    pack = G.Pack(prob)
+    upload_all(pack, sim.P, sim.Bf, sim.U)
+    pack.fill_ghosts()
+    tiles, _ = pack.autotune(reps=1)
+    say("tiles", tiles)
+    for s in range(2):
+        dt = sim.dt()
+        r = pack.reductions()           # also leaves dt on the device
+        say("step", s, "dt oracle", dt, "gpu", r["dt"])
+        assert r["dt"] == pytest.approx(dt, rel=1e-12)
+        pack.step_graph(1)
+        torch.cuda.synchronize()
+        sim.step(dt)
+        eP = rel_err(pack.download("P"), sim.P, prob)
+        eU = rel_err(pack.download("U"), sim.U, prob)
+        eB = rel_err(pack.download("Bf"), sim.Bf, prob, face=True)
+        say("128^3 torus, step", s, "eP", eP.max(), "eU", eU.max(), "eB", eB.max())
+        assert np.all(eP <= 1e-11) and np.all(eU <= 1e-11) and np.all(eB <= 1e-11)
