@@ -160,6 +160,24 @@ def remap(src, level, nx, lloc):
         P = np.zeros((5,) + shp)
         U = np.zeros((5,) + shp)
         B = np.zeros((3,) + shp)
+        # a block present in both layouts (same level, position and size)
+        # keeps its own state: cells and every face, the faces it shares with
+        # a finer neighbour included
+        kept = [bs for bs in range(len(slev)) if slev[bs] == l and
+                tuple(sll[bs]) == tuple(L) and tuple(src.nx[bs]) == tuple(n)]
+        if kept:
+            bs = kept[0]
+            it = (slice(None), slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
+            P[it] = src.P[bs][it]
+            U[it] = src.U[bs][it]
+            for d in range(3):
+                f = (d, slice(g, g + n[2] + (d == 2)), slice(g, g + n[1] + (d == 1)),
+                     slice(g, g + n[0] + (d == 0)))
+                B[f] = src.Bf[bs][f]
+            Ps.append(P)
+            Us.append(U)
+            Bs.append(B)
+            continue
         for k in range(n[2]):
             for j in range(n[1]):
                 for i in range(n[0]):

@@ -119,10 +119,8 @@ def test_remap_matches_oracle(G, mode):
             wf = max(wf, float(np.abs(x[d] - y[d]).max() / den))
     say("remap", mode, len(lev), "->", len(lv2), "blocks; worst relative difference: cells", wc,
         "faces", wf)
-    if mode == "none":
-        # cells are copies; a level-0 face on a level boundary is re-derived
-        # from the 4 fine faces across it (summed in another order)
-        assert wc == 0.0 and wf <= 1e-15
+    if mode == "none":         # every block is kept whole
+        assert wc == 0.0 and wf == 0.0
     else:
         assert wc <= 1e-13 and wf <= 1e-13
 

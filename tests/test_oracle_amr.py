@@ -71,6 +71,9 @@ def test_regrid_layout_refine_then_derefine_is_identity():
 
 
 def test_remap_identity_layout_copies():
+    """A layout equal to the current one copies every block's cells and
+    faces, also the coarse faces on level boundaries (a block's own value,
+    not the mean of the fine faces across it)."""
     mesh = _box_mesh({(0, 0, 0)})
     P, U, B = amr.remap(mesh, mesh.level, mesh.nx, mesh.lloc)
     g = 4
@@ -79,6 +82,10 @@ def test_remap_identity_layout_copies():
         it = (slice(None), slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
         assert np.array_equal(P[b][it], mesh.P[b][it])
         assert np.array_equal(U[b][it], mesh.U[b][it])
+        for d in range(3):
+            f = (d, slice(g, g + n[2] + (d == 2)), slice(g, g + n[1] + (d == 1)),
+                 slice(g, g + n[0] + (d == 0)))
+            assert np.array_equal(B[b][f], mesh.Bf[b][f])
 
 
 @pytest.mark.parametrize("mode", ["refine", "derefine"])
