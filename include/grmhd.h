@@ -369,7 +369,9 @@ int grmhd_m1_source(grmhd_pack *pack, const grmhd_metric *metric, double dt, int
  * and eos serve U(P, B).  Then run grmhd_fill_ghosts, grmhd_con2prim and
  * grmhd_fill_ghosts on dst.  scratch: device memory (256-byte aligned) of
  * grmhd_remap_scratch_bytes(dst, src) bytes; src must not be written while
- * the call runs (it synchronises dst's stream before returning).
+ * the call runs (it synchronises dst's stream before returning).  dst and
+ * src are two packs with their own state arrays (GRMHD_E_INVALID when they
+ * share P, U or Bf).
  */
 int grmhd_tag(grmhd_pack *pack, int var, double *block_max);
 int grmhd_regrid_layout(const grmhd_pack_desc *desc, const int *tags, int cap, int *nb_out,

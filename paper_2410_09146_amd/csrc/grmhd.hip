@@ -1751,6 +1751,8 @@ int grmhd_remap(grmhd_pack *dst, const grmhd_pack *src, const grmhd_metric *metr
                 const grmhd_eos *eos, void *scratch, size_t scratch_bytes)
 {
   if (!dst || !src || !scratch) return perr(dst, "null argument", GRMHD_E_INVALID);
+  if (dst == src || dst->st.P == src->st.P || dst->st.U == src->st.U || dst->st.Bf == src->st.Bf)
+    return perr(dst, "remap needs two packs with their own state arrays", GRMHD_E_INVALID);
   if (int rc = check_metric(dst, metric)) return rc;
   if (int rc = check_eos(dst, eos)) return rc;
   if (dst->desc.nscalar || src->desc.nscalar)

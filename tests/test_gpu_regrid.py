@@ -178,3 +178,20 @@ def test_regrid_cycle_matches_oracle(G):
         say("after regrid step", s, "eP", eP, "eB", eB)
         assert eP <= 1e-11 and eB <= 1e-11
     torch.cuda.synchronize()
+
+
+def test_remap_rejects_one_pack_as_both_sides(G):
+    """dst and src must be two packs: the same pack on both sides is refused
+    on the host, before any launch."""
+    import torch
+    root, lev, nx, ll, Ps, Bs = _box({(0, 0, 0)})
+    pack = G.Pack(root, layout=(nx, ll, lev))
+    pack.init_blocks(Ps, Bs)
+    torch.cuda.synchronize()
+    L = G.lib()
+    s = torch.empty(1 << 20, dtype=torch.uint8, device=pack.device)
+    ptr = (s.data_ptr() + 255) // 256 * 256
+    rc = L.grmhd_remap(pack.h, pack.h, ctypes.byref(pack.metric), ctypes.byref(pack.eos),
+                       ctypes.c_void_p(ptr), ctypes.c_size_t(1 << 19))
+    assert rc == -1
+    assert b"two packs" in L.grmhd_last_error(pack.h)
