@@ -117,7 +117,8 @@ typedef struct {
  *          plane 5, reconstructed and fluxed like the hydro variables (its
  *          conserved form D Y_e, its flux Y_e times the mass flux).  Needs
  *          precision FP64 and a single-level pack (GRMHD_E_UNSUPPORTED
- *          otherwise); the flux tiles then use shape 0.
+ *          otherwise); the flux tiles then use shape 0 except with
+ *          WENO5-Z-AOAH point values and LLF.
  */
 typedef struct {
   int nblocks, ng;
@@ -243,8 +244,8 @@ int grmhd_step_graph(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_e
 /*
  * Face-tile shapes of the flux kernels: shape s has TD faces along the flux
  * direction and 256/TD columns (TD = 16, 32, 8, 64, 4 for s = 0..4).  Shapes
- * 1..4 exist for the WENO5-Z-AOAH point-value reconstruction; every other
- * reconstruction runs shape 0.  grmhd_autotune times each shape's tile kernel
+ * 1..4 exist for the WENO5-Z-AOAH point-value reconstruction (with the
+ * passive scalar: with LLF); every other combination runs shape 0.  grmhd_autotune times each shape's tile kernel
  * per direction (reps launches after one untimed launch, HIP events on the
  * pack's stream; the kernels only read the state and write the flux scratch),
  * keeps the fastest in chosen[3] and ms_table[3 * 5] (ms per launch, -1 when

@@ -833,12 +833,15 @@ void launch_tiles(grmhd_pack *p, const KArgs &a)
 }
 
 // Every shape is instantiated for the WENO5-Z-AOAH point-value path (the
-// production reconstruction); the other reconstructions, and every pack with
-// the passive scalar, use 16 x 16 tiles.
+// production reconstruction; with the passive scalar, for LLF); the other
+// reconstructions and combinations use 16 x 16 tiles.
+template <int RC, int FV, int RS, int NSC>
+constexpr bool all_shapes() { return RC == RC_WENO && FV == 0 && (NSC == 0 || RS == RS_LLF); }
+
 template <int MK, int D, int RC, int FV, int RS, typename T, int NSC>
 void launch_tiles_sh(grmhd_pack *p, const KArgs &a, int sh)
 {
-  if constexpr (RC == RC_WENO && FV == 0 && NSC == 0) {
+  if constexpr (all_shapes<RC, FV, RS, NSC>()) {
     switch (sh) {
       case 1: launch_tiles<MK, D, RC, FV, RS, T, 1, NSC>(p, a); return;
       case 2: launch_tiles<MK, D, RC, FV, RS, T, 2, NSC>(p, a); return;
@@ -1924,7 +1927,7 @@ int grmhd_autotune(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
   fill_eos(a, eos);
   const int rcn = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
   const int prec = p->desc.precision;
-  const bool all = rcn == RC_WENO && fv == 0 && !p->desc.nscalar;
+  const bool all = rcn == RC_WENO && fv == 0 && (!p->desc.nscalar || rs == RS_LLF);
   hipEvent_t e0, e1;
   HIPCHK(p, hipEventCreate(&e0));
   HIPCHK(p, hipEventCreate(&e1));
