@@ -287,8 +287,8 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "nothing here spans a second GPU", file=sys.stderr)
+        print(f"bench.py: the GRMHD step runs on one GPU (asked for {args.gpus}); "
+              "no code path here spans a second GPU", file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: one GPU only; refusing a multi-rank launch", file=sys.stderr)

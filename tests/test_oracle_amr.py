@@ -1,7 +1,7 @@
 """Pins of the oracle's mesh refinement (two-level block mesh: tagging, the
 next layout, the conservative and divergence-free remap).  The paper
-evolves on Parthenon's adaptive block mesh (Sec. 1, Sec. 3); the operators
-are this build's reading."""
+evolves on Parthenon's adaptive block mesh (Sec. 1, Sec. 3) and does not
+give the operators; the ones pinned here are a reading of that mesh."""
 import numpy as np
 import pytest
 
