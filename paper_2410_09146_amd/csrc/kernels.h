@@ -1017,7 +1017,7 @@ __global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
                                                   const int2 *__restrict__ chunks,
                                                   float *__restrict__ mu_out)
 {
-  __shared__ unsigned short X[64 * 16], H1[64 * 64], H2[64 * 64];
+  __shared__ __align__(16) unsigned short X[64 * 16];
   __shared__ float out[64 * MLP_OUT];
   const int lane = threadIdx.x;
   const int2 ch = chunks[blockIdx.x >> 2];
@@ -1047,7 +1047,7 @@ __global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
 #pragma unroll
   for (int q = 0; q < 16; ++q) X[lane * 16 + q] = q < 5 ? f2bf(x[q]) : 0;
   __syncthreads();
-  mlp_wave(m, X, H1, H2, out, lane);
+  mlp_wave(m, X, out, lane);
   if (live) {
     // mu = 1/(hW) <= 1 always: a guess above 1 (log hW output slightly
     // negative near h W = 1) is clamped; a non-finite or non-positive one is

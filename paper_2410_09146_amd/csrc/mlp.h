@@ -167,73 +167,109 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// A fragment from a row-major bf16 matrix in LDS (ld = row length)
-__device__ __forceinline__ bf16x4 lds_frag(const unsigned short *M, int ld, int row, int k0)
+// SiLU for inference, z / (1 + e^-z) with the hardware exp2 and reciprocal:
+// the activations are rounded to BF16 right after, far above their error.
+__device__ __forceinline__ float silu_hw(float z)
 {
-  const unsigned short *p = M + row * ld + k0;
-  bf16x4 r;
-  r.x = (short)p[0]; r.y = (short)p[1]; r.z = (short)p[2]; r.w = (short)p[3];
-  return r;
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
 }
 
-// One dense layer for the 64 rows of a wavefront: Hout = act(Hin W^T + b),
-// Hin [64][K] bf16 in LDS, W [Nout][K] bf16 (global), Hout [64][64] bf16 LDS.
-template <int K, int NT, bool ACT>
-__device__ __forceinline__ void mfma_layer(const unsigned short *Hin, const unsigned short *W,
-                                           const float *bias, unsigned short *Hout,
-                                           float *outf, int lane)
+// Four floats to BF16 (round to nearest even) with gfx950's packed convert,
+// two values per instruction.
+typedef __bf16 bf16v2 __attribute__((ext_vector_type(2)));
+typedef float f32v2 __attribute__((ext_vector_type(2)));
+struct Bf16Pair { bf16v2 lo, hi; };
+__device__ __forceinline__ bf16x4 pack_bf16(float a, float b, float c, float d)
 {
-  const int r16 = lane % 16, q = lane / 16;
+  const Bf16Pair p = {__builtin_convertvector(f32v2{a, b}, bf16v2),
+                      __builtin_convertvector(f32v2{c, d}, bf16v2)};
+  return __builtin_bit_cast(bf16x4, p);
+}
+
+// One dense layer over the 64 rows (cells) of a wavefront, computed
+// transposed, O^T = W H^T, so that the MFMA result tile is already the next
+// layer's B operand: with r = lane % 16 and q = lane / 16,
+//   H[kt][mt] (lane) = H(row 16 mt + r, columns 16 kt + 4 q .. + 3)   (B operand)
+//   A operand = W(row 16 nt + r, columns 16 kt + 4 q .. + 3)           (8-byte load)
+//   D[mt] of tile nt (lane) = O(row 16 mt + r, columns 16 nt + 4 q .. + 3)
+// W [N][K] bf16 row-major (global, L2-resident).  Hidden layers (ACT): the
+// bias enters as the accumulator's initial value and SiLU + BF16 rounding
+// are applied tile by tile (16 output columns at a time, so only 16
+// accumulators are live) into Hout[nt][mt].  Output layer: the raw tiles in
+// Dout[nt][mt], bias left to the caller.
+template <int K, int N, bool ACT>
+__device__ __forceinline__ void dense_t(const bf16x4 (&H)[K / 16][4], const unsigned short *W,
+                                        const float *bias, bf16x4 (&Hout)[N / 16][4],
+                                        f32x4 (&Dout)[N / 16][4], int lane)
+{
+  const int r = lane % 16, q = lane / 16;
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
+  for (int nt = 0; nt < N / 16; ++nt) {
+    f32x4 init = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (ACT)
+      init = f32x4{bias[16 * nt + 4 * q], bias[16 * nt + 4 * q + 1], bias[16 * nt + 4 * q + 2],
+                   bias[16 * nt + 4 * q + 3]};
+    f32x4 D[4] = {init, init, init, init};
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int kt = 0; kt < K / 16; ++kt) {
+      const bf16x4 a = *(const bf16x4 *)(W + (16 * nt + r) * K + 16 * kt + 4 * q);
 #pragma unroll
-      for (int kt = 0; kt < K / 16; ++kt) {
-        const bf16x4 af = lds_frag(Hin, K, 16 * mt + r16, 16 * kt + 4 * q);
-        const bf16x4 bf = lds_frag(W, K, 16 * nt + r16, 16 * kt + 4 * q);
-        acc = mfma16(af, bf, acc);
-      }
-      const int col = 16 * nt + r16;
+      for (int mt = 0; mt < 4; ++mt) D[mt] = mfma16(a, H[kt][mt], D[mt]);
+    }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * mt + 4 * q + i;
-        if constexpr (ACT) {
-          Hout[row * 64 + col] = f2bf(silu_f(acc[i] + bias[col]));
-        } else {
-          if (col < MLP_OUT) outf[row * MLP_OUT + col] = acc[i] + bias[col];
-        }
-      }
+    for (int mt = 0; mt < 4; ++mt) {
+      if constexpr (ACT)
+        Hout[nt][mt] = pack_bf16(silu_hw(D[mt][0]), silu_hw(D[mt][1]), silu_hw(D[mt][2]),
+                                 silu_hw(D[mt][3]));
+      else
+        Dout[nt][mt] = D[mt];
     }
   }
 }
 
 // Features of one cell (undensitized conserved state on the cell's metric):
 // log10 D, log(1 + S^2/D^2), log(1 + tau/D), log(1 + B^2/D), log(1 + (S.B)^2/D^3),
-// standardised with the training set's mean and standard deviation.
+// standardised with the training set's mean and standard deviation.  The
+// ratios are formed in FP64 and the logarithms taken in FP32 with the
+// hardware log2: the features are rounded to BF16 next.
 __device__ __forceinline__ void mlp_features(double D, double S2, double tau, double BB, double SB,
                                              const float *mean, const float *istd, float x[5])
 {
   const double iD = 1.0 / D;
-  const double raw[5] = {log10(D), log1p(S2 * iD * iD), log1p(fmax(tau, 0.0) * iD),
-                         log1p(BB * iD), log1p(SB * SB * iD * iD * iD)};
+  auto ratio = [](double v) { return (float)fmin(fmax(v, 0.0), 1e30); };
+  constexpr float ln2 = 0.69314718055994531f, lg2 = 0.30102999566398120f;
+  const float raw[5] = {__builtin_amdgcn_logf((float)fmax(D, 1e-37)) * lg2,
+                        __builtin_amdgcn_logf(1.0f + ratio(S2 * iD * iD)) * ln2,
+                        __builtin_amdgcn_logf(1.0f + ratio(tau * iD)) * ln2,
+                        __builtin_amdgcn_logf(1.0f + ratio(BB * iD)) * ln2,
+                        __builtin_amdgcn_logf(1.0f + ratio(SB * SB * iD * iD * iD)) * ln2};
 #pragma unroll
-  for (int k = 0; k < 5; ++k) x[k] = ((float)raw[k] - mean[k]) * istd[k];
+  for (int k = 0; k < 5; ++k) x[k] = (raw[k] - mean[k]) * istd[k];
 }
 
-// Wavefront-level inference for 64 feature rows already in LDS (X [64][16]).
-// Writes y [64][2] to outf (LDS).
-__device__ __forceinline__ void mlp_wave(const MlpDev &m, unsigned short *X, unsigned short *H1,
-                                         unsigned short *H2, float *outf, int lane)
+// Wavefront-level inference for 64 feature rows already in LDS (X [64][16]
+// bf16, written by the 64 lanes before a barrier).  The activations stay in
+// registers; the two outputs of every row go to outf [64][2] (LDS), visible
+// to the whole wavefront when this returns.
+__device__ __forceinline__ void mlp_wave(const MlpDev &m, const unsigned short *X, float *outf,
+                                         int lane)
 {
-  mfma_layer<16, 4, true>(X, m.w + MLPB_W1, m.f + MLPF_B1, H1, nullptr, lane);
-  __syncthreads();
-  mfma_layer<64, 4, true>(H1, m.w + MLPB_W2, m.f + MLPF_B2, H2, nullptr, lane);
-  __syncthreads();
-  mfma_layer<64, 4, true>(H2, m.w + MLPB_W3, m.f + MLPF_B3, H1, nullptr, lane);
-  __syncthreads();
-  mfma_layer<64, 1, false>(H1, m.w + MLPB_W4, m.f + MLPF_B4, nullptr, outf, lane);
+  const int r = lane % 16, q = lane / 16;
+  bf16x4 h0[1][4], h1[4][4], h2[4][4], unused[1][4];
+  f32x4 none[4][4], o[1][4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) h0[0][mt] = *(const bf16x4 *)(X + (16 * mt + r) * 16 + 4 * q);
+  dense_t<16, 64, true>(h0, m.w + MLPB_W1, m.f + MLPF_B1, h1, none, lane);
+  dense_t<64, 64, true>(h1, m.w + MLPB_W2, m.f + MLPF_B2, h2, none, lane);
+  dense_t<64, 64, true>(h2, m.w + MLPB_W3, m.f + MLPF_B3, h1, none, lane);
+  dense_t<64, 16, false>(h1, m.w + MLPB_W4, nullptr, unused, o, lane);   // W4 padded to 16 rows
+  if (q == 0) {          // lanes 0..15 hold outputs 0..3 of rows 16 mt + r
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      outf[(16 * mt + r) * MLP_OUT + 0] = o[0][mt][0] + m.f[MLPF_B4];
+      outf[(16 * mt + r) * MLP_OUT + 1] = o[0][mt][1] + m.f[MLPF_B4 + 1];
+    }
+  }
   __syncthreads();
 }
 
@@ -241,7 +277,7 @@ __device__ __forceinline__ void mlp_wave(const MlpDev &m, unsigned short *X, uns
 __global__ __launch_bounds__(64) void k_mlp_infer(MlpDev m, const float *__restrict__ Xin,
                                                   float *__restrict__ Y, int n)
 {
-  __shared__ unsigned short X[64 * 16], H1[64 * 64], H2[64 * 64];
+  __shared__ __align__(16) unsigned short X[64 * 16];
   __shared__ float out[64 * MLP_OUT];
   const int lane = threadIdx.x;
   const int s = blockIdx.x * 64 + lane;
@@ -252,7 +288,7 @@ __global__ __launch_bounds__(64) void k_mlp_infer(MlpDev m, const float *__restr
     X[lane * 16 + k] = f2bf(v);
   }
   __syncthreads();
-  mlp_wave(m, X, H1, H2, out, lane);
+  mlp_wave(m, X, out, lane);
   if (s < n) {
     Y[s * 2 + 0] = out[lane * 2 + 0];
     Y[s * 2 + 1] = out[lane * 2 + 1];
