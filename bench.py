@@ -42,6 +42,10 @@ def parse():
                          "scalar128: the same with the ideal gas (scalar cost alone); m1_128: "
                          "the implicit gray-M1 collision update of three species on the 128^3 "
                          "torus; regrid640: tag, regrid and remap of the 631-block two-level torus")
+    ap.add_argument("--recon", default="weno5z_aoah", choices=list(RECON_NAMES),
+                    help="reconstruction of the torus128 workload (default: the headline's)")
+    ap.add_argument("--riemann", default="llf", choices=["llf", "hll"],
+                    help="Riemann solver of the torus128 workload (default: the headline's)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -60,6 +64,11 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": n * 8, "copies": 3}), flush=True)
 
+
+# reconstruction options of the torus workload: name -> (inputs constant name, label)
+RECON_NAMES = {"weno5z_aoah": ("RECON_WENO5Z", "WENO5-Z-AOAH"), "mp5": ("RECON_MP5", "MP5"),
+               "plm_mc": ("RECON_PLM_MC", "PLM-MC"), "plm_minmod": ("RECON_PLM_MINMOD", "PLM-minmod"),
+               "const": ("RECON_CONST", "piecewise constant")}
 
 KERNEL_SOURCES = ("paper_2410_09146_amd/csrc/kernels.h", "paper_2410_09146_amd/csrc/dev.h")
 
@@ -306,7 +315,9 @@ def main():
         return growth_workload(args, torch, G, I)
 
     n = args.n
-    prob = I.torus(n=(n, n, n))
+    headline = args.recon == "weno5z_aoah" and args.riemann == "llf"
+    prob = I.torus(n=(n, n, n), recon=getattr(I, RECON_NAMES[args.recon][0]),
+                   riemann=I.RIEMANN_LLF if args.riemann == "llf" else I.RIEMANN_HLL)
     pack = G.Pack(prob, device="cuda:0")
     pack.init()
     pack.reductions(sync=False)        # device-resident dt for the first step
@@ -351,7 +362,7 @@ def main():
     # direction and stage; the three directions are one template); roofline
     # from algorithmic FP64 flops per face
     opc = json.load(open(os.path.join(ROOT, "paper_2410_09146_amd", "opcount", "opcount.json")))
-    per_face = opc["per_face_flux_ks_weno_llf"]
+    per_face = opc[f"per_face_flux_ks_{args.recon}_{args.riemann}"]
     fams = ("flux_x1", "flux_x2", "flux_x3")
     t_ms = sum(prof[f][0] for f in fams)
     cnt = sum(prof[f][1] for f in fams)
@@ -360,7 +371,8 @@ def main():
     achieved = flops / (avg_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-            "traffic": measured_traffic(flux_faces(n)), "kernel": "k_flux (x1, x2, x3 launches)",
+            "traffic": measured_traffic(flux_faces(n)) if headline else None,
+            "kernel": "k_flux (x1, x2, x3 launches)",
             "avg_launch_ms": round(avg_ms, 4), "flops_per_face": per_face,
             "faces_per_launch": flux_faces(n),
             "share_of_step": round(t_ms / args.steps / (ms / args.steps), 3)}
@@ -403,7 +415,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"Kerr-Schild torus {n}^3 (a=0.9375, FM r_in=6 r_max=12, "
                                "gamma=13/9, beta=100 loop field, noise 4e-2 seed 1), "
-                               "WENO5-Z-AOAH + LLF, CT, SSPRK2, FP64, one meshblock",
+                               f"{RECON_NAMES[args.recon][1]} + {args.riemann.upper()}, CT, "
+                               "SSPRK2, FP64, one meshblock",
                    "cells": ncell, "parallelism": "single GPU"},
         "roofline": roof, "hbm_view": hbm, "kernels": kernels,
         "timing": "value and ms_per_step: K graph-replayed steps (the whole SSPRK2 step "

@@ -28,6 +28,10 @@ def count():
     res = json.loads(subprocess.run([exe], check=True, capture_output=True, text=True).stdout)
     f = {k: v["flops"] for k, v in res.items()}
     res["per_face_flux_ks_weno_llf"] = 7 * f["recon_weno5z_aoah"] + f["geo_ks"] + f["riemann_llf"]
+    # every reconstruction x Riemann solver on the Kerr-Schild face
+    for rc in ("weno5z_aoah", "mp5", "plm_mc", "plm_minmod", "const"):
+        for rs in ("llf", "hll"):
+            res[f"per_face_flux_ks_{rc}_{rs}"] = 7 * f[f"recon_{rc}"] + f["geo_ks"] + f[f"riemann_{rs}"]
     res["per_face_flux_mink_plm_hll"] = 7 * f["recon_plm_mc"] + f["riemann_hll_minkowski"]
     res["per_cell_update_ks"] = UPDATE_LOCAL + f["geo_ks"] + f["aux_of"] + f["sources_ks"]
     res["per_cell_update_local"] = UPDATE_LOCAL

@@ -41,6 +41,14 @@ int main()
   const OpCount o_weno = snap();
   recon5<RC_PLM_MC, 0>(cd(1.0), cd(1.1), cd(1.25), cd(1.45), cd(1.7), l, r);
   const OpCount o_mc = snap();
+  recon5<RC_PLM_MINMOD, 0>(cd(1.0), cd(1.1), cd(1.25), cd(1.45), cd(1.7), l, r);
+  const OpCount o_mm = snap();
+  // MP5 on the same smooth stencil: both faces keep the unlimited value (the
+  // common path; the limiter's extra work is counted nowhere)
+  recon5<RC_MP5, 0>(cd(1.0), cd(1.1), cd(1.25), cd(1.45), cd(1.7), l, r);
+  const OpCount o_mp5 = snap();
+  recon5<RC_CONST, 0>(cd(1.0), cd(1.1), cd(1.25), cd(1.45), cd(1.7), l, r);
+  const OpCount o_const = snap();
   const Aux A = aux_of(G, gam, L);
   const OpCount o_aux = snap();
   const Sym4 T = tmunu(G, A);
@@ -62,6 +70,9 @@ int main()
   emit("riemann_hll_minkowski", o_hll_mink);
   emit("recon_weno5z_aoah", o_weno);
   emit("recon_plm_mc", o_mc);
+  emit("recon_plm_minmod", o_mm);
+  emit("recon_mp5", o_mp5);
+  emit("recon_const", o_const);
   emit("aux_of", o_aux);
   emit("sources_ks", o_src);
   emit("master_iteration", o_master, true);
