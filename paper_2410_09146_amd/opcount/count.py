@@ -21,7 +21,7 @@ OUT = os.path.join(HERE, "opcount.json")
 UPDATE_LOCAL = 40 + 63 + 40
 
 
-def count():
+def count(write=True):
     exe = os.path.join(tempfile.mkdtemp(), "opcount")
     subprocess.run(["g++", "-std=c++17", "-O0", "-I", os.path.join(HERE, "shim"),
                     os.path.join(HERE, "opcount.cpp"), "-o", exe], check=True)
@@ -35,8 +35,9 @@ def count():
     res["per_face_flux_mink_plm_hll"] = 7 * f["recon_plm_mc"] + f["riemann_hll_minkowski"]
     res["per_cell_update_ks"] = UPDATE_LOCAL + f["geo_ks"] + f["aux_of"] + f["sources_ks"]
     res["per_cell_update_local"] = UPDATE_LOCAL
-    with open(OUT, "w") as fh:
-        json.dump(res, fh, indent=1, sort_keys=True)
+    if write:
+        with open(OUT, "w") as fh:
+            json.dump(res, fh, indent=1, sort_keys=True)
     return res
 
 
