@@ -379,6 +379,38 @@ __device__ __forceinline__ void speeds_of(const GeoT<T> &G, const AuxT<T> &A, T 
   lm = fmin(l1, l2);
 }
 
+// The operation counter counts the plain definitions (both roots, then the
+// largest magnitude), not the shortcuts below.
+#ifdef GRMHD_OPCOUNT
+constexpr bool COUNTING = true;
+#else
+constexpr bool COUNTING = false;
+#endif
+
+// max(|lambda_-|, |lambda_+|) of speeds_of: (|qb| + sqrt(disc)) |1 / (2 qa)|,
+// the same number as the larger magnitude of the two roots computed there.
+template <int DIR, typename T>
+__device__ __forceinline__ T speed_absmax(const GeoT<T> &G, const AuxT<T> &A)
+{
+  const T Nc = A.gp + A.b2;
+  const T omc = (A.w + A.b2) - Nc;
+  const T ia = G.ialpha;
+  const T ia2 = ia * ia;
+  const T u0 = A.W * ia;
+  const T ud = DIR == 0 ? A.uc1 : (DIR == 1 ? A.uc2 : A.uc3);
+  const T g00 = -ia2;
+  const T g0d = DIR == 0 ? G.beta1 * ia2 : T(0);
+  const T gdd = DIR == 0 ? G.gi11 - G.beta1 * G.beta1 * ia2 : (DIR == 1 ? G.gi22 : G.gi33);
+  const T qa = omc * u0 * u0 - Nc * g00;
+  const T qb = T(-2) * (omc * u0 * ud - Nc * g0d);
+  const T qc = omc * ud * ud - Nc * gdd;
+  T disc = qb * qb - T(4) * qa * qc;
+  disc = disc > T(0) ? disc : T(0);
+  const T sq = sqrt(disc);
+  const T i2a = T(0.5) * inv(qa);
+  return (fabs(qb) + sq) * fabs(i2a);
+}
+
 // Face flux of the law d_t(sqrt(gamma) U) + d_i(sqrt(-g) F^i) = ..., returned
 // as two undensitized parts: the densitized flux is sqrt(-g) A + sqrt(gamma) B
 // (the speeds are eigenvalues of d(sqrt(-g)F)/d(sqrt(gamma)U), so the
@@ -396,14 +428,16 @@ __device__ __forceinline__ void riemann_parts(const GeoT<T> &G, const PrimT<T> &
     const AuxT<T> X = aux_th(G, L, pL, gpL);
     cons_of(G, L, X, UL);
     flux_of<DIR>(G, L, X, UL, FL);
-    speeds_of<DIR>(G, X, lmL, lpL);
+    if constexpr (RS == RS_HLL || COUNTING) speeds_of<DIR>(G, X, lmL, lpL);
+    else lpL = speed_absmax<DIR>(G, X), lmL = T(0);
     if constexpr (NSC != 0) { UL[8] = UL[0] * L.ye; FL[8] = FL[0] * L.ye; }
   }
   {
     const AuxT<T> X = aux_th(G, R, pR, gpR);
     cons_of(G, R, X, UR);
     flux_of<DIR>(G, R, X, UR, FR);
-    speeds_of<DIR>(G, X, lmR, lpR);
+    if constexpr (RS == RS_HLL || COUNTING) speeds_of<DIR>(G, X, lmR, lpR);
+    else lpR = speed_absmax<DIR>(G, X), lmR = T(0);
     if constexpr (NSC != 0) { UR[8] = UR[0] * R.ye; FR[8] = FR[0] * R.ye; }
   }
   if constexpr (RS == RS_HLL) {
@@ -420,7 +454,8 @@ __device__ __forceinline__ void riemann_parts(const GeoT<T> &G, const PrimT<T> &
       for (int v = 0; v < NC; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = T(0); }
     }
   } else {
-    const T c = fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)));
+    const T c = COUNTING ? fmax(fmax(fabs(lmL), fabs(lpL)), fmax(fabs(lmR), fabs(lpR)))
+                         : fmax(lpL, lpR);      // the largest |lambda| of either state
     const T hc = T(-0.5) * c;
 #pragma unroll
     for (int v = 0; v < NC; ++v) { A[v] = T(0.5) * (FL[v] + FR[v]); B[v] = hc * (UR[v] - UL[v]); }
@@ -535,24 +570,28 @@ __device__ __forceinline__ bool weno_pair(double f0, double f1, double f2, doubl
   const double ir = rcp_nr(Sr), il = rcp_nr(Sl);
   const double wr0 = ar0 * ir, wr1 = ar1 * ir, wr2 = ar2 * ir;
   const double wl0 = al0 * il, wl1 = al1 * il, wl2 = al2 * il;
+  // the candidates without their common factor (1/8, or 1/6 for cell
+  // averages), applied once to each weighted sum: for 1/8 a power of two, so
+  // the result is the same number as with the factor inside
   double pr0, pr1, pr2, pl0, pl1, pl2;
+  constexpr double cs = FV ? 1.0 / 6.0 : 0.125;
   if constexpr (FV) {
-    pr0 = (2.0 * f0 - 7.0 * f1 + 11.0 * f2) * (1.0 / 6.0);
-    pr1 = (-f1 + 5.0 * f2 + 2.0 * f3) * (1.0 / 6.0);
-    pr2 = (2.0 * f2 + 5.0 * f3 - f4) * (1.0 / 6.0);
-    pl0 = (2.0 * f4 - 7.0 * f3 + 11.0 * f2) * (1.0 / 6.0);
-    pl1 = (-f3 + 5.0 * f2 + 2.0 * f1) * (1.0 / 6.0);
-    pl2 = (2.0 * f2 + 5.0 * f1 - f0) * (1.0 / 6.0);
+    pr0 = 2.0 * f0 - 7.0 * f1 + 11.0 * f2;
+    pr1 = -f1 + 5.0 * f2 + 2.0 * f3;
+    pr2 = 2.0 * f2 + 5.0 * f3 - f4;
+    pl0 = 2.0 * f4 - 7.0 * f3 + 11.0 * f2;
+    pl1 = -f3 + 5.0 * f2 + 2.0 * f1;
+    pl2 = 2.0 * f2 + 5.0 * f1 - f0;
   } else {
-    pr0 = (3.0 * f0 - 10.0 * f1 + 15.0 * f2) * 0.125;
-    pr1 = (-f1 + 6.0 * f2 + 3.0 * f3) * 0.125;
-    pr2 = (3.0 * f2 + 6.0 * f3 - f4) * 0.125;
-    pl0 = (3.0 * f4 - 10.0 * f3 + 15.0 * f2) * 0.125;
-    pl1 = (-f3 + 6.0 * f2 + 3.0 * f1) * 0.125;
-    pl2 = (3.0 * f2 + 6.0 * f1 - f0) * 0.125;
+    pr0 = 3.0 * f0 - 10.0 * f1 + 15.0 * f2;
+    pr1 = -f1 + 6.0 * f2 + 3.0 * f3;
+    pr2 = 3.0 * f2 + 6.0 * f3 - f4;
+    pl0 = 3.0 * f4 - 10.0 * f3 + 15.0 * f2;
+    pl1 = -f3 + 6.0 * f2 + 3.0 * f1;
+    pl2 = 3.0 * f2 + 6.0 * f1 - f0;
   }
-  pr = wr0 * pr0 + wr1 * pr1 + wr2 * pr2;
-  pl = wl0 * pl0 + wl1 * pl1 + wl2 * pl2;
+  pr = (wr0 * pr0 + wr1 * pr1 + wr2 * pr2) * cs;
+  pl = (wl0 * pl0 + wl1 * pl1 + wl2 * pl2) * cs;
   const double Nr = 3.0 * wr0 * wr1 * wr2, Dr = g2 * wr0 * wr1 + g1 * wr0 * wr2 + g0 * wr1 * wr2;
   const double Nl = 3.0 * wl0 * wl1 * wl2, Dl = g2 * wl0 * wl1 + g1 * wl0 * wl2 + g0 * wl1 * wl2;
   const double den = Nr * Dl + Nl * Dr;
