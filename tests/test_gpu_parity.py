@@ -308,3 +308,32 @@ def test_linear_fast_wave_second_order_on_gpu(grmhd):
     say("orders", orders)
     assert np.all(orders > 1.7), (tot, orders)
     assert tot[-1] < 0.05
+
+
+def test_michel_inflow_held_to_truncation_error_on_gpu(grmhd):
+    """The HIP path alone: stationary transonic inflow on Schwarzschild
+    (Kerr-Schild, a = 0) at 32, 64, 128 radial cells; after t = 5 with the
+    GPU's own dt the deviation from the exact solution shrinks at about
+    second order."""
+    import torch
+    errs = []
+    for N in (32, 64, 128):
+        prob = I.bondi(N)
+        pack = grmhd.Pack(prob)
+        pack.init()
+        t, tend = 0.0, 5.0
+        while t < tend - 1e-14:
+            dt = min(pack.reductions()["dt"], tend - t)
+            pack.step(dt)
+            t += dt
+        torch.cuda.synchronize()
+        g = prob.ng
+        rho = pack.download("P")[0, g, g, g:g + N]
+        rho0 = prob.P[0, g, g, g:g + N]
+        errs.append(np.mean(np.abs(rho - rho0) / rho0))
+        say("michel", N, "mean relative deviation of rho", errs[-1])
+        del pack
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    say("orders", orders)
+    assert np.all(orders > 1.5), (errs, orders)
