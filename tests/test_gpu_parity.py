@@ -337,3 +337,40 @@ def test_michel_inflow_held_to_truncation_error_on_gpu(grmhd):
     orders = np.log2(errs[:-1] / errs[1:])
     say("orders", orders)
     assert np.all(orders > 1.5), (errs, orders)
+
+
+@pytest.mark.parametrize("case", ["sod", "strong", "sod_weno_llf"])
+def test_shock_tube_vs_exact_on_gpu(grmhd, case):
+    """The HIP path alone against the exact special-relativistic Riemann
+    solution (B = 0): L1(rho) at 100 / 200 / 400 cells converges at about
+    first order (discontinuities)."""
+    import torch
+    from srhd_exact import ExactRiemann
+    kw = dict(recon=I.RECON_WENO5Z, riemann=I.RIEMANN_LLF) if case.endswith("weno_llf") \
+        else dict(recon=I.RECON_PLM_MC)
+    if case.startswith("sod"):
+        L, R, g, tend = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 5.0 / 3.0, 0.4
+    else:
+        L, R, g, tend = (10.0, 0.0, 13.33), (1.0, 0.0, 0.01333), 5.0 / 3.0, 0.35
+    ex = ExactRiemann(L, R, g)
+    errs = []
+    for N in (100, 200, 400):
+        prob = I.shock_tube(N, L, R, g, **kw)
+        pack = grmhd.Pack(prob)
+        pack.init()
+        t = 0.0
+        while t < tend - 1e-14:
+            dt = min(pack.reductions()["dt"], tend - t)
+            pack.step(dt)
+            t += dt
+        torch.cuda.synchronize()
+        x = prob.centers(0)[prob.ng:prob.ng + N]
+        rho = pack.download("P")[0, prob.ng, prob.ng, prob.ng:prob.ng + N]
+        rho_ex = ex.sample((x - 0.5) / tend)[:, 0]
+        errs.append(np.mean(np.abs(rho - rho_ex)))
+        del pack
+    errs = np.array(errs)
+    orders = np.log2(errs[:-1] / errs[1:])
+    say("shock tube", case, "L1(rho)", errs, "orders", orders)
+    assert np.all(orders > 0.6), (errs, orders)
+    assert errs[-1] < (0.01 if case.startswith("sod") else 0.05)
