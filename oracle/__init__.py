@@ -19,15 +19,17 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-s
           "-std=c11", "-Wall"]
 
 
-def build(force=True):
-    """Compile liboracle.so with gcc (no fast-math, no FMA contraction)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
-    cmd = ["gcc"] + CFLAGS + ["-o", LIB_PATH + ".tmp"] + \
-        [os.path.join(_HERE, s) for s in SOURCES] + ["-lm"]
+def build(force=True, src_dir=_HERE, out=LIB_PATH):
+    """Compile liboracle.so with gcc (no fast-math, no FMA contraction).
+    src_dir / out: another copy of the sources and its library (the pin tests
+    build deliberately broken copies to show that each pin catches them)."""
+    if not force and os.path.exists(out):
+        return out
+    cmd = ["gcc"] + CFLAGS + ["-I", _HERE, "-o", out + ".tmp"] + \
+        [os.path.join(src_dir, s) for s in SOURCES] + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(LIB_PATH + ".tmp", LIB_PATH)
-    return LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 class Grid(ctypes.Structure):
@@ -81,16 +83,22 @@ def eos_struct(prob):
 _lib = None
 
 
+def load(path):
+    """A ctypes handle of an oracle library with the return types set."""
+    L = ctypes.CDLL(path)
+    L.orc_pt_master.restype = ctypes.c_double
+    L.orc_pt_master_tab.restype = ctypes.c_double
+    L.orc_m1_chi.restype = ctypes.c_double
+    L.orc_m1_chi.argtypes = [ctypes.c_double]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        _lib = ctypes.CDLL(LIB_PATH)
-        _lib.orc_pt_master.restype = ctypes.c_double
-        _lib.orc_pt_master_tab.restype = ctypes.c_double
-        _lib.orc_m1_chi.restype = ctypes.c_double
-        _lib.orc_m1_chi.argtypes = [ctypes.c_double]
+        _lib = load(LIB_PATH)
     return _lib
 
 

@@ -41,7 +41,8 @@ double orc_c2p_master(double gam, double q, double r2, double b2, double rb, dou
 /*
  * Ud = undensitized (D, S_1, S_2, S_3, tau, D Y_e) (the last entry is read only
  * with a scalar); B = undensitized B^i.
- * Returns 0 on success, 1 for an invalid state, 2 if the bracket fails.
+ * Returns 0 on success, 1 for an invalid state, 2 if the bracket fails, 3 if
+ * the root's primitives are not finite.
  */
 int orc_c2p_point(const orc_eos *e, const orc_geom *G, const double Ud[6], const double B[3],
                   orc_prim *P, double *mu_out)
@@ -120,5 +121,10 @@ int orc_c2p_point(const orc_eos *e, const orc_geom *G, const double Ud[6], const
     P->B[i] = B[i];
   }
   if (mu_out) *mu_out = mu;
+  /* a root whose primitives are not finite (v^2 bound rounded to 1, so that
+     W overflows) is no inversion: the state is reported as failed */
+  if (!(P->rho > 0.0) || !isfinite(P->rho) || !isfinite(P->u)) return 3;
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(P->ut[i])) return 3;
   return 0;
 }
