@@ -184,7 +184,8 @@ def growth_workload(args, torch, G, I):
            "k_flux": {"avg_launch_ms": round(avg, 4), "faces_per_launch": faces},
            "kernels": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
            "tiling": tiles,
-           "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"]}}
+           "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"],
+                     "c2p_fail_total": red["c2p_fail_total"]}}
     if args.workload not in ("table128", "scalar128"):     # the operation count is the ideal path's
         out["k_flux"]["algorithmic_TFLOPs"] = round(
             opc["per_face_flux_ks_weno_llf"] * faces / (avg * 1e-3) / 1e12, 3)
@@ -428,6 +429,7 @@ def main():
         "tiling": {"shape_per_direction": tiles,
                    "autotune_ms": None if tune_ms is None else tune_ms.round(4).tolist()},
         "state": {"dt": red["dt"], "divb_rel": red["divb_rel"], "c2p_fail": red["c2p_fail"],
+                  "c2p_fail_total": red["c2p_fail_total"],
                   "floor_hits": red["floor_hits"], "c2p_iter_mean": red["c2p_iter_mean"],
                   "c2p_iter_wavemax_mean": red["c2p_iter_wavemax_mean"]},
         "cpu_baseline": cpu,

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define GRMHD_ABI_VERSION 2
+#define GRMHD_ABI_VERSION 3
 
 enum { GRMHD_OK = 0, GRMHD_E_INVALID = -1, GRMHD_E_SHAPE = -2, GRMHD_E_HIP = -3,
        GRMHD_E_UNSUPPORTED = -4 };
@@ -140,6 +140,9 @@ typedef struct { void *P, *Bf, *U, *U0, *Bf0; } grmhd_state_ptrs;
  *   divb_rel: max |sum_d delta_d Bf_d / dx_d| / (max |Bf| / min dx);
  *   totals[5]: sum over interior of U_v dx1 dx2 dx3;
  *   c2p_fail, floor_hits: flagged cells of the last con2prim;
+ *   c2p_fail_total: failed inversions summed over every con2prim since the
+ *   pack was created (a device counter that both inversions of every step
+ *   add to; the difference of two reads counts the calls in between);
  *   c2p_iter_mean / c2p_iter_wavemax_mean: Newton iterations per cell and the
  *   mean over 64-cell wavefronts of the per-wavefront maximum;
  *   total_scalar: sum over interior of U_5 dx1 dx2 dx3 (0 without a scalar).
@@ -150,6 +153,7 @@ typedef struct {
   double c2p_iter_mean, c2p_iter_wavemax_mean;
   long long guess_fallback;   /* cells whose learned guess was rejected */
   double total_scalar;
+  long long c2p_fail_total;
 } grmhd_reduction_out;
 
 int grmhd_abi_version(void);
@@ -190,8 +194,10 @@ int grmhd_fill_ghosts(grmhd_pack *pack, const grmhd_metric *metric);
  * rk_coeffs = {c0, c1, c_dt}.  When c1 == 0 the current U and Bf are the
  * base: they are first saved into U0 and Bf0 (so SSPRK2 is {1,0,1} then
  * {1/2,1/2,1/2}).  dt <= 0 means: use the device-resident dt written by the
- * last grmhd_reductions (no host round trip).  Requires grmhd_fill_ghosts
- * since the last change of P or Bf.
+ * last reduction fold (grmhd_reductions, or a grmhd_step with cfl > 0; no
+ * host round trip); before any fold of this pack such a call returns
+ * GRMHD_E_INVALID.  Requires grmhd_fill_ghosts since the last change of P
+ * or Bf.
  */
 int grmhd_stage(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos,
                 double dt, const double rk_coeffs[3]);
@@ -205,7 +211,10 @@ int grmhd_stage(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *e
  * current P; MLP: the learned initial guess bound by grmhd_mlp_bind, used
  * where the W it implies through the master function agrees with the
  * network's own W output to 50 %, else COLD and flag GUESS_FALLBACK).
- * A failed inversion keeps the previous P.  Where a floor or the failure
+ * The inversion fails (flag C2P_FAIL) for D <= 0 or a non-finite U, when
+ * f(1) < 0 (no root in (0, 1]), when Newton has not met |dmu| <= c2p_tol mu
+ * within c2p_max_iter iterations, and when the root's primitives are not
+ * finite.  A failed inversion keeps the previous P.  Where a floor or the failure
  * acts, the hydro part of U is rewritten from the final P (Sec. 3.1
  * inversion, Sec. 3.2 floors).
  */

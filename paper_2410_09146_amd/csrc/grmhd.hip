@@ -29,6 +29,11 @@ namespace {
 thread_local std::string g_err;
 
 constexpr size_t ALIGN = 256;
+// reduction result block in the workspace: 16 doubles written by the fold
+// (dt first); slot RES_NFAIL holds the device counter of failed inversions
+// (every con2prim adds its failures; zeroed once, at pack creation)
+constexpr int RES_SLOTS = 32;
+constexpr int RES_NFAIL = 24;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Everything derived from a descriptor on the host.
@@ -649,7 +654,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_fixF = take(sizeof(FixF) * p.fixF.size());
   p.o_fixE = take(sizeof(FixE) * p.fixE.size());
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
-  p.o_res = take(sizeof(double) * 32);
+  p.o_res = take(sizeof(double) * RES_SLOTS);
   p.o_mlp = take(sizeof(float) * 2 * (size_t)p.nct);   // learned mu0 and W per cell
   p.o_mlpw = take(sizeof(unsigned short) * MLPB_N);
   p.o_mlpf = take(sizeof(float) * MLPF_N);
@@ -673,6 +678,7 @@ struct grmhd_pack {
   int tune_sh = -1;             // >= 0 while the autotuner times one shape
   int tune_dir = -1;            // direction being timed (-1: all)
   int persist = 0;              // > 0: persistent flux grid of this many workgroups
+  bool dt_ready = false;        // a reduction fold has written the device dt
   // captured SSPRK2 step (dt read on the device)
   hipGraphExec_t gexec = nullptr;
   int g_guess = -1;
@@ -708,6 +714,7 @@ struct grmhd_pack {
     a.E = (double *)(ws + plan.o_E);
     std::memset(&a.et, 0, sizeof a.et);
     a.npv = 5 + desc.nscalar;
+    a.nfail = (unsigned long long *)(ws + plan.o_res) + RES_NFAIL;
     return a;
   }
 };
@@ -1212,6 +1219,8 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   // flags / iteration counters / flux scratch start defined
   if (!e) e = hipMemsetAsync(p->ws + pl.o_flags, 0, 2 * align_up(pl.nct), p->stream);
   if (!e) e = hipMemsetAsync(p->ws + pl.o_F, 0, sizeof(double) * 24 * (size_t)pl.nct, p->stream);
+  // reduction results (dt = 0 until the first fold) and the failure counter
+  if (!e) e = hipMemsetAsync(p->ws + pl.o_res, 0, sizeof(double) * RES_SLOTS, p->stream);
   // host vectors must outlive the async copies
   if (!e) e = hipStreamSynchronize(p->stream);
   if (e) {
@@ -1296,6 +1305,9 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   if (int rc = check_metric(p, m)) return rc;
   if (int rc = check_eos(p, eos)) return rc;
   if (!rk) return perr(p, "null rk_coeffs", GRMHD_E_INVALID);
+  if (!(dt > 0.0) && !p->dt_ready)
+    return perr(p, "dt <= 0 asks for the device-resident dt, but no reduction has written one "
+                   "(call grmhd_reductions or a grmhd_step with cfl > 0 first)", GRMHD_E_INVALID);
   KArgs a = p->args();
   a.met.M = m->M; a.met.a = m->a;
   fill_eos(a, eos);
@@ -1405,6 +1417,7 @@ int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, in
   }
   }
   if (reduce) {
+    p->dt_ready = true;
     Prof t(p, GRMHD_PROF_REDUCE);
     hipLaunchKernelGGL(k_reduce_fin, dim3(1), dim3(256), 0, p->stream, (const double *)part,
                        (int)pl.ch_int.size(), cfl, pl.dxmin, (double *)(p->ws + pl.o_res));
@@ -1473,8 +1486,9 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
                      (int)pl.ch_int.size(), cfl, pl.dxmin, res);
   }
   LAUNCHCHK(p);
+  p->dt_ready = true;
   if (out) {
-    double h[16];
+    double h[RES_SLOTS];
     HIPCHK(p, hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(p, hipStreamSynchronize(p->stream));
     out->dt = h[0];
@@ -1494,6 +1508,9 @@ int grmhd_reductions(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
       const long long live = std::min<long long>(256, nb - c.y);
       nwave += (live + 63) / 64;
     }
+    unsigned long long nfail;
+    std::memcpy(&nfail, &h[RES_NFAIL], sizeof nfail);
+    out->c2p_fail_total = (long long)nfail;
     out->guess_fallback = (long long)h[14];
     out->total_scalar = h[15];
     out->c2p_iter_mean = ncell ? h[10] / ncell : 0.0;

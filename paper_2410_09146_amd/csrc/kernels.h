@@ -33,6 +33,7 @@ struct KArgs {
   double *E;            // two-level meshes: edge EMFs [3][nct] (corrected at level boundaries)
   EosTab et;            // tabulated EOS (et.d == nullptr: ideal gas)
   int npv;              // primitive planes: 5, or 6 with the Y_e scalar in P[5]
+  unsigned long long *nfail;  // failed inversions since the pack was created
 };
 
 // p and Gamma_1 p of a cell or face state: the table when one is bound (only
@@ -876,6 +877,8 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
         mu = mn;
         if (dmu <= tol * mu) break;
       }
+      // no root within the iteration cap: the state counts as not inverted
+      if (iters > a.eos.max_iter) ok = false;
       const double x = inv(1.0 + mu * m.b2);
       const double rbar2 = m.r2 * x * x + mu * x * (1.0 + x) * m.rb * m.rb;
       const double qbar = m.q - 0.5 * m.b2 - 0.5 * mu * mu * x * x * (m.b2 * m.r2 - m.rb * m.rb);
@@ -893,6 +896,11 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
       q.u1 = f1 * (Su1 * iD + f2 * B1);
       q.u2 = f1 * (Su2 * iD + f2 * B2);
       q.u3 = f1 * (Su3 * iD + f2 * B3);
+      // a root whose primitives are not finite (the v^2 bound rounded to 1,
+      // so W overflowed) is no inversion either
+      if (!(q.rho > 0.0) || !isfinite(q.rho) || !isfinite(q.ie) || !isfinite(q.u1) ||
+          !isfinite(q.u2) || !isfinite(q.u3))
+        ok = false;
     }
   }
   if (!ok) {
@@ -925,6 +933,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   if (flag & 47) cons_store<MK, NSC>(a, c, G, q, Ur);
   a.flags[c] = (int8_t)flag;
   a.iters[c] = (uint8_t)min(iters, 255);
+  if (flag & 8) atomicAdd(a.nfail, 1ull);
   if constexpr (RED != 0) cell_diag<MK, NSC>(a, b, G, q, bf, Ur, flag, min(iters, 255), val);
 }
 

@@ -55,7 +55,8 @@ class ReductionOut(ctypes.Structure):
                 ("divb_max", ctypes.c_double), ("totals", ctypes.c_double * 5),
                 ("c2p_fail", ctypes.c_longlong), ("floor_hits", ctypes.c_longlong),
                 ("c2p_iter_mean", ctypes.c_double), ("c2p_iter_wavemax_mean", ctypes.c_double),
-                ("guess_fallback", ctypes.c_longlong), ("total_scalar", ctypes.c_double)]
+                ("guess_fallback", ctypes.c_longlong), ("total_scalar", ctypes.c_double),
+                ("c2p_fail_total", ctypes.c_longlong)]
 
 
 EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
@@ -441,7 +442,8 @@ class Pack:
                 "totals": np.array(out.totals[:]), "c2p_fail": out.c2p_fail,
                 "floor_hits": out.floor_hits, "c2p_iter_mean": out.c2p_iter_mean,
                 "c2p_iter_wavemax_mean": out.c2p_iter_wavemax_mean,
-                "guess_fallback": out.guess_fallback, "total_scalar": out.total_scalar}
+                "guess_fallback": out.guess_fallback, "total_scalar": out.total_scalar,
+                "c2p_fail_total": out.c2p_fail_total}
 
     def m1_source(self, R, kap, dt, couple=False, tol=1e-13, max_iter=40, iters=None):
         """Implicit gray-M1 collision update (grmhd_m1_source).  R: float64

@@ -30,6 +30,16 @@ def rel_err(a, b, prob, face=False):
     return np.array(out)
 
 
+def totals_drift(r1, r0, floor=1e-2):
+    """Per-total relative change of the conserved totals between two
+    reductions, each normalised by its own magnitude (at least floor times
+    the largest total, so that a total near zero is judged on a scale of its
+    own kind rather than the energy's)."""
+    t0, t1 = np.asarray(r0["totals"]), np.asarray(r1["totals"])
+    den = np.maximum(np.abs(t0), floor * np.abs(t0).max())
+    return np.abs(t1 - t0) / den
+
+
 def oracle_state(prob, nthreads=8):
     """Initial (P, Bf, U) from the oracle (ghosts filled)."""
     blk = oracle.Block(prob)

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(L):
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(G.EXPORTS)
-    assert L.grmhd_abi_version() == 2
+    assert L.grmhd_abi_version() == 3
 
 
 def _desc(prob, nblk=(1, 1, 1), **over):

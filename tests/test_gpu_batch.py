@@ -61,4 +61,4 @@ def test_batch_256_octree_pack():
     say("256^3 batch:", nb, "blocks; eP", eP.max(), "eB", eB.max(), "divb", rn["divb_rel"])
     assert 500 <= nb <= 800
     assert np.all(eP <= 1e-13) and np.all(eB <= 1e-13)
-    assert rn["divb_rel"] < 1e-12 and rn["c2p_fail"] == 0
+    assert rn["divb_rel"] < 1e-12 and rn["c2p_fail_total"] == 0

@@ -70,8 +70,12 @@ def test_mfma_inference_matches_bf16_reference(env):
     scale = np.abs(h).max()
     err = np.abs(Yg - h)
     say("mfma inference: max err", err.max() / scale, "median", np.median(err) / scale)
-    assert err.max() <= 2e-2 * scale
-    assert np.median(err) <= 2e-3 * scale
+    # The kernel's SiLU (hardware exp2 and reciprocal) and the reference's
+    # differ by a few FP32 ulp, which now and then moves a hidden activation
+    # to the neighbouring BF16 value (a step of 2^-8 of it); one such step in a
+    # 64-term sum moves an output by ~1e-4 of the output scale.
+    assert err.max() <= 5e-4 * scale
+    assert np.median(err) <= 5e-5 * scale
 
 
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from paper_2410_09146_amd import inputs as I
-from parity_util import oracle_state, rel_err, say, upload_all
+from parity_util import oracle_state, rel_err, say, totals_drift, upload_all
 
 pytestmark = pytest.mark.gpu
 
@@ -111,13 +111,18 @@ def test_stage_fluxes_and_update(grmhd, case):
             hi = [g + prob.n[k] + 1 for k in range(3)]
             lo[d] = g
             sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
-            # diagnostic: face fluxes of direction d against that direction's
-            # largest flux component (individual components can be pure
-            # cancellation, e.g. the energy flux of a static background)
-            den = max(np.abs(Fo[d][(slice(None),) + sl]).max(), 1e-300)
+            # each flux component against its own max norm, floored at
+            # 1e-12 of the direction's largest component (a component that is
+            # zero on both sides, e.g. the normal field's slot, passes at 0)
+            scale = max(np.abs(Fo[d][(slice(None),) + sl]).max(), 1e-300)
+            worst = []
             for v in range(8):
                 a, b = Fg[d, v][sl], Fo[d, v][sl]
-                assert np.abs(a - b).max() / den <= TOL, (case, d, v, np.abs(a - b).max() / den)
+                den = max(np.abs(b).max(), 1e-12 * scale)
+                worst.append(np.abs(a - b).max() / den)
+            say("  flux", case, "rk", rk, "dir", d, "own-norm err per component",
+                " ".join(f"{w:.1e}" for w in worst))
+            assert max(worst) <= TOL, (case, d, worst)
         eU = rel_err(pack.download("U"), Uo, prob)
         eB = rel_err(pack.download("Bf"), Bo, prob, face=True)
         say("  rk", rk, "eU", eU.max(), "eB", eB.max())
@@ -388,13 +393,16 @@ def test_periodic_box_conserves_and_keeps_divb_on_gpu(grmhd, recon, riemann, nbl
     pack = grmhd.Pack(prob) if nblk is None else grmhd.Pack(prob, nblk=nblk)
     pack.init()
     r0 = pack.reductions()
-    scale = np.abs(r0["totals"]).max()
-    worst_t = worst_d = 0.0
+    worst_t = np.zeros(5)
+    worst_d = 0.0
+    nfail = []
     for _ in range(20):
         pack.step(pack.reductions()["dt"])
         r = pack.reductions()
-        worst_t = max(worst_t, float(np.abs(r["totals"] - r0["totals"]).max() / scale))
+        worst_t = np.maximum(worst_t, totals_drift(r, r0))
         worst_d = max(worst_d, r["divb_rel"])
-    say("periodic 64^3", recon, riemann, nblk, "totals drift", worst_t, "divb_rel", worst_d,
-        "c2p fail", r["c2p_fail"])
-    assert worst_t <= 1e-13 and worst_d <= 1e-13 and r["c2p_fail"] == 0
+        # failures of both inversions of the step (cumulative device counter)
+        nfail.append(r["c2p_fail_total"] - r0["c2p_fail_total"])
+    say("periodic 64^3", recon, riemann, nblk, "totals drift per total", worst_t, "divb_rel",
+        worst_d, "c2p fail (cumulative)", nfail[-1])
+    assert np.all(worst_t <= 1e-13) and worst_d <= 1e-13 and nfail[-1] == 0
