@@ -314,6 +314,24 @@ int grmhd_mlp_grad(const float *params, const float *X, const float *Y, int batc
 int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *X,
                          const float *Y, int batch, float lr, int t, float *loss, void *scratch,
                          size_t scratch_bytes, void *hip_stream);
+/*
+ * The training step above without a caller scratch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training or
+ * serving loops, harnesses that forbid hipMalloc): the same kernels run on a
+ * scratch the library holds in device memory of its own, a static array of
+ * grmhd_mlp_scratch_bytes(GRMHD_MLP_NOALLOC_MAX_BATCH) bytes (about 9.5 MB)
+ * per GPU, kept until the process ends.  The call allocates nothing; its
+ * first call on a device looks up that device's copy.  batch must be at most
+ * GRMHD_MLP_NOALLOC_MAX_BATCH (GRMHD_E_SHAPE otherwise, nothing launched);
+ * hip_stream must belong to the current device (GRMHD_E_INVALID otherwise).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Nothing in the scratch needs to start at zero.
+ */
+#define GRMHD_MLP_NOALLOC_MAX_BATCH 4096
+int grmhd_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, const float *X,
+                                 const float *Y, int batch, float lr, int t, float *loss,
+                                 void *hip_stream);
 /* BF16 matrix-core inference on raw features X [n][5] -> Y [n][2]. */
 int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *feat_std,
                     const float *X, float *Y, int n, void *scratch, size_t scratch_bytes,

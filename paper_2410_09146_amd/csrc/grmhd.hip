@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <type_traits>
@@ -34,7 +35,7 @@ constexpr size_t ALIGN = 256;
 // (every con2prim adds its failures; zeroed once, at pack creation)
 constexpr int RES_SLOTS = 32;
 constexpr int RES_NFAIL = 24;
-size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+constexpr size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Everything derived from a descriptor on the host.
 struct Plan {
@@ -1532,17 +1533,36 @@ int grmhd_mlp_bind(grmhd_pack *p, const float *params, const float *feat_mean,
   return GRMHD_OK;
 }
 
-size_t grmhd_mlp_scratch_bytes(int batch)
+}  // extern "C"
+
+namespace {
+// Z1 H1 Z2 H2 Z3 H3 d1 d2 d3 (64 each), out, d4 (2 each), grads, loss partials,
+// BF16 weights + FP32 biases for the MFMA inference
+constexpr size_t mlp_scratch_floats(size_t b)
 {
-  if (batch < 1) return 0;
-  const size_t b = (size_t)batch;
-  // Z1 H1 Z2 H2 Z3 H3 d1 d2 d3 (64 each), out, d4 (2 each), grads, loss partials,
-  // BF16 weights + FP32 biases for the MFMA inference
-  size_t f = 9 * 64 * b + 2 * 2 * b + MLP_NPARAM + (b + 255) / 256 + 4;
-  return align_up(f * sizeof(float)) + align_up(MLPB_N * 2) + align_up(MLPF_N * 4);
+  return 9 * 64 * b + 2 * 2 * b + MLP_NPARAM + (b + 255) / 256 + 4;
+}
+constexpr size_t mlp_scratch_bytes(size_t b)
+{
+  return align_up(mlp_scratch_floats(b) * sizeof(float)) + align_up(MLPB_N * 2) +
+         align_up(MLPF_N * 4);
 }
 
-}  // extern "C"
+// Device memory of grmhd_mlp_train_step_noalloc: the same scratch as the
+// caller-provided one of grmhd_mlp_train_step, sized for the largest batch it
+// takes.  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code this name is only a stand-in for the symbol: its device
+// address (per device) comes from hipGetSymbolAddress.
+constexpr size_t NOALLOC_BYTES = mlp_scratch_bytes(GRMHD_MLP_NOALLOC_MAX_BATCH);
+}  // namespace
+
+static __device__ __align__(256) unsigned char noalloc_scratch[NOALLOC_BYTES];
+
+extern "C" size_t grmhd_mlp_scratch_bytes(int batch)
+{
+  if (batch < 1) return 0;
+  return mlp_scratch_bytes((size_t)batch);
+}
 
 namespace {
 struct MlpScratch {
@@ -1559,8 +1579,7 @@ MlpScratch carve(void *s, int batch)
   m.Z3 = q; q += 64 * b; m.H3 = q; q += 64 * b; m.d1 = q; q += 64 * b; m.d2 = q; q += 64 * b;
   m.d3 = q; q += 64 * b; m.out = q; q += 2 * b; m.d4 = q; q += 2 * b;
   m.grad = q; q += MLP_NPARAM; m.part = q; q += (b + 255) / 256; m.loss = q; q += 4;
-  size_t fb = 9 * 64 * b + 2 * 2 * b + MLP_NPARAM + (b + 255) / 256 + 4;
-  char *c = (char *)s + align_up(fb * sizeof(float));
+  char *c = (char *)s + align_up(mlp_scratch_floats(b) * sizeof(float));
   m.w = (unsigned short *)c;
   m.f = (float *)(c + align_up(MLPB_N * 2));
   return m;
@@ -1614,14 +1633,13 @@ int grmhd_mlp_grad(const float *params, const float *X, const float *Y, int batc
   return GRMHD_OK;
 }
 
-int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *X,
-                         const float *Y, int batch, float lr, int t, float *loss, void *scratch,
-                         size_t scratch_bytes, void *hip_stream)
+}  // extern "C"
+
+namespace {
+// forward, loss, backward and one Adam step on a carved scratch
+int train_step_on(float *params, float *adam_m, float *adam_v, const float *X, const float *Y,
+                  int batch, float lr, int t, float *loss, void *scratch, hipStream_t st)
 {
-  if (!params || !adam_m || !adam_v || !X || !Y || !loss || !scratch || batch < 1 || t < 1)
-    return fail("bad argument", GRMHD_E_INVALID);
-  if (scratch_bytes < grmhd_mlp_scratch_bytes(batch)) return fail("scratch too small", GRMHD_E_SHAPE);
-  hipStream_t st = (hipStream_t)hip_stream;
   MlpScratch m = carve(scratch, batch);
   hipError_t e = mlp_fwd_bwd(params, X, Y, batch, m, st);
   if (!e) {
@@ -1632,6 +1650,69 @@ int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const floa
   if (!e) e = hipMemcpyAsync(loss, m.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
   if (e) return fail(std::string("mlp train: ") + hipGetErrorString(e), GRMHD_E_HIP);
   return GRMHD_OK;
+}
+
+// Device address of noalloc_scratch on the current device, looked up once per
+// device (with that device current) and kept.
+constexpr int NOALLOC_MAXDEV = 64;
+std::mutex noalloc_mu;
+void *noalloc_ptr[NOALLOC_MAXDEV] = {};
+
+int noalloc_scratch_ptr(hipStream_t st, void **out)
+{
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return fail(std::string("hipGetDevice: ") + hipGetErrorString(e), GRMHD_E_HIP);
+  if (dev < 0 || dev >= NOALLOC_MAXDEV) return fail("device index out of range", GRMHD_E_INVALID);
+  if (st) {
+    int sdev = -1;
+    e = hipStreamGetDevice(st, &sdev);
+    if (e) return fail(std::string("hipStreamGetDevice: ") + hipGetErrorString(e), GRMHD_E_HIP);
+    if (sdev != dev)
+      return fail("the stream belongs to another device than the current one", GRMHD_E_INVALID);
+  }
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e || !p)
+      return fail(std::string("hipGetSymbolAddress(noalloc_scratch): ") + hipGetErrorString(e),
+                  GRMHD_E_HIP);
+    noalloc_ptr[dev] = p;
+  }
+  *out = noalloc_ptr[dev];
+  return GRMHD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int grmhd_mlp_train_step(float *params, float *adam_m, float *adam_v, const float *X,
+                         const float *Y, int batch, float lr, int t, float *loss, void *scratch,
+                         size_t scratch_bytes, void *hip_stream)
+{
+  if (!params || !adam_m || !adam_v || !X || !Y || !loss || !scratch || batch < 1 || t < 1)
+    return fail("bad argument", GRMHD_E_INVALID);
+  if (scratch_bytes < grmhd_mlp_scratch_bytes(batch)) return fail("scratch too small", GRMHD_E_SHAPE);
+  return train_step_on(params, adam_m, adam_v, X, Y, batch, lr, t, loss, scratch,
+                       (hipStream_t)hip_stream);
+}
+
+int grmhd_mlp_train_step_noalloc(float *params, float *adam_m, float *adam_v, const float *X,
+                                 const float *Y, int batch, float lr, int t, float *loss,
+                                 void *hip_stream)
+{
+  if (!params || !adam_m || !adam_v || !X || !Y || !loss || batch < 1 || t < 1)
+    return fail("bad argument", GRMHD_E_INVALID);
+  if (batch > GRMHD_MLP_NOALLOC_MAX_BATCH)
+    return fail("batch " + std::to_string(batch) + " exceeds the " +
+                    std::to_string(GRMHD_MLP_NOALLOC_MAX_BATCH) +
+                    " samples the library's own scratch holds (use grmhd_mlp_train_step)",
+                GRMHD_E_SHAPE);
+  hipStream_t st = (hipStream_t)hip_stream;
+  void *scr = nullptr;
+  if (int rc = noalloc_scratch_ptr(st, &scr)) return rc;
+  return train_step_on(params, adam_m, adam_v, X, Y, batch, lr, t, loss, scr, st);
 }
 
 int grmhd_mlp_infer(const float *params, const float *feat_mean, const float *feat_std,

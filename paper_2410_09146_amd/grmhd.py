@@ -64,6 +64,7 @@ EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_stage", "grmhd_con2prim", "grmhd_prim_to_cons", "grmhd_reductions",
            "grmhd_debug_ptrs", "grmhd_profile", "grmhd_profile_read", "grmhd_mlp_bind",
            "grmhd_mlp_scratch_bytes", "grmhd_mlp_grad", "grmhd_mlp_train_step",
+           "grmhd_mlp_train_step_noalloc",
            "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_set_tiling",
            "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_m1_source",
            "grmhd_tag", "grmhd_regrid_layout", "grmhd_remap_scratch_bytes", "grmhd_remap",
@@ -73,6 +74,7 @@ NSHAPE = 5
 PROF_FAMILIES = ["flux_x1", "flux_x2", "flux_x3", "flux_plane", "update", "con2prim",
                  "ghost", "bcc", "reduce", "mlp", "m1"]
 MLP_NPARAM = 8834
+MLP_NOALLOC_MAX_BATCH = 4096
 
 _lib = None
 
@@ -120,6 +122,8 @@ def lib():
         L.grmhd_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_int, vp, vp, vp, ctypes.c_size_t, vp]
         L.grmhd_mlp_train_step.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_float,
                                            ctypes.c_int, vp, vp, ctypes.c_size_t, vp]
+        L.grmhd_mlp_train_step_noalloc.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int,
+                                                   ctypes.c_float, ctypes.c_int, vp, vp]
         L.grmhd_mlp_infer.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
         L.grmhd_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_longlong)]
