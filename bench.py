@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--fused", action="store_true",
+                    help="torus: the optional fused stage (hydro update inside the flux tiles)")
     ap.add_argument("--persist", type=int, default=0,
                     help="persistent flux grid size in workgroups (0, the default: one "
                          "workgroup per tile, which measured faster on every workload)")
@@ -321,6 +323,8 @@ def main():
     prob = I.torus(n=(n, n, n), recon=getattr(I, RECON_NAMES[args.recon][0]),
                    riemann=I.RIEMANN_LLF if args.riemann == "llf" else I.RIEMANN_HLL)
     pack = G.Pack(prob, device="cuda:0")
+    if args.fused:
+        pack.set_fused(True)
     pack.init()
     pack.reductions(sync=False)        # device-resident dt for the first step
     tiles, tune_ms = pack.autotune(reps=3) if not args.no_autotune else ([0, 0, 0], None)
@@ -418,7 +422,8 @@ def main():
         "config": {"workload": f"Kerr-Schild torus {n}^3 (a=0.9375, FM r_in=6 r_max=12, "
                                "gamma=13/9, beta=100 loop field, noise 4e-2 seed 1), "
                                f"{RECON_NAMES[args.recon][1]} + {args.riemann.upper()}, CT, "
-                               "SSPRK2, FP64, one meshblock",
+                               "SSPRK2, FP64, one meshblock"
+                               + (", fused stage" if args.fused else ""),
                    "cells": ncell, "parallelism": "single GPU"},
         "roofline": roof, "hbm_view": hbm, "kernels": kernels,
         "timing": "value and ms_per_step: K graph-replayed steps (the whole SSPRK2 step "

@@ -266,6 +266,19 @@ int grmhd_set_tiling(grmhd_pack *pack, const int shape[3]);
  * many workgroups striding over the tile work-list; 0: one workgroup per tile. */
 int grmhd_set_persistent(grmhd_pack *pack, int workgroups);
 int grmhd_get_tiling(const grmhd_pack *pack, int shape[3]);
+/*
+ * Fused stage (optional, off by default; single-level packs without the
+ * scalar): the flux tiles of x1 and x2 leave their part of the hydro flux divergence in
+ * the workspace and those of x3 add theirs, the sources (Sec. 2.1) and the
+ * Runge-Kutta combination, so no hydro face flux reaches device memory and
+ * the boundary-plane launch is not needed (tiles along D overlap by one face);
+ * the update kernel then does constrained transport only.  The face-flux
+ * scratch then holds only the induction fluxes.  enable = 0 is the default
+ * unfused path (every face flux stored, grmhd_debug_ptrs' flux array
+ * complete).  GRMHD_E_UNSUPPORTED for two-level packs and packs with the
+ * scalar, which always run unfused.
+ */
+int grmhd_set_fused(grmhd_pack *pack, int enable);
 int grmhd_autotune(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos, int reps,
                    int chosen[3], double *ms_table);
 

@@ -45,6 +45,9 @@ struct Plan {
   std::vector<BlockInfo> blocks;
   std::vector<double> rc, rf, sc, cc, sf, cf;
   std::vector<int4> tiles[3][NSHAPE];
+  // fused stage: tiles along D at stride TD - 1 over the faces ng .. ng + n
+  // (the block's upper face included), for single-level packs
+  std::vector<int4> tilesF[3][NSHAPE];
   std::vector<int2> planes;       // (3 block + D, first face), 64 faces each
   std::vector<int2> ch_int, ch_ext, ch_bcc;
   std::vector<GhostP> gP;
@@ -67,7 +70,7 @@ struct Plan {
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes, o_chi, o_che,
       o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res, o_mlp,
       o_mlpw, o_mlpf, total;
-  size_t o_tl[3][NSHAPE];
+  size_t o_tl[3][NSHAPE], o_tlF[3][NSHAPE];
 };
 
 int fail(const std::string &m, int code)
@@ -266,6 +269,14 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
               o[D] = f0; o[AX] = a0; o[BX] = kb;
               p.tiles[D][sh].push_back(make_int4(b, o[0], o[1], o[2]));
             }
+        if (p.maxlev == 0 && !d->nscalar)
+          for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
+            for (int a0 = ng - 1; a0 <= ng + bi.n[AX]; a0 += ta)
+              for (int f0 = ng; f0 < ng + bi.n[D]; f0 += td - 1) {
+                int o[3];
+                o[D] = f0; o[AX] = a0; o[BX] = kb;
+                p.tilesF[D][sh].push_back(make_int4(b, o[0], o[1], o[2]));
+              }
       }
     }
   }
@@ -284,7 +295,10 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     L.swap(out);
   };
   for (int D = 0; D < 3; ++D)
-    for (int sh = 0; sh < NSHAPE; ++sh) xcd_order(p.tiles[D][sh]);
+    for (int sh = 0; sh < NSHAPE; ++sh) {
+      xcd_order(p.tiles[D][sh]);
+      xcd_order(p.tilesF[D][sh]);
+    }
   for (int b = 0; b < p.nb; ++b) {
     const BlockInfo &bi = p.blocks[b];
     for (int D = 0; D < 3; ++D) {
@@ -638,7 +652,10 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_blocks = take(sizeof(BlockInfo) * p.nb);
   p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
   for (int D = 0; D < 3; ++D)
-    for (int sh = 0; sh < NSHAPE; ++sh) p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
+    for (int sh = 0; sh < NSHAPE; ++sh) {
+      p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
+      p.o_tlF[D][sh] = take(sizeof(int4) * p.tilesF[D][sh].size());
+    }
   p.o_planes = take(sizeof(int2) * p.planes.size());
   p.o_chi = take(sizeof(int2) * p.ch_int.size());
   p.o_che = take(sizeof(int2) * p.ch_ext.size());
@@ -680,6 +697,11 @@ struct grmhd_pack {
   int tune_dir = -1;            // direction being timed (-1: all)
   int persist = 0;              // > 0: persistent flux grid of this many workgroups
   bool dt_ready = false;        // a reduction fold has written the device dt
+  // fused stage (optional; single-level packs without the scalar): the flux
+  // tiles do the hydro divergence, sources and RK update, the update kernel
+  // keeps CT only
+  bool fused = false;
+  RkArgs rk{};                  // the stage being launched (fused tiles)
   // captured SSPRK2 step (dt read on the device)
   hipGraphExec_t gexec = nullptr;
   int g_guess = -1;
@@ -832,12 +854,21 @@ template <int MK, int D, int RC, int FV, int RS, typename T, int SH, int NSC>
 void launch_tiles(grmhd_pack *p, const KArgs &a)
 {
   const Plan &pl = p->plan;
-  if (pl.tiles[D][SH].empty()) return;
+  const bool fz = p->fused && NSC == 0;
+  const auto &L = fz ? pl.tilesF[D][SH] : pl.tiles[D][SH];
+  if (L.empty()) return;
   Prof t(p, GRMHD_PROF_FLUX_X1 + D);
-  const int nt = (int)pl.tiles[D][SH].size();
+  const int nt = (int)L.size();
   const int grid = p->persist > 0 ? std::min(nt, p->persist) : nt;
-  hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, NSC>), dim3(grid), dim3(256), 0, p->stream,
-                     a, dptr<int4>(p, pl.o_tl[D][SH]), nt);
+  if constexpr (NSC == 0) {
+    if (fz) {
+      hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, 0, 1>), dim3(grid), dim3(256), 0,
+                         p->stream, a, dptr<int4>(p, pl.o_tlF[D][SH]), nt, p->rk);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, NSC, 0>), dim3(grid), dim3(256), 0,
+                     p->stream, a, dptr<int4>(p, pl.o_tl[D][SH]), nt, p->rk);
 }
 
 // Every shape is instantiated for the WENO5-Z-AOAH point-value path (the
@@ -875,6 +906,7 @@ void launch_flux3(grmhd_pack *p, const KArgs &a)
   if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T, NSC>(p, a);
   const Plan &pl = p->plan;
   if (p->tune_sh >= 0 || pl.planes.empty()) return;   // autotuning times the tiles alone
+  if (p->fused) return;           // the fused tiles include the upper faces
   Prof t(p, GRMHD_PROF_FLUX_PLANE);
   hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T, NSC>), dim3(pl.planes.size()), dim3(64), 0,
                      p->stream, a, dptr<int2>(p, pl.o_planes));
@@ -1204,7 +1236,10 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   if (!e) e = up(pl.o_tab, tab.data(), sizeof(double) * tab.size());
   for (int D = 0; D < 3; ++D)
     for (int sh = 0; sh < NSHAPE; ++sh)
+    {
       if (!e) e = up(pl.o_tl[D][sh], pl.tiles[D][sh].data(), sizeof(int4) * pl.tiles[D][sh].size());
+      if (!e) e = up(pl.o_tlF[D][sh], pl.tilesF[D][sh].data(), sizeof(int4) * pl.tilesF[D][sh].size());
+    }
   if (!e) e = up(pl.o_planes, pl.planes.data(), sizeof(int2) * pl.planes.size());
   if (!e) e = up(pl.o_chi, pl.ch_int.data(), sizeof(int2) * pl.ch_int.size());
   if (!e) e = up(pl.o_che, pl.ch_ext.data(), sizeof(int2) * pl.ch_ext.size());
@@ -1315,11 +1350,12 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   const Plan &pl = p->plan;
   const int rc = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
   const int prec = p->desc.precision;
+  const double *dtd = dptr<double>(p, pl.o_res);
+  const int save = rk[1] == 0.0;
+  p->rk = RkArgs{dt, dtd, rk[0], rk[1], rk[2], save};
   if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rc, fv, rs, prec);
   else launch_flux_all<MK_MINK>(p, a, rc, fv, rs, prec);
   LAUNCHCHK(p);
-  const double *dtd = dptr<double>(p, pl.o_res);
-  const int save = rk[1] == 0.0;
   Prof t(p, GRMHD_PROF_UPDATE);
   const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
   if (pl.maxlev > 0) {
@@ -1342,6 +1378,12 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
     if (ks) hipLaunchKernelGGL((k_update<MK_KS, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
                                p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
     else hipLaunchKernelGGL((k_update<MK_MINK, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+  } else if (p->fused) {
+    // the flux tiles did the hydro update: constrained transport only
+    if (ks) hipLaunchKernelGGL((k_update<MK_KS, 0, 0, 0>), dim3(pl.ch_ext.size()), dim3(256), 0,
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+    else hipLaunchKernelGGL((k_update<MK_MINK, 0, 0, 0>), dim3(pl.ch_ext.size()), dim3(256), 0,
                             p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
   } else if (ks) {
     hipLaunchKernelGGL((k_update<MK_KS, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
@@ -2006,6 +2048,17 @@ int grmhd_set_persistent(grmhd_pack *p, int workgroups)
   return GRMHD_OK;
 }
 
+int grmhd_set_fused(grmhd_pack *p, int enable)
+{
+  if (!p) return GRMHD_E_INVALID;
+  if (enable && (p->plan.maxlev > 0 || p->desc.nscalar))
+    return perr(p, "the fused stage needs a single-level pack without the scalar",
+                GRMHD_E_UNSUPPORTED);
+  p->fused = enable != 0;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  return GRMHD_OK;
+}
+
 int grmhd_get_tiling(const grmhd_pack *p, int shape[3])
 {
   if (!p || !shape) return GRMHD_E_INVALID;
@@ -2026,6 +2079,13 @@ int grmhd_autotune(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, i
   const int rcn = p->desc.recon, rs = p->desc.riemann, fv = p->desc.weno_fv;
   const int prec = p->desc.precision;
   const bool all = rcn == RC_WENO && fv == 0 && (!p->desc.nscalar || rs == RS_LLF);
+  if (p->fused) {
+    // the fused x3 tiles end in the Runge-Kutta update: timed here, it writes
+    // into unused flux scratch (the x2 hydro slots) instead of U, U0
+    a.U = a.F + 8 * a.nct;
+    a.U0 = a.U;
+    p->rk = RkArgs{1.0, nullptr, 1.0, 0.0, 1.0, 0};
+  }
   hipEvent_t e0, e1;
   HIPCHK(p, hipEventCreate(&e0));
   HIPCHK(p, hipEventCreate(&e1));

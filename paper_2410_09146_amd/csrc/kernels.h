@@ -36,6 +36,15 @@ struct KArgs {
   unsigned long long *nfail;  // failed inversions since the pack was created
 };
 
+// Runge-Kutta coefficients of a stage (U = c0 U0 + c1 U + cdt dt L); dt <= 0:
+// the device-resident dt at dtd.  save: U0 <- U first (the stage's base).
+struct RkArgs {
+  double dt;
+  const double *dtd;
+  double c0, c1, cdt;
+  int save;
+};
+
 // p and Gamma_1 p of a cell or face state: the table when one is bound (only
 // packs with the scalar, NSC = 1, can bind one), else the ideal gas.
 template <int NSC>
@@ -292,14 +301,13 @@ __device__ __forceinline__ GeoT<T> geo_cast(const Geo &G)
 // 5 + D carries the passive-scalar flux when NSC = 1 (and is not written
 // otherwise).
 template <int MK, int D, int RS, typename T, int NSC>
-__device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo &b, int i, int j,
-                                                long long c, const T qL[7 + NSC],
-                                                const T qR[7 + NSC])
+__device__ __forceinline__ void face_flux(const KArgs &a, const BlockInfo &b, int i, int j,
+                                          long long c, const T qL[7 + NSC], const T qR[7 + NSC],
+                                          double Fo[8])
 {
   if (D == 1 && (j == b.pole_lo || j == b.pole_hi)) {   // sqrt(-g) = 0 on the axis
 #pragma unroll
-    for (int v = 0; v < 8; ++v)
-      if (v != 5 + D || NSC) a.F[(D * 8 + v) * a.nct + c] = 0.0;
+    for (int v = 0; v < 8; ++v) Fo[v] = 0.0;
     return;
   }
   const Geo G = geo_face<MK, D>(a, b, i, j);
@@ -320,10 +328,20 @@ __device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo 
   const double smg = G.alpha * G.sqrtg, sg = G.sqrtg;
 #pragma unroll
   for (int v = 0; v < 8; ++v)
-    if (v != 5 + D)
-      a.F[(D * 8 + v) * a.nct + c] = smg * (double)A[v] + sg * (double)B[v];
-  if constexpr (NSC != 0)
-    a.F[(D * 8 + 5 + D) * a.nct + c] = smg * (double)A[8] + sg * (double)B[8];
+    Fo[v] = (v != 5 + D) ? smg * (double)A[v] + sg * (double)B[v] : 0.0;
+  if constexpr (NSC != 0) Fo[5 + D] = smg * (double)A[8] + sg * (double)B[8];
+}
+
+template <int MK, int D, int RS, typename T, int NSC>
+__device__ __forceinline__ void face_flux_store(const KArgs &a, const BlockInfo &b, int i, int j,
+                                                long long c, const T qL[7 + NSC],
+                                                const T qR[7 + NSC])
+{
+  double Fo[8];
+  face_flux<MK, D, RS, T, NSC>(a, b, i, j, c, qL, qR, Fo);
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+    if (v != 5 + D || NSC) a.F[(D * 8 + v) * a.nct + c] = Fo[v];
 }
 
 template <typename T>
@@ -335,20 +353,70 @@ __device__ __forceinline__ void positivity(int v, T f2, T &l, T &r)
   }
 }
 
+// Kerr-Schild geometric source terms of one cell (sqrt(-g) S, Sec. 2.1) added
+// to the momentum and energy parts of rhs.
+template <int MK, int NSC>
+__device__ __forceinline__ void add_sources(const KArgs &a, const BlockInfo &b, int i, int j,
+                                            const Prim &q, double *rhs)
+{
+  if constexpr (MK == MK_KS) {
+    const double r = a.tab.rc[b.tab1 + i], s = a.tab.sc[b.tab2 + j], ct = a.tab.cc[b.tab2 + j];
+    const Geo G = geo_ks(r, s, ct, a.met);
+    const Aux A = aux_cell<NSC>(a, G, q);
+    const Sym4 T = tmunu(G, A);
+    double S1, S2, St;
+    ks_sources(r, s, ct, a.met, G, T, S1, S2, St);
+    rhs[1] += S1;
+    rhs[2] += S2;
+    rhs[4] += St;
+  }
+}
+
+// U <- c0 U0 + c1 U + h rhs for one cell (save: U0 <- U and U <- c0 U + h rhs)
+template <int NV>
+__device__ __forceinline__ void rk_cell(const KArgs &a, long long c, double c0, double c1,
+                                        double h, int save, const double *rhs)
+{
+  const long long n = a.nct;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const double u = a.U[v * n + c];
+    if (save) {
+      a.U0[v * n + c] = u;
+      a.U[v * n + c] = c0 * u + h * rhs[v];
+    } else {
+      a.U[v * n + c] = c0 * a.U0[v * n + c] + c1 * u + h * rhs[v];
+    }
+  }
+}
+
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
 // else x1), one row along the third axis.  Tile origin = lower face of the
 // tile in block-local (i, j, k).
 // Occupancy target: 4 waves per SIMD (128 VGPRs) for the hydro variables;
 // with the scalar and the table lookups 3 (up to 168 VGPRs, no spills).
-template <int MK, int D, int RECON, int FV, int RS, typename T, int SH, int NSC = 0>
+template <int MK, int D, int RECON, int FV, int RS, typename T, int SH, int NSC = 0, int FUSE = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4 - NSC)))
-void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
+void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles, RkArgs rk)
 {
+  static_assert(FUSE == 0 || NSC == 0, "the fused stage has no scalar");
   constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NS = TD + 5, NR = TD + 1;
   constexpr int NV = 7 + NSC;
-  __shared__ T stg[NV * TA * NS];
-  __shared__ T sfr[NV * TA * NR];     // right-face states of cells org[D]-1 .. org[D]+TD-1
+  constexpr int NSTG = NV * TA * NS, NSFR = NV * TA * NR;
+  // fused: the hydro face fluxes of the tile (FP64) take the staged window's
+  // place once it has been read; FP32 windows are too small, so they get
+  // space of their own
+  constexpr int NFLX = (FUSE && sizeof(T) != sizeof(double)) ? 10 * TA * TD : 0;
+  static_assert(!FUSE || sizeof(T) != sizeof(double) || NSTG >= 5 * TA * TD,
+                "the fused hydro fluxes reuse the staging space");
+  // staged stencil window, then the right-face states of cells org[D]-1 ..
+  // org[D]+TD-1
+  __shared__ __align__(16) T lds[NSTG + NSFR + NFLX];
+  T *const stg = lds;
+  T *const sfr = lds + NSTG;
+  double *const flx = (double *)(NFLX ? lds + NSTG + NSFR : lds);
   constexpr int AX = (D == 0) ? 1 : 0;
+  constexpr int BX = 3 - D - AX;
   const int tid = threadIdx.x;
   // this thread's face (and cell) within the tile
   int fd, aa;
@@ -414,7 +482,10 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
       const int v = it / TA, ca = it % TA;
       const T *f = &stg[(v * TA + ca) * NS];
       T l, r;
-      recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
+      // fused: the same reconstruction as the tile's own cells, so that a
+      // face shared by two tiles gets the same flux in both
+      if (!FUSE || !recon5_fast<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r))
+        recon5<RECON, FV, T>(f[0], f[1], f[2], f[3], f[4], l, r);
       positivity(v, f[2], l, r);
       sfr[(v * TA + ca) * NR] = r;
     }
@@ -423,13 +494,75 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles)
     int idx[3] = {org[0], org[1], org[2]};
     idx[D] = org[D] + fd;
     idx[AX] = org[AX] + aa;
-    const bool live = idx[D] < a.ng + b.n[D] && idx[AX] <= a.ng + b.n[AX] && idx[AX] < b.s[AX];
-    if (live) {
-      const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
-      T qL[NV];
+    const int ng = a.ng;
+    const bool tr = idx[AX] <= ng + b.n[AX] && idx[AX] < b.s[AX];
+    const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+    if constexpr (!FUSE) {
+      // every flux of the faces org[D] .. org[D]+TD-1 to HBM
+      if (tr && idx[D] < ng + b.n[D]) {
+        T qL[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];   // cell idx[D]-1
-      face_flux_store<MK, D, RS, T, NSC>(a, b, idx[0], idx[1], c, qL, qR);
+        for (int v = 0; v < NV; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];   // cell idx[D]-1
+        face_flux_store<MK, D, RS, T, NSC>(a, b, idx[0], idx[1], c, qL, qR);
+      }
+    } else {
+      // Fused: the tiles overlap by one face (stride TD - 1), so the faces
+      // org[D] .. org[D]+TD-1, up to the block's upper face, give the flux
+      // difference of the cells org[D] .. org[D]+TD-2 within the tile.  Only
+      // the induction fluxes (for the edge EMFs) go to HBM; the hydro flux
+      // divergence accumulates in the cell's dU (F[0][0..4]): x1 writes it,
+      // x2 adds to it, and x3 adds its own, the sources and does the
+      // Runge-Kutta combination, so no hydro flux is stored.
+      const bool live = tr && idx[D] <= ng + b.n[D];
+      const bool cell = live && fd < TD - 1 && idx[D] < ng + b.n[D] && idx[AX] >= ng &&
+                        idx[AX] < ng + b.n[AX] && idx[BX] >= ng && idx[BX] < ng + b.n[BX];
+      if (live) {
+        T qL[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qL[v] = sfr[(v * TA + aa) * NR + fd];
+        double Fo[8];
+        face_flux<MK, D, RS, T, NSC>(a, b, idx[0], idx[1], c, qL, qR, Fo);
+        // Each face is stored by one tile; the other tile that computes it
+        // (the shared face) writes into the unused normal-field slot.  A
+        // select rather than a branch: a conditional store here costs the
+        // Riemann solve its registers.
+        const bool own = fd > 0 || org[D] == ng;
+#pragma unroll
+        for (int v = 5; v < 8; ++v)
+          if (v != 5 + D) a.F[(D * 8 + (own ? v : 5 + D)) * a.nct + c] = Fo[v];
+        // the window is no longer read after the reconstruction barrier
+#pragma unroll
+        for (int v = 0; v < 5; ++v) flx[(v * TA + aa) * TD + fd] = Fo[v];
+      }
+      __syncthreads();
+      if (cell) {
+        const long long n = a.nct;
+        const double *f0 = &flx[aa * TD + fd];
+        const double id = 1.0 / b.dx[D];
+        if constexpr (D == 0) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) a.F[v * n + c] = -(f0[v * TA * TD + 1] - f0[v * TA * TD]) * id;
+        } else if constexpr (D == 1) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            a.F[v * n + c] = a.F[v * n + c] - (f0[v * TA * TD + 1] - f0[v * TA * TD]) * id;
+        } else {
+          double rhs[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v)
+            rhs[v] = a.F[v * n + c] - (f0[v * TA * TD + 1] - f0[v * TA * TD]) * id;
+          if constexpr (MK == MK_KS) {
+            Prim q;    // the cell's own state in FP64
+            q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+            q.ie = a.P[4 * n + c];
+            q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
+            q.ye = 0.0;
+            add_sources<MK, 0>(a, b, idx[0], idx[1], q, rhs);
+          }
+          const double dt = rk.dt > 0.0 ? rk.dt : *rk.dtd;
+          rk_cell<5>(a, c, rk.c0, rk.c1, rk.cdt * dt, rk.save, rhs);
+        }
+      }
     }
     __syncthreads();   // LDS is restaged by the next tile
   }
@@ -537,7 +670,9 @@ __global__ __launch_bounds__(256) void k_emf_fix(KArgs a, const FixE *__restrict
 
 // ------------------------------------------------------------------ update
 
-template <int MK, int EARR, int NSC = 0>
+// HYDRO = 0: the constrained-transport part only (the flux tiles have done
+// the hydro update).
+template <int MK, int EARR, int NSC = 0, int HYDRO = 1>
 __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict__ chunks,
                                                 double dt_in, const double *__restrict__ dt_dev,
                                                 double c0, double c1, double cdt, int save_base)
@@ -558,7 +693,7 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
   const double *F0 = a.F, *F1 = a.F + 8 * n, *F2 = a.F + 16 * n;
   const bool in1 = i < ng + b.n[0], in2 = j < ng + b.n[1], in3 = k < ng + b.n[2];
 
-  if (in1 && in2 && in3) {
+  if (HYDRO && in1 && in2 && in3) {
     double rhs[5 + NSC];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
@@ -568,31 +703,14 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
       rhs[5] = -(F0[5 * n + c + 1] - F0[5 * n + c]) * i1 -
                (F1[6 * n + c + sj] - F1[6 * n + c]) * i2 - (F2[7 * n + c + sk] - F2[7 * n + c]) * i3;
     if constexpr (MK == MK_KS) {
-      const double r = a.tab.rc[b.tab1 + i], s = a.tab.sc[b.tab2 + j], ct = a.tab.cc[b.tab2 + j];
-      const Geo G = geo_ks(r, s, ct, a.met);
       Prim q;
       q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
       q.ie = a.P[4 * n + c];
       q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
       q.ye = NSC ? a.P[5 * n + c] : 0.0;
-      const Aux A = aux_cell<NSC>(a, G, q);
-      const Sym4 T = tmunu(G, A);
-      double S1, S2, St;
-      ks_sources(r, s, ct, a.met, G, T, S1, S2, St);
-      rhs[1] += S1;
-      rhs[2] += S2;
-      rhs[4] += St;
+      add_sources<MK, NSC>(a, b, i, j, q, rhs);
     }
-#pragma unroll
-    for (int v = 0; v < 5 + NSC; ++v) {
-      const double u = a.U[v * n + c];
-      if (save_base) {
-        a.U0[v * n + c] = u;
-        a.U[v * n + c] = c0 * u + h * rhs[v];
-      } else {
-        a.U[v * n + c] = c0 * a.U0[v * n + c] + c1 * u + h * rhs[v];
-      }
-    }
+    rk_cell<5 + NSC>(a, c, c0, c1, h, save_base, rhs);
   }
 
   // edge EMFs: E1 = Omega_23 at (i, j-1/2, k-1/2), E2 = Omega_31 at
