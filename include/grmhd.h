@@ -263,7 +263,10 @@ int grmhd_step_graph(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_e
 #define GRMHD_NSHAPE 5
 int grmhd_set_tiling(grmhd_pack *pack, const int shape[3]);
 /* workgroups > 0: launch the flux-tile kernels as a persistent grid of that
- * many workgroups striding over the tile work-list; 0: one workgroup per tile. */
+ * many workgroups striding over the tile work-list; 0: one workgroup per tile.
+ * With FP64 face states and no scalar the persistent tiles stream each
+ * workgroup's next stencil window from global memory straight into LDS while
+ * the current tile's Riemann solves run (the same fluxes to rounding). */
 int grmhd_set_persistent(grmhd_pack *pack, int workgroups);
 int grmhd_get_tiling(const grmhd_pack *pack, int shape[3]);
 /*
@@ -292,7 +295,9 @@ int grmhd_debug_ptrs(grmhd_pack *pack, void **flags, void **iters, void **flux);
  * synchronises the stream and returns, per family, the summed milliseconds and
  * the number of launches since the last read (arrays of GRMHD_PROF_NFAM).
  * Families: flux tiles along x1 / x2 / x3, boundary face planes, update,
- * con2prim, ghost gather, cell-centred field, reductions.
+ * con2prim (the learned guess's inference included: it runs inside the
+ * inversion kernel, so the MLP family stays empty), ghost gather,
+ * cell-centred field, reductions.
  */
 enum { GRMHD_PROF_FLUX_X1 = 0, GRMHD_PROF_FLUX_X2 = 1, GRMHD_PROF_FLUX_X3 = 2,
        GRMHD_PROF_FLUX_PLANE = 3, GRMHD_PROF_UPDATE = 4, GRMHD_PROF_C2P = 5,

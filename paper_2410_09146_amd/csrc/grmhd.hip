@@ -48,6 +48,9 @@ struct Plan {
   // fused stage: tiles along D at stride TD - 1 over the faces ng .. ng + n
   // (the block's upper face included), for single-level packs
   std::vector<int4> tilesF[3][NSHAPE];
+  // persistent streaming tiles (k_flux_pf): as tiles, but for D = x2, x3 the
+  // columns start at an even x1 (ng - 2) so that cell pairs are 16-byte aligned
+  std::vector<int4> tilesP[3][NSHAPE];
   std::vector<int2> planes;       // (3 block + D, first face), 64 faces each
   std::vector<int2> ch_int, ch_ext, ch_bcc;
   std::vector<GhostP> gP;
@@ -68,9 +71,9 @@ struct Plan {
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes, o_chi, o_che,
-      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res, o_mlp,
+      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res,
       o_mlpw, o_mlpf, total;
-  size_t o_tl[3][NSHAPE], o_tlF[3][NSHAPE];
+  size_t o_tl[3][NSHAPE], o_tlF[3][NSHAPE], o_tlP[3][NSHAPE];
 };
 
 int fail(const std::string &m, int code)
@@ -269,6 +272,16 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
               o[D] = f0; o[AX] = a0; o[BX] = kb;
               p.tiles[D][sh].push_back(make_int4(b, o[0], o[1], o[2]));
             }
+        {
+          const int a_lo = AX == 0 ? ng - 2 : ng - 1;
+          for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
+            for (int a0 = a_lo; a0 <= ng + bi.n[AX]; a0 += ta)
+              for (int f0 = ng; f0 < ng + bi.n[D]; f0 += td) {
+                int o[3];
+                o[D] = f0; o[AX] = a0; o[BX] = kb;
+                p.tilesP[D][sh].push_back(make_int4(b, o[0], o[1], o[2]));
+              }
+        }
         if (p.maxlev == 0 && !d->nscalar)
           for (int kb = ng - 1; kb <= ng + bi.n[BX]; ++kb)
             for (int a0 = ng - 1; a0 <= ng + bi.n[AX]; a0 += ta)
@@ -298,6 +311,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     for (int sh = 0; sh < NSHAPE; ++sh) {
       xcd_order(p.tiles[D][sh]);
       xcd_order(p.tilesF[D][sh]);
+      xcd_order(p.tilesP[D][sh]);
     }
   for (int b = 0; b < p.nb; ++b) {
     const BlockInfo &bi = p.blocks[b];
@@ -655,6 +669,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
     for (int sh = 0; sh < NSHAPE; ++sh) {
       p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
       p.o_tlF[D][sh] = take(sizeof(int4) * p.tilesF[D][sh].size());
+      p.o_tlP[D][sh] = take(sizeof(int4) * p.tilesP[D][sh].size());
     }
   p.o_planes = take(sizeof(int2) * p.planes.size());
   p.o_chi = take(sizeof(int2) * p.ch_int.size());
@@ -673,7 +688,6 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_fixE = take(sizeof(FixE) * p.fixE.size());
   p.o_part = take(sizeof(double) * NPART * p.ch_int.size());
   p.o_res = take(sizeof(double) * RES_SLOTS);
-  p.o_mlp = take(sizeof(float) * 2 * (size_t)p.nct);   // learned mu0 and W per cell
   p.o_mlpw = take(sizeof(unsigned short) * MLPB_N);
   p.o_mlpf = take(sizeof(float) * MLPF_N);
   p.total = o;
@@ -865,6 +879,16 @@ void launch_tiles(grmhd_pack *p, const KArgs &a)
       hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, 0, 1>), dim3(grid), dim3(256), 0,
                          p->stream, a, dptr<int4>(p, pl.o_tlF[D][SH]), nt, p->rk);
       return;
+    }
+    if constexpr (std::is_same<T, double>::value) {
+      if (p->persist > 0) {
+        // persistent grid: each workgroup streams its next stencil window
+        // into LDS while it solves the current tile
+        const int np = (int)pl.tilesP[D][SH].size();
+        hipLaunchKernelGGL((k_flux_pf<MK, D, RC, FV, RS, SH>), dim3(std::min(np, p->persist)),
+                           dim3(256), 0, p->stream, a, dptr<int4>(p, pl.o_tlP[D][SH]), np);
+        return;
+      }
     }
   }
   hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, NSC, 0>), dim3(grid), dim3(256), 0,
@@ -1239,6 +1263,7 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
     {
       if (!e) e = up(pl.o_tl[D][sh], pl.tiles[D][sh].data(), sizeof(int4) * pl.tiles[D][sh].size());
       if (!e) e = up(pl.o_tlF[D][sh], pl.tilesF[D][sh].data(), sizeof(int4) * pl.tilesF[D][sh].size());
+      if (!e) e = up(pl.o_tlP[D][sh], pl.tilesP[D][sh].data(), sizeof(int4) * pl.tilesP[D][sh].size());
     }
   if (!e) e = up(pl.o_planes, pl.planes.data(), sizeof(int2) * pl.planes.size());
   if (!e) e = up(pl.o_chi, pl.ch_int.data(), sizeof(int2) * pl.ch_int.size());
@@ -1402,7 +1427,7 @@ namespace {
 
 template <int MK, int RED, int NSC>
 void launch_c2p_n(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch,
-                  const float *mlp, double *part)
+                  const MlpDev &mlp, double *part)
 {
   if (guess == 0) hipLaunchKernelGGL((k_c2p<MK, 0, RED, NSC>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
   else if (guess == 1) hipLaunchKernelGGL((k_c2p<MK, 1, RED, NSC>), g, dim3(256), 0, p->stream, a, ch, mlp, part);
@@ -1410,8 +1435,8 @@ void launch_c2p_n(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *
 }
 
 template <int MK, int RED>
-void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch, const float *mlp,
-                double *part)
+void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch,
+                const MlpDev &mlp, double *part)
 {
   if (p->desc.nscalar) launch_c2p_n<MK, RED, 1>(p, a, guess, g, ch, mlp, part);
   else launch_c2p_n<MK, RED, 0>(p, a, guess, g, ch, mlp, part);
@@ -1434,19 +1459,8 @@ int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, in
   const Plan &pl = p->plan;
   const dim3 g(pl.ch_int.size());
   const int2 *ch = dptr<int2>(p, pl.o_chi);
-  const float *mlp = dptr<float>(p, pl.o_mlp);
-  if (guess == GRMHD_GUESS_MLP) {
-    Prof tm(p, GRMHD_PROF_MLP);
-    MlpDev md{dptr<unsigned short>(p, pl.o_mlpw), dptr<float>(p, pl.o_mlpf)};
-    float *mu = (float *)(p->ws + pl.o_mlp);
-    if (m->kind == GRMHD_METRIC_KS_LOGSPH)
-      hipLaunchKernelGGL(k_mlp_guess<MK_KS>, dim3(4 * pl.ch_int.size()), dim3(64), 0, p->stream, a,
-                         md, ch, mu);
-    else
-      hipLaunchKernelGGL(k_mlp_guess<MK_MINK>, dim3(4 * pl.ch_int.size()), dim3(64), 0, p->stream,
-                         a, md, ch, mu);
-    LAUNCHCHK(p);
-  }
+  // the learned guess is evaluated inside the inversion kernel
+  const MlpDev mlp{dptr<unsigned short>(p, pl.o_mlpw), dptr<float>(p, pl.o_mlpf)};
   double *part = (double *)(p->ws + pl.o_part);
   {
   Prof t(p, GRMHD_PROF_C2P);

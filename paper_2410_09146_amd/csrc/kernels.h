@@ -301,6 +301,11 @@ __device__ __forceinline__ GeoT<T> geo_cast(const Geo &G)
 // 5 + D carries the passive-scalar flux when NSC = 1 (and is not written
 // otherwise).
 template <int MK, int D, int RS, typename T, int NSC>
+__device__ __forceinline__ void face_flux_geo(const KArgs &a, const Geo &G, double bface,
+                                              const T qL[7 + NSC], const T qR[7 + NSC],
+                                              double Fo[8]);
+
+template <int MK, int D, int RS, typename T, int NSC>
 __device__ __forceinline__ void face_flux(const KArgs &a, const BlockInfo &b, int i, int j,
                                           long long c, const T qL[7 + NSC], const T qR[7 + NSC],
                                           double Fo[8])
@@ -310,8 +315,18 @@ __device__ __forceinline__ void face_flux(const KArgs &a, const BlockInfo &b, in
     for (int v = 0; v < 8; ++v) Fo[v] = 0.0;
     return;
   }
-  const Geo G = geo_face<MK, D>(a, b, i, j);
-  const double bn = a.Bf[D * a.nct + c] / G.sqrtg;
+  face_flux_geo<MK, D, RS, T, NSC>(a, geo_face<MK, D>(a, b, i, j), a.Bf[D * a.nct + c], qL, qR,
+                                   Fo);
+}
+
+// The Riemann solve of a face given its metric and the face field
+// sqrt(gamma) B^D (bface).
+template <int MK, int D, int RS, typename T, int NSC>
+__device__ __forceinline__ void face_flux_geo(const KArgs &a, const Geo &G, double bface,
+                                              const T qL[7 + NSC], const T qR[7 + NSC],
+                                              double Fo[8])
+{
+  const double bn = bface / G.sqrtg;
   const PrimT<T> L = make_prim<D, NSC>(qL, T(bn)), R = make_prim<D, NSC>(qR, T(bn));
   T A[8 + NSC], B[8 + NSC];
   if constexpr (sizeof(T) == sizeof(double)) {
@@ -565,6 +580,186 @@ void k_flux(KArgs a, const int4 *__restrict__ tiles, int ntiles, RkArgs rk)
       }
     }
     __syncthreads();   // LDS is restaged by the next tile
+  }
+}
+
+// Persistent face tiles with the next tile's stencil window streamed into LDS
+// while the current tile's Riemann solves run (FP64, no scalar).  The window
+// goes from global memory straight to LDS (gfx950 global_load_lds_dwordx4: 16
+// bytes, two adjacent cells along x1, per lane; consecutive lanes fill
+// consecutive LDS), so no registers hold it and the loads stay in flight
+// across the solves.  Layouts keep x1 contiguous in LDS as in memory:
+//   D = x1: stg[v][column][cell], NW = TD + 6 cells from org - 4 (even, so
+//           every pair is 16-byte aligned; the first cell is not used);
+//   D = x2, x3: stg[v][cell][column], NS = TD + 5 cells from org - 3, the TA
+//           columns from an even x1 (the tile lists start at ng - 2).
+// The right-face states use the same orientation.  Each workgroup walks the
+// tile list with stride gridDim.x.  Results equal k_flux's to rounding (the
+// same reconstruction and Riemann code on the same values; the two kernels
+// are compiled apart, so fused multiply-adds may be formed differently).
+#ifndef GRMHD_PF_WAVES
+#define GRMHD_PF_WAVES 3
+#endif
+template <int MK, int D, int RECON, int FV, int RS, int SH>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRMHD_PF_WAVES)))
+void k_flux_pf(KArgs a, const int4 *__restrict__ tiles, int ntiles)
+{
+  constexpr int TD = Shape<SH>::TD, TA = Shape<SH>::TA, NR = TD + 1, NV = 7;
+  constexpr int NW = (D == 0) ? TD + 6 : TD + 5;      // window cells along D
+  static_assert(TA % 2 == 0 && TD % 2 == 0, "pairs of cells along x1");
+  __shared__ __align__(16) double stg[NV * TA * NW];
+  __shared__ __align__(16) double sfr[NV * TA * NR];
+  constexpr int AX = (D == 0) ? 1 : 0;
+  constexpr int NCH = NV * TA * NW / 2;                // 16-byte chunks of a window
+  constexpr int NIT = (NCH + 255) / 256;
+  const int4 *const ctl = tiles;
+  const BlockInfo *const cbl = a.blocks;
+  const int tid = threadIdx.x;
+  int fd, aa;
+  if constexpr (D == 0) { fd = tid % TD; aa = tid / TD; }
+  else                  { aa = tid % TA; fd = tid / TA; }
+
+  // the window of tile ti into stg (asynchronous; completion: vmcnt)
+  auto issue = [&](int ti) {
+    const int4 t = ctl[ti];
+    const BlockInfo b = cbl[t.x];
+    const long long s1 = b.s[0], s12 = (long long)b.s[0] * b.s[1];
+    // not unrolled: unrolled, the per-thread chunk offsets are hoisted out of
+    // the tile loop and held in registers the Riemann solve needs
+#pragma unroll 1
+    for (int m = 0; m < NIT; ++m) {
+      const int q0 = (tid & ~63) + 256 * m;
+      const int q = q0 + (tid & 63);
+      if (q < NCH) {
+        int v, x1, j2, j3;           // variable, x1 of the pair's first cell, other indices
+        if constexpr (D == 0) {
+          v = q / (TA * NW / 2);
+          const int r = q % (TA * NW / 2);
+          const int pa = r / (NW / 2), s2 = r % (NW / 2);
+          x1 = min(max(t.y - 4 + 2 * s2, 0), b.s[0] - 2);
+          j2 = min(t.z + pa, b.s[1] - 1);
+          j3 = t.w;
+        } else {
+          v = q / (NW * TA / 2);
+          const int r = q % (NW * TA / 2);
+          const int sd = r / (TA / 2), p2 = r % (TA / 2);
+          x1 = min(t.y + 2 * p2, b.s[0] - 2);
+          const int jd = min(max((D == 1 ? t.z : t.w) - 3 + sd, 0), b.s[D] - 1);
+          j2 = D == 1 ? jd : t.z;
+          j3 = D == 2 ? jd : t.w;
+        }
+        const double *src = v < 5 ? a.P + (long long)v * a.nct
+                                  : a.Bcc + (long long)tcomp<D>(v - 5) * a.nct;
+        src += b.off + x1 + s1 * j2 + s12 * j3;
+        __builtin_amdgcn_global_load_lds((const void *)src,
+                                         (__attribute__((address_space(3))) void *)(stg + 2 * q0),
+                                         16, 0, 0);
+      }
+    }
+  };
+
+  int ti = blockIdx.x;
+  if (ti < ntiles) issue(ti);
+  for (; ti < ntiles; ti += gridDim.x) {
+    __builtin_amdgcn_s_waitcnt(0);     // this wave's window loads (and stores) done
+    __syncthreads();                   // ... and every other wave's
+    const int4 t = ctl[ti];
+    const BlockInfo b = cbl[t.x];
+    const int org[3] = {t.y, t.z, t.w};
+    const long long str[3] = {1, b.s[0], (long long)b.s[0] * b.s[1]};
+
+    // reconstruct the own cell org[D]+fd (all variables; left state kept,
+    // right state published), then the right faces of the cells org[D]-1
+    auto win = [&](int v, int col, int k) -> double {   // stencil value k (0..4) of the own cell
+      if constexpr (D == 0) return stg[(v * TA + col) * NW + fd + 2 + k];
+      else return stg[(v * NW + fd + 1 + k) * TA + col];
+    };
+    auto rslot = [&](int v, int col, int f) -> double & {
+      if constexpr (D == 0) return sfr[(v * TA + col) * NR + f];
+      else return sfr[(v * NR + f) * TA + col];
+    };
+    double qR[NV];
+    bool redo = false;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double f0 = win(v, aa, 0), f1 = win(v, aa, 1), f2 = win(v, aa, 2),
+                   f3 = win(v, aa, 3), f4 = win(v, aa, 4);
+      double l, r;
+      redo |= !recon5_fast<RECON, FV, double>(f0, f1, f2, f3, f4, l, r);
+      positivity(v, f2, l, r);
+      rslot(v, aa, fd + 1) = r;
+      qR[v] = l;
+    }
+    if (redo) {           // rare: a WENO pair that could not be normalised
+#pragma unroll 1
+      for (int v = 0; v < NV; ++v) {
+        const double f0 = win(v, aa, 0), f1 = win(v, aa, 1), f2 = win(v, aa, 2),
+                     f3 = win(v, aa, 3), f4 = win(v, aa, 4);
+        double l, r;
+        recon5<RECON, FV, double>(f0, f1, f2, f3, f4, l, r);
+        positivity(v, f2, l, r);
+        rslot(v, aa, fd + 1) = r;
+#pragma unroll
+        for (int w = 0; w < NV; ++w)
+          if (w == v) qR[w] = l;
+      }
+    }
+    for (int it = tid; it < NV * TA; it += 256) {
+      const int v = it / TA, ca = it % TA;
+      double f[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        if constexpr (D == 0) f[k] = stg[(v * TA + ca) * NW + 1 + k];
+        else f[k] = stg[(v * NW + k) * TA + ca];
+      }
+      double l, r;
+      recon5<RECON, FV, double>(f[0], f[1], f[2], f[3], f[4], l, r);
+      positivity(v, f[2], l, r);
+      rslot(v, ca, 0) = r;
+    }
+
+    // this face: position and the values it reads from global memory, loaded
+    // before the next window is requested (vector loads complete in order,
+    // so a load issued behind the stream would wait for all of it)
+    int idx[3] = {org[0], org[1], org[2]};
+    idx[D] = org[D] + fd;
+    idx[AX] = org[AX] + aa;
+    const bool live = idx[D] < a.ng + b.n[D] && idx[AX] >= a.ng - 1 &&
+                      idx[AX] <= a.ng + b.n[AX] && idx[AX] < b.s[AX];
+    const bool pole = D == 1 && (idx[1] == b.pole_lo || idx[1] == b.pole_hi);
+    const long long c = b.off + idx[0] * str[0] + idx[1] * str[1] + idx[2] * str[2];
+    double gr = 0.0, gs = 0.0, gc = 0.0, bface = 0.0;
+    if (live && !pole) {
+      if constexpr (MK == MK_KS) {
+        gr = D == 0 ? a.tab.rf[b.tab1 + idx[0]] : a.tab.rc[b.tab1 + idx[0]];
+        gs = D == 1 ? a.tab.sf[b.tab2 + idx[1]] : a.tab.sc[b.tab2 + idx[1]];
+        gc = D == 1 ? a.tab.cf[b.tab2 + idx[1]] : a.tab.cc[b.tab2 + idx[1]];
+      }
+      bface = a.Bf[D * a.nct + c];
+    }
+    // wait for these loads here, while no window load is in flight behind them
+    asm volatile("" ::"v"(gr), "v"(gs), "v"(gc), "v"(bface));
+    __syncthreads();      // the window is read: stream the next one in
+    if (ti + (int)gridDim.x < ntiles) issue(ti + gridDim.x);
+
+    if (live) {
+      double qL[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) qL[v] = rslot(v, aa, fd);   // cell idx[D]-1
+      double Fo[8];
+      if (pole) {     // sqrt(-g) = 0 on the axis
+#pragma unroll
+        for (int v = 0; v < 8; ++v) Fo[v] = 0.0;
+      } else {
+        Geo G;
+        if constexpr (MK == MK_KS) G = geo_ks<double>(gr, gs, gc, a.met.M, a.met.a);
+        else G = geo_mink<double>();
+        face_flux_geo<MK, D, RS, double, 0>(a, G, bface, qL, qR, Fo);
+      }
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        if (v != 5 + D) a.F[(D * 8 + v) * a.nct + c] = Fo[v];
+    }
   }
 }
 
@@ -885,7 +1080,7 @@ __device__ __forceinline__ void cons_store(const KArgs &a, long long c, const Ge
 // (Sec. 3.2: rho, eps and Y_e stay inside the table).
 template <int MK, int GUESS, int RED, int NSC = 0>
 __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int e,
-                                         const float *__restrict__ mlp_mu, double val[NPART])
+                                         float g_mu, float g_W, double val[NPART])
 {
   constexpr int NU = 5 + NSC;
   const int ng = a.ng;
@@ -967,7 +1162,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
         if constexpr (GUESS == 2) {
           // learned guess, kept if its W(mu0) agrees with the network's own
           // W output to 50 % (out-of-distribution check); else the cold guess
-          const double g = (double)mlp_mu[c];
+          const double g = (double)g_mu;
           bool take = g > 0.0 && g <= 1.0;
           if (take) {
             const double x0 = 1.0 / (1.0 + g * m.b2);
@@ -975,7 +1170,7 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
             double v20 = g * g * rb0;
             v20 = v20 > m.v2max ? m.v2max : v20;
             const double W0 = 1.0 / sqrt(1.0 - v20);
-            take = fabs((double)mlp_mu[a.nct + c] - W0) <= 0.5 * W0;
+            take = fabs((double)g_W - W0) <= 0.5 * W0;
           }
           if (take) mu = g;
           else flag |= 16;
@@ -1058,18 +1253,46 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
 // Inversion of every interior cell; RED = 1 also folds the reduction
 // diagnostics of the final state into part[] (the reductions pass fused into
 // the last inversion of a step).
+template <int MK>
+__device__ __forceinline__ void mlp_cell_features(const KArgs &a, const MlpDev &m,
+                                                  const BlockInfo &b, int e, float x[5]);
+
+// Inversion of every interior cell; RED = 1 also folds the reduction
+// diagnostics of the final state into part[] (the reductions pass fused into
+// the last inversion of a step).  GUESS = 2: each wavefront first evaluates
+// the learned guess of its 64 cells (features -> LDS -> BF16 matrix-core
+// layers with the activations in registers), so the guess never leaves the
+// chip.
 template <int MK, int GUESS, int RED, int NSC = 0>
-__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks,
-                                             const float *__restrict__ mlp_mu,
+__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks, MlpDev md,
                                              double *__restrict__ part)
 {
   const int2 ch = chunks[blockIdx.x];
   const BlockInfo b = a.blocks[ch.x];
   const int e = ch.y + threadIdx.x;
+  const bool live = e < b.n[0] * b.n[1] * b.n[2];
   double val[NPART];
 #pragma unroll
   for (int q = 0; q < NPART; ++q) val[q] = 0.0;
-  if (e < b.n[0] * b.n[1] * b.n[2]) c2p_cell<MK, GUESS, RED, NSC>(a, b, e, mlp_mu, val);
+  float g_mu = -1.0f, g_W = 0.0f;
+  if constexpr (GUESS == 2) {
+    __shared__ __align__(16) unsigned short X[4][64 * 16];
+    __shared__ float out[4][64 * MLP_OUT];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float x[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (live) mlp_cell_features<MK>(a, md, b, e, x);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) X[w][lane * 16 + q] = q < 5 ? f2bf(x[q]) : 0;
+    __syncthreads();
+    mlp_wave(md, X[w], out[w], lane);
+    // mu = 1/(hW) <= 1 always: a guess above 1 (log hW output slightly
+    // negative near h W = 1) is clamped; a non-finite or non-positive one is
+    // marked -1.  The network's own W rides along for the consistency check.
+    const float mu = fminf(expf(-out[w][lane * 2 + 1]), 1.0f);
+    g_mu = (mu > 0.0f) ? mu : -1.0f;
+    g_W = expf(out[w][lane * 2]);
+  }
+  if (live) c2p_cell<MK, GUESS, RED, NSC>(a, b, e, g_mu, g_W, val);
   if constexpr (RED != 0) block_diag_store(val, part);
 }
 
@@ -1137,53 +1360,28 @@ __global__ __launch_bounds__(256) void k_reduce_fin(const double *__restrict__ p
 
 // ----------------------------------------------------------- learned guess
 
-// mu0 = exp(-y1) of the BF16 network for every interior cell (64-cell
-// wavefronts, 4 per 256-cell chunk); -1 marks a rejected guess.
+// The network's standardised features of interior cell e of block b (its
+// undensitized conserved state and cell-centred field on the cell's metric).
 template <int MK>
-__global__ __launch_bounds__(64) void k_mlp_guess(KArgs a, MlpDev m,
-                                                  const int2 *__restrict__ chunks,
-                                                  float *__restrict__ mu_out)
+__device__ __forceinline__ void mlp_cell_features(const KArgs &a, const MlpDev &m,
+                                                  const BlockInfo &b, int e, float x[5])
 {
-  __shared__ __align__(16) unsigned short X[64 * 16];
-  __shared__ float out[64 * MLP_OUT];
-  const int lane = threadIdx.x;
-  const int2 ch = chunks[blockIdx.x >> 2];
-  const BlockInfo b = a.blocks[ch.x];
-  const int e = ch.y + 64 * (blockIdx.x & 3) + lane;
-  const bool live = e < b.n[0] * b.n[1] * b.n[2];
-  float x[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  long long c = 0;
-  if (live) {
-    const int ng = a.ng;
-    const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
-    const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
-    c = b.off + i + sj * j + sk * k;
-    const long long n = a.nct;
-    const Geo G = geo_center<MK>(a, b, i, j);
-    const double isg = 1.0 / G.sqrtg;
-    const double D = a.U[c] * isg, S1 = a.U[n + c] * isg, S2 = a.U[2 * n + c] * isg;
-    const double S3 = a.U[3 * n + c] * isg, tau = a.U[4 * n + c] * isg;
-    const double B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
-    const double B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
-    const double B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
-    const double SS = G.gi11 * S1 * S1 + 2.0 * G.gi13 * S1 * S3 + G.gi22 * S2 * S2 + G.gi33 * S3 * S3;
-    const double BB = G.g11 * B1 * B1 + 2.0 * G.g13 * B1 * B3 + G.g22 * B2 * B2 + G.g33 * B3 * B3;
-    const double SB = S1 * B1 + S2 * B2 + S3 * B3;
-    if (D > 0.0) mlp_features(D, SS, tau, BB, SB, m.f + MLPF_MEAN, m.f + MLPF_ISTD, x);
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) X[lane * 16 + q] = q < 5 ? f2bf(x[q]) : 0;
-  __syncthreads();
-  mlp_wave(m, X, out, lane);
-  if (live) {
-    // mu = 1/(hW) <= 1 always: a guess above 1 (log hW output slightly
-    // negative near h W = 1) is clamped; a non-finite or non-positive one is
-    // marked -1.  The network's own W rides along for the consistency check
-    // of the inversion kernel.
-    const float mu = fminf(expf(-out[lane * 2 + 1]), 1.0f);
-    mu_out[c] = (mu > 0.0f) ? mu : -1.0f;
-    mu_out[a.nct + c] = expf(out[lane * 2]);
-  }
+  const int ng = a.ng;
+  const int i = ng + e % b.n[0], j = ng + (e / b.n[0]) % b.n[1], k = ng + e / (b.n[0] * b.n[1]);
+  const long long sj = b.s[0], sk = (long long)b.s[0] * b.s[1];
+  const long long c = b.off + i + sj * j + sk * k;
+  const long long n = a.nct;
+  const Geo G = geo_center<MK>(a, b, i, j);
+  const double isg = 1.0 / G.sqrtg;
+  const double D = a.U[c] * isg, S1 = a.U[n + c] * isg, S2 = a.U[2 * n + c] * isg;
+  const double S3 = a.U[3 * n + c] * isg, tau = a.U[4 * n + c] * isg;
+  const double B1 = 0.5 * (a.Bf[c] + a.Bf[c + 1]) * isg;
+  const double B2 = 0.5 * (a.Bf[n + c] + a.Bf[n + c + sj]) * isg;
+  const double B3 = 0.5 * (a.Bf[2 * n + c] + a.Bf[2 * n + c + sk]) * isg;
+  const double SS = G.gi11 * S1 * S1 + 2.0 * G.gi13 * S1 * S3 + G.gi22 * S2 * S2 + G.gi33 * S3 * S3;
+  const double BB = G.g11 * B1 * B1 + 2.0 * G.g13 * B1 * B3 + G.g22 * B2 * B2 + G.g33 * B3 * B3;
+  const double SB = S1 * B1 + S2 * B2 + S3 * B3;
+  if (D > 0.0) mlp_features(D, SS, tau, BB, SB, m.f + MLPF_MEAN, m.f + MLPF_ISTD, x);
 }
 
 }  // namespace grmhd

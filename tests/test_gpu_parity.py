@@ -422,3 +422,41 @@ def test_periodic_box_conserves_and_keeps_divb_on_gpu(grmhd, recon, riemann, nbl
     say("periodic 64^3", recon, riemann, nblk, "totals drift per total", worst_t, "divb_rel",
         worst_d, "c2p fail (cumulative)", nfail[-1])
     assert np.all(worst_t <= 1e-13) and worst_d <= 1e-13 and nfail[-1] == 0
+
+
+@pytest.mark.parametrize("case", ["torus", "wave_weno_llf", "box_mp5", "bondi"])
+def test_persistent_streaming_tiles_equal_plain_tiles(grmhd, case):
+    """The persistent flux grid (each workgroup streams its next stencil
+    window into LDS during the current tile's solves) gives the face fluxes of
+    one workgroup per tile, for every tile shape the reconstruction has, to
+    rounding (the two kernels are compiled apart, so their fused multiply-adds
+    may differ; the energy flux of a near-static background is a cancellation
+    and shows it at ~2e-13 of its own norm: the gate is the parity bar, 1e-11
+    of each component's max norm), and the oracle's stage."""
+    import torch
+    prob = _cases()[case]()
+    blk, P, Bf, U = oracle_state(prob)
+    dt = blk.reductions(P, Bf, U, prob.cfl)["dt"]
+    Uo, Bo = blk.stage(P, Bf, U, Bf, U, dt, (1.0, 0.0, 1.0), nthreads=8)
+    shapes = range(grmhd.NSHAPE) if prob.recon == I.RECON_WENO5Z and not prob.weno_fv else [0]
+    for sh in shapes:
+        out = []
+        for persist in (0, 97):          # 97 workgroups: several tiles each, a ragged last round
+            pack = grmhd.Pack(prob)
+            pack.set_tiling([sh] * 3)
+            pack.set_persistent(persist)
+            upload_all(pack, P, Bf, U)
+            pack.fill_ghosts()
+            pack.stage(dt, (1.0, 0.0, 1.0))
+            out.append((pack.flux_array(), pack.download("U"), pack.download("Bf")))
+            del pack
+        F0, F1 = out[0][0], out[1][0]
+        dscale = np.abs(F0).max(axis=(1, 2, 3, 4), keepdims=True)
+        scale = np.maximum(np.abs(F0).max(axis=(2, 3, 4), keepdims=True), 1e-12 * dscale)
+        dF = (np.abs(F1 - F0) / np.maximum(scale, 1e-300)).max()
+        eU = rel_err(out[1][1], Uo, prob)
+        eB = rel_err(out[1][2], Bo, prob, face=True)
+        say("persistent streaming tiles", case, "shape", sh, "bitwise", np.array_equal(F0, F1),
+            "max flux diff / own norm", dF, "eU", eU.max(), "eB", eB.max())
+        assert dF <= TOL
+        assert np.all(eU <= TOL) and np.all(eB <= TOL)
