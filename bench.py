@@ -49,6 +49,10 @@ def parse():
                     help="reconstruction of the torus128 workload (default: the headline's)")
     ap.add_argument("--riemann", default="llf", choices=["llf", "hll"],
                     help="Riemann solver of the torus128 workload (default: the headline's)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar="CSV",
+                    help="write profiles/k_flux_torus128_traffic.json from the rocprofv3 "
+                         "counter files of four runs: FETCH_SIZE and WRITE_SIZE of the "
+                         "benchmark, then of --copy-calibration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -294,8 +298,80 @@ def regrid_workload(args, torch, G, I):
     print(json.dumps(out), flush=True)
 
 
+def traffic_summary(paths):
+    """HBM bytes per k_flux launch from rocprofv3 --pmc counter files (KiB per
+    dispatch): per direction the production tile shape (the one launched
+    most; the autotuner launches every shape a few times), each counter scaled
+    by the true bytes of a plain 1 GiB device copy over what the same counter
+    reads for it."""
+    import collections
+    import csv
+    import re
+
+    def per_kernel(path, counter):
+        acc = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return acc
+
+    fetch, write = per_kernel(paths[0], "FETCH_SIZE"), per_kernel(paths[1], "WRITE_SIZE")
+    cf = max(sum(v) / len(v) for v in per_kernel(paths[2], "FETCH_SIZE").values())
+    cw = max(sum(v) / len(v) for v in per_kernel(paths[3], "WRITE_SIZE").values())
+    copy_bytes = 1 << 30
+    ff, wf = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    # the production FP64 WENO5-Z-AOAH + LLF Kerr-Schild tile kernel, unfused
+    pat = re.compile(r"void grmhd::k_flux<1, (\d), 2, 0, 1, double, (\d), 0, 0>")
+    per_dir = {}
+    for counters, key in ((fetch, "fetch"), (write, "write")):
+        for name, vals in counters.items():
+            m = pat.match(name)
+            if not m:
+                continue
+            d, sh = int(m.group(1)), int(m.group(2))
+            cur = per_dir.setdefault(d, {}).get(key)
+            if cur is None or len(vals) > cur[2]:
+                per_dir[d][key] = (sum(vals) / len(vals), sh, len(vals))
+    out_dirs = {}
+    for d in sorted(per_dir):
+        f, w = per_dir[d]["fetch"], per_dir[d]["write"]
+        out_dirs[f"x{d + 1}"] = {"fetch_KiB_raw": round(f[0], 1), "fetch_shape": f[1],
+                                 "write_KiB_raw": round(w[0], 1), "write_shape": w[1],
+                                 "hbm_bytes": int(f[0] * 1024 * ff + w[0] * 1024 * wf)}
+    faces = flux_faces(128)
+    cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc {c} -d "
+           "<repo>/gpurun_out/{d} -o run --output-format csv -- python3 <repo>/bench.py {a}")
+    summary = {
+        "kernel": "k_flux (FP64, WENO5-Z-AOAH + LLF, Kerr-Schild), 128^3 torus",
+        "kernel_source_hash": kernel_source_hash(),
+        "hbm_bytes_per_launch": int(sum(v["hbm_bytes"] for v in out_dirs.values()) / len(out_dirs)),
+        "algorithmic_bytes_per_launch": faces * 120,
+        "calibration": {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": round(cf, 1),
+                        "WRITE_SIZE_KiB": round(cw, 1), "fetch_factor": round(ff, 5),
+                        "write_factor": round(wf, 5)},
+        "per_direction": out_dirs,
+        "commands": [cmd.format(c="FETCH_SIZE", d="pmc_flux_fetch", a="--steps 2 --warmup 1 --no-cpu-baseline"),
+                     cmd.format(c="WRITE_SIZE", d="pmc_flux_write", a="--steps 2 --warmup 1 --no-cpu-baseline"),
+                     cmd.format(c="FETCH_SIZE", d="pmc_copy_fetch", a="--copy-calibration"),
+                     cmd.format(c="WRITE_SIZE", d="pmc_copy_write", a="--copy-calibration"),
+                     "python3 bench.py --traffic-summary <the four run_counter_collection.csv files>"],
+        "note": "FETCH_SIZE and WRITE_SIZE are KiB per dispatch, averaged over the dispatches of "
+                "the production tile shape of each direction and scaled by the ratio of a plain "
+                "1 GiB device copy's true bytes to what the same counter reads for it; "
+                "hbm_bytes_per_launch is the mean over the three directions; algorithmic bytes: "
+                "64 B read (P 40, the two transverse cell-centred B 16, the face B 8) and 56 B "
+                "written (7 fluxes) per face"}
+    path = os.path.join(ROOT, "profiles", "k_flux_torus128_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(summary, fh, indent=1)
+    print(json.dumps(summary), flush=True)
+
+
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -386,6 +462,15 @@ def main():
     hbm = {"algorithmic_bytes_per_zone_cycle": 480,
            "achieved_GBs": round(480 * value / 1e9, 1),
            "frac_of_8TBs": round(480 * value / 1e9 / HBM_PEAK_GBS, 4)}
+    # the whole step against both roofs: the target is 60 % of the HBM roof,
+    # and the step's FP64 work (flux tiles and update by their operation
+    # counts; the inversion, whose cost depends on its iterations, not counted)
+    step_flops = 2 * (3 * per_face * flux_faces(n) + opc["per_cell_update_ks"] * ncell)
+    step_tf = step_flops * args.steps / (ms_graph * 1e-3) / 1e12
+    roof["step"] = {"hbm_frac": hbm["frac_of_8TBs"], "hbm_target_frac": 0.6,
+                    "hbm_gap_x": round(0.6 / hbm["frac_of_8TBs"], 2),
+                    "fp64_flops_per_step": step_flops, "fp64_TFLOPs": round(step_tf, 3),
+                    "fp64_frac": round(step_tf / FP64_PEAK_TFLOPS, 4)}
 
     kernels = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                for k, v in prof.items()}

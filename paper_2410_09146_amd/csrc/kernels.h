@@ -1263,8 +1263,11 @@ __device__ __forceinline__ void mlp_cell_features(const KArgs &a, const MlpDev &
 // the learned guess of its 64 cells (features -> LDS -> BF16 matrix-core
 // layers with the activations in registers), so the guess never leaves the
 // chip.
+// Occupancy: 4 waves per SIMD (128 VGPRs, a few spilled) for the plain
+// inversion; the one with the fused reductions keeps the compiler's choice.
 template <int MK, int GUESS, int RED, int NSC = 0>
-__global__ __launch_bounds__(256) void k_c2p(KArgs a, const int2 *__restrict__ chunks, MlpDev md,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RED ? 1 : 4)))
+void k_c2p(KArgs a, const int2 *__restrict__ chunks, MlpDev md,
                                              double *__restrict__ part)
 {
   const int2 ch = chunks[blockIdx.x];
