@@ -30,6 +30,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="torus: every flux launch on the pack's stream (no concurrent directions)")
     ap.add_argument("--fused", action="store_true",
                     help="torus: the optional fused stage (hydro update inside the flux tiles)")
     ap.add_argument("--persist", type=int, default=0,
@@ -401,6 +403,8 @@ def main():
     pack = G.Pack(prob, device="cuda:0")
     if args.fused:
         pack.set_fused(True)
+    if args.serial:
+        pack.set_concurrency(False)
     pack.init()
     pack.reductions(sync=False)        # device-resident dt for the first step
     tiles, tune_ms = pack.autotune(reps=3) if not args.no_autotune else ([0, 0, 0], None)

@@ -282,6 +282,16 @@ int grmhd_get_tiling(const grmhd_pack *pack, int shape[3]);
  * scalar, which always run unfused.
  */
 int grmhd_set_fused(grmhd_pack *pack, int enable);
+/*
+ * Concurrency (on by default): the x2 and x3 flux tiles and the boundary
+ * planes of a stage run on three auxiliary streams of the pack (default
+ * priority, forked from and joined back into the pack's stream, so a captured
+ * step graph holds them as parallel branches) beside the x1 tiles; they write
+ * disjoint face fluxes.  With kernel timing (grmhd_profile), while autotuning,
+ * in the fused stage, or with enable = 0 every launch stays on the pack's
+ * stream.
+ */
+int grmhd_set_concurrency(grmhd_pack *pack, int enable);
 int grmhd_autotune(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos, int reps,
                    int chosen[3], double *ms_table);
 

@@ -716,6 +716,20 @@ struct grmhd_pack {
   // keeps CT only
   bool fused = false;
   RkArgs rk{};                  // the stage being launched (fused tiles)
+  // concurrent flux launches: auxiliary streams (default priority) and the
+  // fork / join events; ls = the stream a tile launch goes to (null: stream)
+  bool concurrent = true;
+  hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+  hipStream_t ls = nullptr;
+  ~grmhd_pack()
+  {
+    for (int k = 0; k < 3; ++k) {
+      if (aux[k]) { (void)hipStreamSynchronize(aux[k]); (void)hipStreamDestroy(aux[k]); }
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+  }
   // captured SSPRK2 step (dt read on the device)
   hipGraphExec_t gexec = nullptr;
   int g_guess = -1;
@@ -872,12 +886,13 @@ void launch_tiles(grmhd_pack *p, const KArgs &a)
   const auto &L = fz ? pl.tilesF[D][SH] : pl.tiles[D][SH];
   if (L.empty()) return;
   Prof t(p, GRMHD_PROF_FLUX_X1 + D);
+  const hipStream_t st = p->ls ? p->ls : p->stream;
   const int nt = (int)L.size();
   const int grid = p->persist > 0 ? std::min(nt, p->persist) : nt;
   if constexpr (NSC == 0) {
     if (fz) {
       hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, 0, 1>), dim3(grid), dim3(256), 0,
-                         p->stream, a, dptr<int4>(p, pl.o_tlF[D][SH]), nt, p->rk);
+                         st, a, dptr<int4>(p, pl.o_tlF[D][SH]), nt, p->rk);
       return;
     }
     if constexpr (std::is_same<T, double>::value) {
@@ -886,13 +901,13 @@ void launch_tiles(grmhd_pack *p, const KArgs &a)
         // into LDS while it solves the current tile
         const int np = (int)pl.tilesP[D][SH].size();
         hipLaunchKernelGGL((k_flux_pf<MK, D, RC, FV, RS, SH>), dim3(std::min(np, p->persist)),
-                           dim3(256), 0, p->stream, a, dptr<int4>(p, pl.o_tlP[D][SH]), np);
+                           dim3(256), 0, st, a, dptr<int4>(p, pl.o_tlP[D][SH]), np);
         return;
       }
     }
   }
   hipLaunchKernelGGL((k_flux<MK, D, RC, FV, RS, T, SH, NSC, 0>), dim3(grid), dim3(256), 0,
-                     p->stream, a, dptr<int4>(p, pl.o_tl[D][SH]), nt, p->rk);
+                     st, a, dptr<int4>(p, pl.o_tl[D][SH]), nt, p->rk);
 }
 
 // Every shape is instantiated for the WENO5-Z-AOAH point-value path (the
@@ -925,15 +940,37 @@ void launch_flux(grmhd_pack *p, const KArgs &a)
 template <int MK, int RC, int FV, int RS, typename T, int NSC>
 void launch_flux3(grmhd_pack *p, const KArgs &a)
 {
-  if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T, NSC>(p, a);
-  if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T, NSC>(p, a);
-  if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T, NSC>(p, a);
+  // The three directions' tiles and the boundary planes write disjoint face
+  // fluxes: with concurrency on, x2, x3 and the planes run on streams of their
+  // own (forked from and joined back into the pack's stream, so a captured
+  // step graph holds them as parallel branches) and fill one another's tails.
+  // Per-family timing and autotuning keep everything on the pack's stream;
+  // the fused stage's directions depend on one another.
   const Plan &pl = p->plan;
-  if (p->tune_sh >= 0 || pl.planes.empty()) return;   // autotuning times the tiles alone
-  if (p->fused) return;           // the fused tiles include the upper faces
-  Prof t(p, GRMHD_PROF_FLUX_PLANE);
-  hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T, NSC>), dim3(pl.planes.size()), dim3(64), 0,
-                     p->stream, a, dptr<int2>(p, pl.o_planes));
+  const bool planes = p->tune_sh < 0 && !pl.planes.empty() && !p->fused;
+  const bool conc = p->concurrent && p->aux[0] && !p->prof && p->tune_sh < 0 &&
+                    p->tune_dir < 0 && !p->fused;
+  if (conc) {
+    (void)hipEventRecord(p->ev_fork, p->stream);
+    for (int k = 0; k < 3; ++k) (void)hipStreamWaitEvent(p->aux[k], p->ev_fork, 0);
+  }
+  if (p->tune_dir < 0 || p->tune_dir == 0) launch_flux<MK, 0, RC, FV, RS, T, NSC>(p, a);
+  p->ls = conc ? p->aux[0] : nullptr;
+  if (p->tune_dir < 0 || p->tune_dir == 1) launch_flux<MK, 1, RC, FV, RS, T, NSC>(p, a);
+  p->ls = conc ? p->aux[1] : nullptr;
+  if (p->tune_dir < 0 || p->tune_dir == 2) launch_flux<MK, 2, RC, FV, RS, T, NSC>(p, a);
+  p->ls = nullptr;
+  if (planes) {
+    Prof t(p, GRMHD_PROF_FLUX_PLANE);
+    hipLaunchKernelGGL((k_flux_planes<MK, RC, FV, RS, T, NSC>), dim3(pl.planes.size()), dim3(64), 0,
+                       conc ? p->aux[2] : p->stream, a, dptr<int2>(p, pl.o_planes));
+  }
+  if (conc) {
+    for (int k = 0; k < 3; ++k) {
+      (void)hipEventRecord(p->ev_join[k], p->aux[k]);
+      (void)hipStreamWaitEvent(p->stream, p->ev_join[k], 0);
+    }
+  }
 }
 
 template <int MK, int RC, int FV, typename T, int NSC>
@@ -1284,6 +1321,9 @@ int grmhd_pack_create(const grmhd_pack_desc *desc, const grmhd_state_ptrs *state
   if (!e) e = hipMemsetAsync(p->ws + pl.o_res, 0, sizeof(double) * RES_SLOTS, p->stream);
   // host vectors must outlive the async copies
   if (!e) e = hipStreamSynchronize(p->stream);
+  for (int k = 0; k < 3 && !e; ++k) e = hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking);
+  if (!e) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+  for (int k = 0; k < 3 && !e; ++k) e = hipEventCreateWithFlags(&p->ev_join[k], hipEventDisableTiming);
   if (e) {
     std::string m = std::string("upload: ") + hipGetErrorString(e);
     delete p;
@@ -2069,6 +2109,14 @@ int grmhd_set_fused(grmhd_pack *p, int enable)
     return perr(p, "the fused stage needs a single-level pack without the scalar",
                 GRMHD_E_UNSUPPORTED);
   p->fused = enable != 0;
+  if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+  return GRMHD_OK;
+}
+
+int grmhd_set_concurrency(grmhd_pack *p, int enable)
+{
+  if (!p) return GRMHD_E_INVALID;
+  p->concurrent = enable != 0;
   if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
   return GRMHD_OK;
 }

@@ -67,6 +67,7 @@ EXPORTS = ["grmhd_abi_version", "grmhd_layout", "grmhd_pack_workspace_bytes",
            "grmhd_mlp_train_step_noalloc",
            "grmhd_mlp_infer", "grmhd_step", "grmhd_step_graph", "grmhd_set_tiling",
            "grmhd_get_tiling", "grmhd_autotune", "grmhd_set_persistent", "grmhd_set_fused",
+           "grmhd_set_concurrency",
            "grmhd_m1_source",
            "grmhd_tag", "grmhd_regrid_layout", "grmhd_remap_scratch_bytes", "grmhd_remap",
            "grmhd_last_error"]
@@ -115,6 +116,7 @@ def lib():
         L.grmhd_set_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.grmhd_set_persistent.argtypes = [vp, ctypes.c_int]
         L.grmhd_set_fused.argtypes = [vp, ctypes.c_int]
+        L.grmhd_set_concurrency.argtypes = [vp, ctypes.c_int]
         L.grmhd_get_tiling.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.grmhd_step_graph.argtypes = [vp, ctypes.POINTER(Metric), ctypes.POINTER(Eos),
                                        ctypes.c_int, ctypes.c_double, ctypes.c_int]
@@ -569,6 +571,11 @@ class Pack:
     def set_fused(self, enable):
         """Fused stage on or off (the default; grmhd_set_fused)."""
         _check(lib().grmhd_set_fused(self.h, int(enable)), self.h)
+
+    def set_concurrency(self, enable):
+        """Flux directions on streams of their own (default) or all on the
+        pack's stream (grmhd_set_concurrency)."""
+        _check(lib().grmhd_set_concurrency(self.h, int(enable)), self.h)
 
     def set_tiling(self, shape):
         _check(lib().grmhd_set_tiling(self.h, (ctypes.c_int * 3)(*shape)), self.h)
