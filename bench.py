@@ -55,6 +55,10 @@ def parse():
                     help="write profiles/k_flux_torus128_traffic.json from the rocprofv3 "
                          "counter files of four runs: FETCH_SIZE and WRITE_SIZE of the "
                          "benchmark, then of --copy-calibration")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="print a markdown table of a rocprofv3 kernel trace (run_kernel_trace.csv): "
+                         "per kernel the dispatches, the mean duration over all of them and over "
+                         "those that ran alone (overlapping no other dispatch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (calibrates rocprofv3's "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count)")
@@ -369,8 +373,49 @@ def traffic_summary(paths):
     print(json.dumps(summary), flush=True)
 
 
+def trace_summary(path):
+    """Per kernel of a rocprofv3 kernel trace: dispatches, mean duration, and
+    the mean over the dispatches that overlapped no other one (with the flux
+    directions on streams of their own, the graph-replayed steps run them side
+    by side, which stretches each; the eager pass that bench.py times kernel by
+    kernel runs every launch alone)."""
+    import collections
+    import csv
+    rows = [(r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+            for r in csv.DictReader(open(path))]
+    rows.sort(key=lambda r: r[1])
+    alone = [True] * len(rows)
+    end_max, arg = -1, -1
+    for k, (_, t0, t1) in enumerate(rows):
+        if t0 < end_max:
+            alone[k] = False
+            alone[arg] = False
+        if t1 > end_max:
+            end_max, arg = t1, k
+    acc = collections.defaultdict(lambda: [0, 0.0, 0, 0.0, 1e30, 0.0])
+    for k, (name, t0, t1) in enumerate(rows):
+        a = acc[name]
+        d = (t1 - t0) * 1e-3
+        a[0] += 1; a[1] += d; a[4] = min(a[4], d); a[5] = max(a[5], d)
+        if alone[k]:
+            a[2] += 1; a[3] += d
+    total = sum(a[1] for a in acc.values())
+    print("| kernel | dispatches | mean us | alone: dispatches | alone: mean us | min us | max us | share of summed time |")
+    print("|---|---|---|---|---|---|---|---|")
+    for name, a in sorted(acc.items(), key=lambda kv: -kv[1][1]):
+        if a[1] < 0.002 * total:
+            continue
+        nm = name.split("(")[0]
+        am = f"{a[3] / a[2]:.1f}" if a[2] else "-"
+        print(f"| `{nm}` | {a[0]} | {a[1] / a[0]:.1f} | {a[2]} | {am} | {a[4]:.1f} | {a[5]:.1f} | "
+              f"{100 * a[1] / total:.1f} % |")
+
+
 def main():
     args = parse()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.traffic_summary:
         traffic_summary(args.traffic_summary)
         return
