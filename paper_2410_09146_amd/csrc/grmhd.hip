@@ -293,17 +293,20 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
       }
     }
   }
-  // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs, so
-  // entry w of the list is taken from position (w % 8) * ceil(n/8) + w / 8 of
-  // the natural (spatially ordered) list; each XCD then sweeps one contiguous
-  // eighth of the tiles and reuses the stencil halos in its own L2.
+  // XCD-aware order of the flux tile lists: workgroups are dealt round-robin
+  // over the 8 XCDs (workgroup w to XCD w % 8), so the natural, spatially
+  // ordered list is cut into 8 contiguous runs (the first n % 8 one entry
+  // longer) and workgroup w takes entry w / 8 of run w % 8.  Each XCD then
+  // sweeps one contiguous eighth of the tiles and reuses the stencil halos in
+  // its own L2.  (The cell-chunk lists keep the natural order: the same
+  // permutation of them measured slower for the update and the cell-centred
+  // field.)
   auto xcd_order = [](auto &L) {
-    const size_t n = L.size(), q = (n + 7) / 8;
-    std::remove_reference_t<decltype(L)> out;
-    out.reserve(n);
-    for (size_t w = 0; w < 8 * q; ++w) {
-      const size_t src = (w % 8) * q + w / 8;
-      if (src < n) out.push_back(L[src]);
+    const size_t n = L.size(), base = n / 8, rem = n % 8;
+    std::remove_reference_t<decltype(L)> out(n);
+    for (size_t w = 0; w < n; ++w) {
+      const size_t x = w % 8;
+      out[w] = L[x * base + std::min(x, rem) + w / 8];
     }
     L.swap(out);
   };
