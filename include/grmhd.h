@@ -235,7 +235,14 @@ int grmhd_reductions(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_e
 /*
  * One SSPRK2 step: stage {1,0,1}, con2prim(guess), ghosts, stage {1/2,1/2,1/2},
  * con2prim(guess), ghosts, then (cfl > 0) reductions leaving the next dt on the
- * device.  dt <= 0 uses the device-resident dt.  Asynchronous.
+ * device.  dt <= 0 uses the device-resident dt.  Asynchronous.  The base of
+ * the step is not copied: the first stage writes its state into U0 and Bf0
+ * (which then hold that state after the call), the first inversion and ghost
+ * fill and the second stage work on them, and the second stage combines U / Bf
+ * with them into U / Bf.  P, U and Bf come out bitwise equal to the sequence
+ * of the calls above (which copy the base), with one write of U and Bf per
+ * cell less.  A pack with the fused stage (grmhd_set_fused) keeps the copying
+ * form.
  */
 int grmhd_step(grmhd_pack *pack, const grmhd_metric *metric, const grmhd_eos *eos, double dt,
                int guess, double cfl);

@@ -15,6 +15,7 @@
 #include <string>
 #include <tuple>
 #include <type_traits>
+#include <utility>
 #include <unordered_map>
 #include <vector>
 
@@ -725,6 +726,11 @@ struct grmhd_pack {
   hipStream_t aux[3] = {nullptr, nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
   hipStream_t ls = nullptr;
+  // grmhd_step without a copy of its base: the first stage writes its result
+  // over U0 / Bf0 (to_base), the first inversion and ghost fill and the second
+  // stage then see U0 / Bf0 as the current state (swap), and the second stage
+  // writes the combination over U / Bf
+  bool to_base = false, swap = false;
   ~grmhd_pack()
   {
     for (int k = 0; k < 3; ++k) {
@@ -747,6 +753,7 @@ struct grmhd_pack {
     KArgs a;
     a.P = (double *)st.P; a.Bf = (double *)st.Bf; a.U = (double *)st.U;
     a.U0 = (double *)st.U0; a.Bf0 = (double *)st.Bf0;
+    if (swap) { std::swap(a.U, a.U0); std::swap(a.Bf, a.Bf0); }
     a.F = (double *)(ws + plan.o_F);
     a.Bcc = (double *)(ws + plan.o_Bcc);
     a.flags = (int8_t *)(ws + plan.o_flags);
@@ -1421,6 +1428,9 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
   const double *dtd = dptr<double>(p, pl.o_res);
   const int save = rk[1] == 0.0;
   p->rk = RkArgs{dt, dtd, rk[0], rk[1], rk[2], save};
+  // update mode (rk_value): save or combine, result in the current arrays or
+  // over the base arrays
+  const int mode = p->to_base ? (save ? 2 : 3) : save;
   if (m->kind == GRMHD_METRIC_KS_LOGSPH) launch_flux_all<MK_KS>(p, a, rc, fv, rs, prec);
   else launch_flux_all<MK_MINK>(p, a, rc, fv, rs, prec);
   LAUNCHCHK(p);
@@ -1439,26 +1449,26 @@ int grmhd_stage(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doub
       hipLaunchKernelGGL(k_emf_fix, dim3((pl.fixE.size() + 255) / 256), dim3(256), 0, p->stream,
                          a, dptr<FixE>(p, pl.o_fixE), (int)pl.fixE.size());
     if (ks) hipLaunchKernelGGL((k_update<MK_KS, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
     else hipLaunchKernelGGL((k_update<MK_MINK, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
   } else if (p->desc.nscalar) {
     if (ks) hipLaunchKernelGGL((k_update<MK_KS, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
     else hipLaunchKernelGGL((k_update<MK_MINK, 0, 1>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
   } else if (p->fused) {
     // the flux tiles did the hydro update: constrained transport only
     if (ks) hipLaunchKernelGGL((k_update<MK_KS, 0, 0, 0>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                               p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
     else hipLaunchKernelGGL((k_update<MK_MINK, 0, 0, 0>), dim3(pl.ch_ext.size()), dim3(256), 0,
-                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                            p->stream, a, dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
   } else if (ks) {
     hipLaunchKernelGGL((k_update<MK_KS, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
   } else {
     hipLaunchKernelGGL((k_update<MK_MINK, 0>), dim3(pl.ch_ext.size()), dim3(256), 0, p->stream, a,
-                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], save);
+                       dptr<int2>(p, pl.o_che), dt, dtd, rk[0], rk[1], rk[2], mode);
   }
   LAUNCHCHK(p);
   return GRMHD_OK;
@@ -2043,11 +2053,23 @@ int grmhd_step(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, doubl
                double cfl)
 {
   static const double rk1[3] = {1.0, 0.0, 1.0}, rk2[3] = {0.5, 0.5, 0.5};
+  if (!p) return GRMHD_E_INVALID;
+  // the first stage's state lives in U0 / Bf0 (no copy of the base; the fused
+  // stage keeps the copying form), and the flags are cleared on every exit
+  struct Reset {
+    grmhd_pack *p;
+    ~Reset() { p->to_base = false; p->swap = false; }
+  } reset{p};
+  const bool pp = !p->fused;
   int rc;
+  p->to_base = pp;
   if ((rc = grmhd_stage(p, m, eos, dt, rk1))) return rc;
+  p->swap = pp;
   if ((rc = grmhd_con2prim(p, m, eos, guess))) return rc;
   if ((rc = grmhd_fill_ghosts(p, m))) return rc;
   if ((rc = grmhd_stage(p, m, eos, dt, rk2))) return rc;
+  p->swap = false;
+  p->to_base = false;
   // the last inversion also produces the reductions (dt of the next step)
   if ((rc = con2prim_impl(p, m, eos, guess, cfl, cfl > 0.0))) return rc;
   if ((rc = grmhd_fill_ghosts(p, m))) return rc;

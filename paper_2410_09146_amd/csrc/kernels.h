@@ -387,22 +387,36 @@ __device__ __forceinline__ void add_sources(const KArgs &a, const BlockInfo &b, 
   }
 }
 
-// U <- c0 U0 + c1 U + h rhs for one cell (save: U0 <- U and U <- c0 U + h rhs)
+// The Runge-Kutta combination of one value, by mode:
+//   0: cur <- c0 base + c1 cur + h r          1: base <- cur, cur <- c0 cur + h r
+//   2: base <- c0 cur + h r (cur kept)        3: base <- c0 base + c1 cur + h r
+// Modes 0/1 are a stage that leaves its result in the current array; 2/3 the
+// same two stages with the result written over the base array instead, so a
+// two-stage step needs no copy of its base (the arithmetic is the same).
+__device__ __forceinline__ void rk_value(double *cur, double *base, long long i, double c0,
+                                         double c1, double h, int mode, double r)
+{
+  const double u = cur[i];
+  if (mode == 1) {
+    base[i] = u;
+    cur[i] = c0 * u + h * r;
+  } else if (mode == 0) {
+    cur[i] = c0 * base[i] + c1 * u + h * r;
+  } else if (mode == 2) {
+    base[i] = c0 * u + h * r;
+  } else {
+    base[i] = c0 * base[i] + c1 * u + h * r;
+  }
+}
+
+// U (and base U0) of one cell by rk_value's mode
 template <int NV>
 __device__ __forceinline__ void rk_cell(const KArgs &a, long long c, double c0, double c1,
-                                        double h, int save, const double *rhs)
+                                        double h, int mode, const double *rhs)
 {
   const long long n = a.nct;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double u = a.U[v * n + c];
-    if (save) {
-      a.U0[v * n + c] = u;
-      a.U[v * n + c] = c0 * u + h * rhs[v];
-    } else {
-      a.U[v * n + c] = c0 * a.U0[v * n + c] + c1 * u + h * rhs[v];
-    }
-  }
+  for (int v = 0; v < NV; ++v) rk_value(a.U, a.U0, v * n + c, c0, c1, h, mode, rhs[v]);
 }
 
 // Main face tiles: TD faces along D x TA columns along A (x2 for D = x1,
@@ -870,7 +884,7 @@ __global__ __launch_bounds__(256) void k_emf_fix(KArgs a, const FixE *__restrict
 template <int MK, int EARR, int NSC = 0, int HYDRO = 1>
 __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict__ chunks,
                                                 double dt_in, const double *__restrict__ dt_dev,
-                                                double c0, double c1, double cdt, int save_base)
+                                                double c0, double c1, double cdt, int mode)
 {
   const int2 ch = chunks[blockIdx.x];
   const BlockInfo b = a.blocks[ch.x];
@@ -905,7 +919,7 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
       q.ye = NSC ? a.P[5 * n + c] : 0.0;
       add_sources<MK, NSC>(a, b, i, j, q, rhs);
     }
-    rk_cell<5 + NSC>(a, c, c0, c1, h, save_base, rhs);
+    rk_cell<5 + NSC>(a, c, c0, c1, h, mode, rhs);
   }
 
   // edge EMFs: E1 = Omega_23 at (i, j-1/2, k-1/2), E2 = Omega_31 at
@@ -930,16 +944,8 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
   rb[1] = upd[1] ? -(E3(c + 1) - E3(c)) * i1 + (E1(c + sk) - E1(c)) * i3 : 0.0;
   rb[2] = upd[2] ? (E2(c + 1) - E2(c)) * i1 - (E1(c + sj) - E1(c)) * i2 : 0.0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    if (!upd[d]) continue;
-    const double bf = a.Bf[d * n + c];
-    if (save_base) {
-      a.Bf0[d * n + c] = bf;
-      a.Bf[d * n + c] = c0 * bf + h * rb[d];
-    } else {
-      a.Bf[d * n + c] = c0 * a.Bf0[d * n + c] + c1 * bf + h * rb[d];
-    }
-  }
+  for (int d = 0; d < 3; ++d)
+    if (upd[d]) rk_value(a.Bf, a.Bf0, d * n + c, c0, c1, h, mode, rb[d]);
 }
 
 // ------------------------------------------------------------- reductions

@@ -595,8 +595,9 @@ class Pack:
                                       nsteps), self.h)
 
     def step(self, dt=None, guess=GUESS_PREV):
-        """One SSPRK2 step (Shu-Osher): ghosts, stage {1,0,1}, con2prim, ghosts,
-        stage {1/2,1/2,1/2}, con2prim, ghosts.  dt = None: device-resident dt
+        """One SSPRK2 step (Shu-Osher) through the public calls: stage {1,0,1},
+        con2prim, ghosts, stage {1/2,1/2,1/2}, con2prim, ghosts (the first
+        stage saves the base into U0 / Bf0).  dt = None: device-resident dt
         from reductions(sync=False) (no host round trip)."""
         h = dt if dt is not None else -1.0
         self.stage(h, (1.0, 0.0, 1.0))
