@@ -72,7 +72,7 @@ struct Plan {
   double dxmin = 0.0;
   // workspace carve-up (byte offsets)
   size_t o_F, o_Bcc, o_flags, o_iters, o_blocks, o_tab, o_planes, o_chi, o_che,
-      o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res,
+      o_flr, o_chb, o_gP, o_gB, o_gR, o_gPro, o_gBR, o_gBPro, o_SP, o_SB, o_E, o_fixF, o_fixE, o_part, o_res,
       o_mlpw, o_mlpf, total;
   size_t o_tl[3][NSHAPE], o_tlF[3][NSHAPE], o_tlP[3][NSHAPE];
 };
@@ -669,6 +669,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_iters = take((size_t)p.nct);
   p.o_blocks = take(sizeof(BlockInfo) * p.nb);
   p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
+  p.o_flr = take(sizeof(double) * 2 * p.rc.size());
   for (int D = 0; D < 3; ++D)
     for (int sh = 0; sh < NSHAPE; ++sh) {
       p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
@@ -764,6 +765,8 @@ struct grmhd_pack {
     a.tab.rc = t; a.tab.rf = t + n1;
     a.tab.sc = t + 2 * n1; a.tab.cc = t + 2 * n1 + n2;
     a.tab.sf = t + 2 * n1 + 2 * n2; a.tab.cf = t + 2 * n1 + 3 * n2;
+    a.flr_rho = (double *)(ws + plan.o_flr);
+    a.flr_u = a.flr_rho + n1;
     a.met.M = 1.0; a.met.a = 0.0;
     std::memset(&a.eos, 0, sizeof a.eos);
     a.nct = plan.nct;
@@ -1518,6 +1521,10 @@ int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, in
   {
   Prof t(p, GRMHD_PROF_C2P);
   const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
+  // the radial floor table for this call's floors (a few hundred entries)
+  const int nr = (int)pl.rc.size();
+  if (ks && nr > 0)
+    hipLaunchKernelGGL(k_floor_tab, dim3((nr + 255) / 256), dim3(256), 0, p->stream, a, nr);
   if (reduce) {
     if (ks) launch_c2p<MK_KS, 1>(p, a, guess, g, ch, mlp, part);
     else launch_c2p<MK_MINK, 1>(p, a, guess, g, ch, mlp, part);

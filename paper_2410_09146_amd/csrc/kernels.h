@@ -34,6 +34,10 @@ struct KArgs {
   EosTab et;            // tabulated EOS (et.d == nullptr: ideal gas)
   int npv;              // primitive planes: 5, or 6 with the Y_e scalar in P[5]
   unsigned long long *nfail;  // failed inversions since the pack was created
+  // Kerr-Schild: the density and energy floors of every radial table entry
+  // (rho_flr0 r^-rho_flr_pow, u_flr0 r^-u_flr_pow), written by k_floor_tab
+  // before each inversion
+  double *flr_rho, *flr_u;
 };
 
 // Runge-Kutta coefficients of a stage (U = c0 U0 + c1 U + cdt dt L); dt <= 0:
@@ -1227,10 +1231,11 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
     flag = (flag & 16) | 8;
   }
   // floors (Sec. 3.2), never below the table
-  double r = 1.0;
-  if constexpr (MK == MK_KS) r = a.tab.rc[b.tab1 + i];
-  double rflr = a.eos.rho_flr0 * pow(r, -a.eos.rho_flr_pow);
-  double uflr = a.eos.u_flr0 * pow(r, -a.eos.u_flr_pow);
+  double rflr = a.eos.rho_flr0, uflr = a.eos.u_flr0;      // r = 1: no radial factor
+  if constexpr (MK == MK_KS) {
+    rflr = a.flr_rho[b.tab1 + i];
+    uflr = a.flr_u[b.tab1 + i];
+  }
   if (tab) rflr = fmax(rflr, a.et.rho_min);
   if (q.rho < rflr) { q.rho = rflr; flag |= 1; }
   if (tab) {
@@ -1254,6 +1259,17 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
   a.iters[c] = (uint8_t)min(iters, 255);
   if (flag & 8) atomicAdd(a.nfail, 1ull);
   if constexpr (RED != 0) cell_diag<MK, NSC>(a, b, G, q, bf, Ur, flag, min(iters, 255), val);
+}
+
+// The floors of every radial table entry (Sec. 3.2): rho_flr0 r^-rho_flr_pow
+// and u_flr0 r^-u_flr_pow, once per entry instead of twice per cell.
+__global__ __launch_bounds__(256) void k_floor_tab(KArgs a, int nr)
+{
+  const int ir = blockIdx.x * 256 + threadIdx.x;
+  if (ir >= nr) return;
+  const double r = a.tab.rc[ir];
+  a.flr_rho[ir] = a.eos.rho_flr0 * pow(r, -a.eos.rho_flr_pow);
+  a.flr_u[ir] = a.eos.u_flr0 * pow(r, -a.eos.u_flr_pow);
 }
 
 // Inversion of every interior cell; RED = 1 also folds the reduction
