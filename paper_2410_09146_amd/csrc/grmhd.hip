@@ -732,6 +732,11 @@ struct grmhd_pack {
   // stage then see U0 / Bf0 as the current state (swap), and the second stage
   // writes the combination over U / Bf
   bool to_base = false, swap = false;
+  // the floors the radial floor table holds (Kerr-Schild packs), and whether
+  // a step graph is being captured (the table is then brought up to date
+  // before the capture and before each replay, never inside the graph)
+  double flr_key[4] = {0.0, 0.0, 0.0, 0.0};
+  bool flr_ok = false, capturing = false;
   ~grmhd_pack()
   {
     for (int k = 0; k < 3; ++k) {
@@ -1498,6 +1503,19 @@ void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch
   else launch_c2p_n<MK, RED, 0>(p, a, guess, g, ch, mlp, part);
 }
 
+// The radial floor table for the floors of eos (a few hundred entries),
+// rewritten only when they differ from the ones it holds.
+void floor_table(grmhd_pack *p, const KArgs &a, const grmhd_eos *eos)
+{
+  const double key[4] = {eos->rho_flr0, eos->rho_flr_pow, eos->u_flr0, eos->u_flr_pow};
+  if (p->flr_ok && !std::memcmp(key, p->flr_key, sizeof key)) return;
+  const int nr = (int)p->plan.rc.size();
+  if (nr > 0)
+    hipLaunchKernelGGL(k_floor_tab, dim3((nr + 255) / 256), dim3(256), 0, p->stream, a, nr);
+  std::memcpy(p->flr_key, key, sizeof key);
+  p->flr_ok = true;
+}
+
 // part != nullptr: the inversion also writes the reduction partials, and the
 // final fold runs right after it (the reductions of grmhd_reductions).
 int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, int guess,
@@ -1521,10 +1539,7 @@ int con2prim_impl(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos, in
   {
   Prof t(p, GRMHD_PROF_C2P);
   const bool ks = m->kind == GRMHD_METRIC_KS_LOGSPH;
-  // the radial floor table for this call's floors (a few hundred entries)
-  const int nr = (int)pl.rc.size();
-  if (ks && nr > 0)
-    hipLaunchKernelGGL(k_floor_tab, dim3((nr + 255) / 256), dim3(256), 0, p->stream, a, nr);
+  if (ks && !p->capturing) floor_table(p, a, eos);
   if (reduce) {
     if (ks) launch_c2p<MK_KS, 1>(p, a, guess, g, ch, mlp, part);
     else launch_c2p<MK_MINK, 1>(p, a, guess, g, ch, mlp, part);
@@ -2096,12 +2111,21 @@ int grmhd_step_graph(grmhd_pack *p, const grmhd_metric *m, const grmhd_eos *eos,
                     !std::memcmp(&p->g_metric, m, sizeof *m) &&
                     !std::memcmp(&p->g_eos, eos, sizeof *eos) &&
                     !std::memcmp(&p->g_tab, &tab, sizeof tab);
+  // the radial floor table stays outside the graph: brought up to date here,
+  // before any capture and before the replays
+  if (m->kind == GRMHD_METRIC_KS_LOGSPH) {
+    KArgs a = p->args();
+    fill_eos(a, eos);
+    floor_table(p, a, eos);
+  }
   if (!same) {
     if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
     const bool prof = p->prof;
     p->prof = false;                          // no event records inside the graph
     HIPCHK(p, hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal));
+    p->capturing = true;
     const int rc = grmhd_step(p, m, eos, -1.0, guess, cfl);
+    p->capturing = false;
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(p->stream, &g);
     p->prof = prof;

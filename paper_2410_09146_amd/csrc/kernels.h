@@ -36,7 +36,7 @@ struct KArgs {
   unsigned long long *nfail;  // failed inversions since the pack was created
   // Kerr-Schild: the density and energy floors of every radial table entry
   // (rho_flr0 r^-rho_flr_pow, u_flr0 r^-u_flr_pow), written by k_floor_tab
-  // before each inversion
+  // whenever an inversion asks for other floors than the table holds
   double *flr_rho, *flr_u;
 };
 
@@ -1262,7 +1262,8 @@ __device__ __forceinline__ void c2p_cell(const KArgs &a, const BlockInfo &b, int
 }
 
 // The floors of every radial table entry (Sec. 3.2): rho_flr0 r^-rho_flr_pow
-// and u_flr0 r^-u_flr_pow, once per entry instead of twice per cell.
+// and u_flr0 r^-u_flr_pow, once per entry (and per change of the floors)
+// instead of twice per cell and inversion.
 __global__ __launch_bounds__(256) void k_floor_tab(KArgs a, int nr)
 {
   const int ir = blockIdx.x * 256 + threadIdx.x;

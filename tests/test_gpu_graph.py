@@ -179,3 +179,50 @@ def test_step_without_base_copy_equals_stage_sequence(case):
         assert all(same)
         ra, rb = a.reductions(), b.reductions()
         assert ra["dt"] == rb["dt"] and ra["c2p_fail"] == rb["c2p_fail"]
+
+
+def test_floor_table_follows_the_floors():
+    """The inversion reads its density and energy floors from a per-radius
+    table that is rewritten only when the floors change, and never inside a
+    captured step. Pack a replays the step graph (floors A), inverts with
+    floors B (ten times higher), and replays the same graph again; pack b does
+    the same with eager steps; pack d inverts with A in the middle. a and b
+    agree bitwise at every point (so the replay after the B inversion used A
+    again), and the B inversion differs from d's A inversion (so it used B)."""
+    import torch
+    from paper_2410_09146_amd import grmhd as G
+    prob = I.torus(n=(32, 32, 16))
+    packs = [G.Pack(prob) for _ in range(3)]
+    for p in packs:
+        p.init()
+        p.reductions(sync=False)
+    a, b, d = packs
+    a0, u0 = a.eos.rho_flr0, a.eos.u_flr0
+
+    def state(p):
+        p._out()
+        torch.cuda.synchronize()
+        return [getattr(p, w).clone() for w in ("P", "U", "Bf")]
+
+    a.step_graph(1, cfl=prob.cfl)
+    for p in (b, d):
+        p.step_c(None, cfl=prob.cfl)
+    assert all(torch.equal(x, y) for x, y in zip(state(a), state(b)))
+    for p in (a, b):
+        p.eos.rho_flr0, p.eos.u_flr0 = 10.0 * a0, 10.0 * u0
+        p.con2prim()
+    d.con2prim()
+    sa, sb, sd = state(a), state(b), state(d)
+    say("floors x10: P bitwise a == b", torch.equal(sa[0], sb[0]), "a == d (floors A)",
+        torch.equal(sa[0], sd[0]))
+    assert all(torch.equal(x, y) for x, y in zip(sa, sb))
+    assert not torch.equal(sa[0], sd[0])
+    for p in (a, b):
+        p.eos.rho_flr0, p.eos.u_flr0 = a0, u0
+        p.reductions(sync=False)
+    a.step_graph(1, cfl=prob.cfl)
+    b.step_c(None, cfl=prob.cfl)
+    sa, sb = state(a), state(b)
+    say("graph replay after the B inversion: P, U, Bf bitwise",
+        [torch.equal(x, y) for x, y in zip(sa, sb)])
+    assert all(torch.equal(x, y) for x, y in zip(sa, sb))
