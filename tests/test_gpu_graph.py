@@ -139,6 +139,14 @@ def _pack_for(case):
     if case == "mixed":
         prob = I.torus(n=(32, 32, 16))
         return lambda: G.Pack(prob, precision=G.PREC_MIXED), prob
+    if case == "fused":
+        prob = I.torus(n=(32, 32, 16))
+
+        def make_fused():
+            p = G.Pack(prob)
+            p.set_fused(True)
+            return p
+        return make_fused, prob
     fine = I.random_smooth_box((32, 32, 32), seed=6, amp=0.1)
     root = I.coarse_problem(fine)
     ref = {(0, 0, 0), (1, 1, 0), (1, 0, 1)}
@@ -153,14 +161,15 @@ def _pack_for(case):
     return make, root
 
 
-@pytest.mark.parametrize("case", ["torus", "box_blocks", "scalar", "mixed", "two_level"])
+@pytest.mark.parametrize("case", ["torus", "box_blocks", "scalar", "mixed", "two_level", "fused"])
 def test_step_without_base_copy_equals_stage_sequence(case):
     """grmhd_step keeps the first stage's state in U0 / Bf0 instead of copying
     the step's base there (the first stage writes over the base arrays, the
     second combines into U / Bf). Its P, U and face field, ghost zones
     included, equal bitwise those of the public call sequence (stage {1,0,1},
     con2prim, ghosts, stage {1/2,1/2,1/2}, con2prim, ghosts), which copies
-    the base, at the same dt, over three steps."""
+    the base, at the same dt, over three steps.  A pack with the fused stage
+    keeps the copying form in both."""
     import torch
     make, prob = _pack_for(case)
     a, b = make(), make()
