@@ -999,20 +999,44 @@ __device__ __forceinline__ void cell_diag(const KArgs &a, const BlockInfo &b, co
   val[13] = NSC ? U[NSC ? 5 : 0] * dV : 0.0;
 }
 
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // Fold the 256 threads' diagnostics (wavefront shuffles, then a fixed order
 // over the 4 wavefronts) into part[blockIdx.x]; every thread must call it.
+// The 0/1 counters (failures, floors, guess fallbacks) are counted by ballot
+// and the Newton iterations summed as integers: the same exact values as
+// summing them as doubles, with fewer cross-lane shuffles.
+template <int NSC>
 __device__ __forceinline__ void block_diag_store(double val[NPART], double *__restrict__ part)
 {
   __shared__ double sh[4][NPART];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const double itmax = wave_max(val[10]);
+  const double nfail = (double)__popcll(__ballot(val[8] != 0.0));
+  const double nfloor = (double)__popcll(__ballot(val[9] != 0.0));
+  const double nfall = (double)__popcll(__ballot(val[12] != 0.0));
+  const int it = (int)val[10];
+  const int itsum = wave_sum_i(it), itmax = wave_max_i(it);
 #pragma unroll
   for (int q = 0; q < 3; ++q) val[q] = wave_max(val[q]);
 #pragma unroll
-  for (int q = 3; q < 11; ++q) val[q] = wave_sum(val[q]);
-  val[11] = itmax;
-  val[12] = wave_sum(val[12]);
-  val[13] = wave_sum(val[13]);
+  for (int q = 3; q < 8; ++q) val[q] = wave_sum(val[q]);
+  val[8] = nfail;
+  val[9] = nfloor;
+  val[10] = (double)itsum;
+  val[11] = (double)itmax;
+  val[12] = nfall;
+  val[13] = NSC ? wave_sum(val[13]) : 0.0;
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < NPART; ++q) sh[wv][q] = val[q];
@@ -1061,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a, const int2 *__restrict_
     for (int v = 0; v < 5 + NSC; ++v) U[v] = a.U[v * n + c];
     cell_diag<MK, NSC>(a, b, G, q, bf, U, a.flags[c], a.iters[c], val);
   }
-  block_diag_store(val, part);
+  block_diag_store<NSC>(val, part);
 }
 
 // --------------------------------------------------------------- inversion
@@ -1319,7 +1343,7 @@ void k_c2p(KArgs a, const int2 *__restrict__ chunks, MlpDev md,
     g_W = expf(out[w][lane * 2]);
   }
   if (live) c2p_cell<MK, GUESS, RED, NSC>(a, b, e, g_mu, g_W, val);
-  if constexpr (RED != 0) block_diag_store(val, part);
+  if constexpr (RED != 0) block_diag_store<NSC>(val, part);
 }
 
 template <int MK, int NSC = 0>
