@@ -1311,9 +1311,11 @@ __device__ __forceinline__ void mlp_cell_features(const KArgs &a, const MlpDev &
 // layers with the activations in registers), so the guess never leaves the
 // chip.
 // Occupancy: 4 waves per SIMD (128 VGPRs, a few spilled) for the plain
-// inversion; the one with the fused reductions keeps the compiler's choice.
+// inversion; with the scalar 2 (up to 256 VGPRs, none spilled: at 3 or 4 waves
+// the general-EOS inversion spilled 24 or 66 and ran 1.1-1.6x slower); the one
+// with the fused reductions keeps the compiler's choice.
 template <int MK, int GUESS, int RED, int NSC = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RED ? 1 : 4)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RED ? 1 : (NSC ? 2 : 4))))
 void k_c2p(KArgs a, const int2 *__restrict__ chunks, MlpDev md,
                                              double *__restrict__ part)
 {
