@@ -346,7 +346,7 @@ def traffic_summary(paths):
                                  "hbm_bytes": int(f[0] * 1024 * ff + w[0] * 1024 * wf)}
     faces = flux_faces(128)
     cmd = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 150 rocprofv3 --pmc {c} -d "
-           "<repo>/gpurun_out/{d} -o run --output-format csv -- python3 <repo>/bench.py {a}")
+           "<out>/{d} -o run --output-format csv -- python3 <repo>/bench.py {a}")
     summary = {
         "kernel": "k_flux (FP64, WENO5-Z-AOAH + LLF, Kerr-Schild), 128^3 torus",
         "kernel_source_hash": kernel_source_hash(),
@@ -360,7 +360,8 @@ def traffic_summary(paths):
                      cmd.format(c="WRITE_SIZE", d="pmc_flux_write", a="--steps 2 --warmup 1 --no-cpu-baseline"),
                      cmd.format(c="FETCH_SIZE", d="pmc_copy_fetch", a="--copy-calibration"),
                      cmd.format(c="WRITE_SIZE", d="pmc_copy_write", a="--copy-calibration"),
-                     "python3 bench.py --traffic-summary <the four run_counter_collection.csv files>"],
+                     "python3 bench.py --traffic-summary <the four run_counter_collection.csv files>",
+                     "(<repo>: the repository root; <out>: any output directory)"],
         "note": "FETCH_SIZE and WRITE_SIZE are KiB per dispatch, averaged over the dispatches of "
                 "the production tile shape of each direction and scaled by the ratio of a plain "
                 "1 GiB device copy's true bytes to what the same counter reads for it; "
