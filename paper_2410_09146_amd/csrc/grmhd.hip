@@ -669,7 +669,7 @@ int build_plan(const grmhd_pack_desc *d, Plan &p)
   p.o_iters = take((size_t)p.nct);
   p.o_blocks = take(sizeof(BlockInfo) * p.nb);
   p.o_tab = take(sizeof(double) * (2 * p.rc.size() + 4 * p.sc.size()));
-  p.o_flr = take(sizeof(double) * 2 * p.rc.size());
+  p.o_flr = take(sizeof(double) * 4 * p.rc.size());   // two tables (see floor_table)
   for (int D = 0; D < 3; ++D)
     for (int sh = 0; sh < NSHAPE; ++sh) {
       p.o_tl[D][sh] = take(sizeof(int4) * p.tiles[D][sh].size());
@@ -1504,12 +1504,26 @@ void launch_c2p(grmhd_pack *p, const KArgs &a, int guess, dim3 g, const int2 *ch
 }
 
 // The radial floor table for the floors of eos (a few hundred entries),
-// rewritten only when they differ from the ones it holds.
-void floor_table(grmhd_pack *p, const KArgs &a, const grmhd_eos *eos)
+// rewritten only when they differ from the ones it holds.  Inside a capture
+// that the caller started (not grmhd_step_graph's own, which brings the table
+// up to date outside its graph) the inversion uses a second table whose
+// rewrite is always recorded, so each replay writes the floors it was
+// captured with and the first table, which the host keeps track of, is never
+// touched by a replay.
+void floor_table(grmhd_pack *p, KArgs &a, const grmhd_eos *eos)
 {
+  const int nr = (int)p->plan.rc.size();
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(p->stream, &cs) != hipSuccess) cs = hipStreamCaptureStatusNone;
+  if (cs == hipStreamCaptureStatusActive) {
+    a.flr_rho += 2 * nr;
+    a.flr_u += 2 * nr;
+    if (nr > 0)
+      hipLaunchKernelGGL(k_floor_tab, dim3((nr + 255) / 256), dim3(256), 0, p->stream, a, nr);
+    return;
+  }
   const double key[4] = {eos->rho_flr0, eos->rho_flr_pow, eos->u_flr0, eos->u_flr_pow};
   if (p->flr_ok && !std::memcmp(key, p->flr_key, sizeof key)) return;
-  const int nr = (int)p->plan.rc.size();
   if (nr > 0)
     hipLaunchKernelGGL(k_floor_tab, dim3((nr + 255) / 256), dim3(256), 0, p->stream, a, nr);
   std::memcpy(p->flr_key, key, sizeof key);

@@ -235,3 +235,45 @@ def test_floor_table_follows_the_floors():
     say("graph replay after the B inversion: P, U, Bf bitwise",
         [torch.equal(x, y) for x, y in zip(sa, sb)])
     assert all(torch.equal(x, y) for x, y in zip(sa, sb))
+
+
+def test_floor_table_in_a_graph_the_caller_captures():
+    """A step captured by the caller (here with torch's graph capture on the
+    pack's stream) records the floor-table rewrite, so a replay after an
+    inversion with other floors still inverts with the captured ones: the
+    replays equal eager steps bitwise."""
+    import torch
+    from paper_2410_09146_amd import grmhd as G
+    prob = I.torus(n=(32, 32, 16))
+    a, b = G.Pack(prob), G.Pack(prob)
+    for p in (a, b):
+        p.init()
+        p.reductions(sync=False)
+    r0, u0 = a.eos.rho_flr0, a.eos.u_flr0
+
+    def state(p):
+        p._out()
+        torch.cuda.synchronize()
+        return [getattr(p, w).clone() for w in ("P", "U", "Bf")]
+
+    # capture one step of a (capturing runs nothing), then replay it
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=a.stream):
+        a.step_c(None, cfl=prob.cfl)
+    for rep in range(2):
+        g.replay()
+        b.step_c(None, cfl=prob.cfl)
+        assert all(torch.equal(x, y) for x, y in zip(state(a), state(b))), rep
+        # an inversion with ten times the floors between the replays
+        for p in (a, b):
+            p.eos.rho_flr0, p.eos.u_flr0 = 10.0 * r0, 10.0 * u0
+            p.con2prim()
+            p.eos.rho_flr0, p.eos.u_flr0 = r0, u0
+            p.reductions(sync=False)
+        assert all(torch.equal(x, y) for x, y in zip(state(a), state(b)))
+    g.replay()
+    b.step_c(None, cfl=prob.cfl)
+    same = [torch.equal(x, y) for x, y in zip(state(a), state(b))]
+    say("caller-captured step after inversions with other floors: P, U, Bf bitwise", same)
+    assert all(same)
