@@ -906,6 +906,22 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
   const double *F0 = a.F, *F1 = a.F + 8 * n, *F2 = a.F + 16 * n;
   const bool in1 = i < ng + b.n[0], in2 = j < ng + b.n[1], in3 = k < ng + b.n[2];
 
+  // Kerr-Schild sources first, then a scheduling barrier: without it the
+  // compiler hoists the 30 flux loads above the source arithmetic and holds
+  // both (134 VGPRs, 3 waves per SIMD); apart it needs 92 (5 waves).  The
+  // sources are added at the same point as before, so the sums are unchanged.
+  double S[5 + NSC] = {};
+  if constexpr (MK == MK_KS) {
+    if (HYDRO && in1 && in2 && in3) {
+      Prim q;
+      q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
+      q.ie = a.P[4 * n + c];
+      q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
+      q.ye = NSC ? a.P[5 * n + c] : 0.0;
+      add_sources<MK, NSC>(a, b, i, j, q, S);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
   if (HYDRO && in1 && in2 && in3) {
     double rhs[5 + NSC];
 #pragma unroll
@@ -916,12 +932,9 @@ __global__ __launch_bounds__(256) void k_update(KArgs a, const int2 *__restrict_
       rhs[5] = -(F0[5 * n + c + 1] - F0[5 * n + c]) * i1 -
                (F1[6 * n + c + sj] - F1[6 * n + c]) * i2 - (F2[7 * n + c + sk] - F2[7 * n + c]) * i3;
     if constexpr (MK == MK_KS) {
-      Prim q;
-      q.rho = a.P[c]; q.u1 = a.P[n + c]; q.u2 = a.P[2 * n + c]; q.u3 = a.P[3 * n + c];
-      q.ie = a.P[4 * n + c];
-      q.B1 = a.Bcc[c]; q.B2 = a.Bcc[n + c]; q.B3 = a.Bcc[2 * n + c];
-      q.ye = NSC ? a.P[5 * n + c] : 0.0;
-      add_sources<MK, NSC>(a, b, i, j, q, rhs);
+      rhs[1] += S[1];
+      rhs[2] += S[2];
+      rhs[4] += S[4];
     }
     rk_cell<5 + NSC>(a, c, c0, c1, h, mode, rhs);
   }
