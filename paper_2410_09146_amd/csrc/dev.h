@@ -432,6 +432,11 @@ __device__ __forceinline__ void riemann_parts(const GeoT<T> &G, const PrimT<T> &
     else lpL = speed_absmax<DIR>(G, X), lmL = T(0);
     if constexpr (NSC != 0) { UL[8] = UL[0] * L.ye; FL[8] = FL[0] * L.ye; }
   }
+#ifndef GRMHD_OPCOUNT
+  // the right state after the left: interleaved by the scheduler, the two
+  // states' temporaries pushed the x2 tiles past 128 VGPRs (2 spilled)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
   {
     const AuxT<T> X = aux_th(G, R, pR, gpR);
     cons_of(G, R, X, UR);
